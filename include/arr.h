@@ -1,0 +1,226 @@
+/*
+ * arr.h -- C ABI of the MI355X (gfx950) ARRABIT block eigensolver.
+ *
+ * Computes the k algebraically largest or smallest eigenpairs of a sparse
+ * symmetric matrix A with the block algorithm of Wen & Zhang, "Block
+ * algorithms with augmented Rayleigh-Ritz projections for large-scale eigenpair
+ * computation" (arXiv 1507.06078): a multi-power subspace update with a
+ * Chebyshev-interpolant polynomial accelerator (Sec. 5, Algorithm 7) followed by
+ * augmented Rayleigh-Ritz projections (Algorithm 5), driven by the detailed
+ * ARRABIT iteration (Algorithm 8) with the heuristics of Sec. 6.
+ *
+ * Every step runs in hand-written HIP kernels on the GPU; the host only keeps
+ * scalars (interval ends, tolerances, degree, block counts) and makes the
+ * decisions of Sec. 6.
+ *
+ * Conventions shared by all entry points
+ *  - Return codes: ARR_OK (0) on success; ARR_NOT_CONVERGED / ARR_STAGNATED
+ *    (> 0) mean a solve ended by stop rule (i) / (ii) of Sec. 6 and the best
+ *    pairs are still retrievable; negative values are errors, with a message
+ *    available from arr_last_error (handle API) or arr_last_global_error.
+ *  - Dense blocks are ROW-MAJOR: element (i, j) of an n x w block with leading
+ *    dimension ld (>= w) is at p[i*ld + j].
+ *  - CSR matrices are 0-based with int64 row pointers and int32 column
+ *    indices; both triangles are stored (A must be symmetric), duplicates are
+ *    not allowed.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory on the handle's (or the current) device.
+ *  - A handle is not thread-safe; distinct handles may be used from distinct
+ *    threads.
+ */
+#ifndef ARR_H_
+#define ARR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define ARR_OK 0
+#define ARR_NOT_CONVERGED 1 /* stop rule (i): maxit outer iterations reached   */
+#define ARR_STAGNATED 2     /* stop rule (ii): maxres not reduced 3 times     */
+#define ARR_EINVAL (-1)     /* invalid argument (message says which)          */
+#define ARR_ENOMEM (-2)     /* device memory could not be allocated           */
+#define ARR_EDEVICE (-3)    /* a HIP call failed                              */
+#define ARR_ESTATE (-4)     /* call out of order (e.g. results before solve)  */
+#define ARR_EBREAKDOWN (-5) /* numerical breakdown that no fallback resolved  */
+
+typedef enum { ARR_LARGEST_ALGEBRAIC = 0, ARR_SMALLEST_ALGEBRAIC = 1 } arr_which_t;
+
+/* Arithmetic of the block iteration. ARR_FP64: every block in FP64.
+ * ARR_MIXED: filter SpMMs and blocks in FP32 (FP64 small dense work and
+ * FP64 Gram accumulation), then FP64 closing iterations down to tol. */
+typedef enum { ARR_FP64 = 0, ARR_MIXED = 1 } arr_precision_t;
+
+/* Host CSR description (arr_create deep-copies it to the device). */
+typedef struct {
+  int64_t n;             /* order of A                                   */
+  int64_t nnz;           /* stored entries, = rowptr[n]                  */
+  const int64_t *rowptr; /* host, [n+1], rowptr[0] = 0, non-decreasing   */
+  const int32_t *colind; /* host, [nnz], in [0, n)                       */
+  const double *val;     /* host, [nnz]                                  */
+} arr_csr_t;
+
+/* Device CSR description used by the step-level entry points. val is a
+ * device array of FP64 (dtype 0) or FP32 (dtype 1) values. */
+typedef struct {
+  int64_t n, nnz;
+  const int64_t *rowptr; /* device [n+1] */
+  const int32_t *colind; /* device [nnz] */
+  const void *val;       /* device [nnz] */
+  int32_t dtype;         /* 0 = FP64, 1 = FP32 */
+} arr_dev_csr_t;
+
+/* Parameters of Algorithm 8; arr_options_default fills the defaults of
+ * Sec. 6. */
+typedef struct {
+  int32_t w;             /* block width k+q; 0 -> k + round(0.1 k) (Sec. 6, guard vectors) */
+  int32_t p0, p_max;     /* augmentation blocks: initial 1, max 3 (eq. block)              */
+  int32_t d0, d_max;     /* polynomial degree: initial 3, max 15 (eq. degree)              */
+  int32_t maxit;         /* outer iterations, 30 (stop rule (i))                           */
+  int32_t maxit1;        /* inner stop checks, 10                                          */
+  int32_t maxit2;        /* inner iterations between checks, 5                             */
+  double tol1;           /* first continuation tolerance; 0 -> 1e-6 if tol <= 1e-8 else tol */
+  int32_t precision;     /* arr_precision_t                                                */
+  int32_t paper_faithful;/* 1: also stop by rule (iii) of Sec. 6                            */
+  int32_t lanczos_steps; /* Lanczos steps for the lower interval end, 100                  */
+  int32_t device;        /* HIP device ordinal, default 0                                  */
+  uint64_t seed;         /* seed of the device Gaussian starting block                     */
+  double mixed_switch;   /* ARR_MIXED: leave FP32 once maxres <= this (default 1e-5)       */
+  int32_t verbose;       /* 1: one line per outer iteration on stderr                      */
+} arr_options_t;
+
+/* Counters and timings of the last solve. */
+typedef struct {
+  int32_t status;        /* return code of arr_solve */
+  int32_t outer_iters;
+  int32_t arr_calls;
+  int32_t poly_calls;
+  int32_t final_p, final_d;
+  int32_t n_locked;      /* converged pairs held in Q_c at the end */
+  int32_t fp32_outer;    /* outer iterations done in FP32 (ARR_MIXED) */
+  int64_t spmm_degrees;  /* block SpMM filter degrees                 */
+  int64_t spmm_cols;     /* sum over filter degrees of block widths   */
+  double a, b;           /* final interval ends (working operator)    */
+  double norm_est;       /* |A|_2 estimate (Lanczos Ritz values)       */
+  double maxres;         /* final max residual, eq. resi scaling       */
+  double t_total;        /* seconds inside arr_solve                    */
+  double t_setup;        /* interval estimation                         */
+  double t_filter;       /* subspace update (filter, normalize, project, rcond) */
+  double t_arr;          /* augmentation + RR + residuals               */
+  double t_dense;        /* small dense work inside t_arr (Cholesky, eigensolve) */
+} arr_stats_t;
+
+typedef struct arr_solver *arr_handle_t;
+
+/* Fill *o with the defaults of Sec. 6 and Algorithm 8. */
+void arr_options_default(arr_options_t *o);
+
+/* Problem setup: the k extreme eigenpairs of A with residual tolerance tol
+ * (eq. out-stop, eq. resi). Copies the CSR to the device, validates it
+ * (bounds, 0 < k <= w, (p_max+1) w < n as required by Algorithm 8, tol > 0) and
+ * allocates every device block of the solve (about (p_max+3) n w values plus
+ * the CSR). The caller keeps ownership of csr's arrays and may free them on
+ * return. n must equal csr->n. On success *out is a new handle that the
+ * caller releases with arr_destroy. */
+int arr_create(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,
+               arr_handle_t *out);
+int arr_create_ex(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,
+                  const arr_options_t *opts, arr_handle_t *out);
+
+/* Optional: use X0 (host, n x w row-major with leading dimension ld >= w,
+ * FP64) as the starting block instead of the device Gaussian draw (Algorithm 8
+ * initializes X as an i.i.d. Gaussian matrix; its first column also starts
+ * the Lanczos estimate of the lower interval end). Copied; must be called
+ * before arr_solve. */
+int arr_set_initial_block(arr_handle_t h, const double *X0, int64_t ld);
+
+/* Run Algorithm 8 to completion on the handle's stream (blocking). Returns
+ * ARR_OK, ARR_NOT_CONVERGED, ARR_STAGNATED or an error code. */
+int arr_solve(arr_handle_t h);
+
+/* Copy results to caller-owned host buffers (any pointer may be NULL):
+ * evals [k] (descending for LARGEST, ascending for SMALLEST), evecs n x k
+ * row-major with leading dimension ldv >= k (unit columns, sign chosen so the
+ * entry of largest magnitude is positive), resid [k] = ||A x - lambda x||_2 /
+ * max(1, |lambda|) (eq. resi). */
+int arr_get_eigpairs(arr_handle_t h, double *evals, double *evecs, int64_t ldv, double *resid);
+
+int arr_get_stats(arr_handle_t h, arr_stats_t *s);
+const char *arr_last_error(arr_handle_t h);
+const char *arr_last_global_error(void);
+void arr_destroy(arr_handle_t h);
+
+/* ---- step-level entry points (device pointers, for composing and testing
+ * the steps of Algorithm 8). All run on `stream` (a hipStream_t, NULL for
+ * the default stream) and return after the work is enqueued unless stated. */
+
+/* One fused filter degree (the body of the loop of Algorithm 7):
+ *   Yout = alpha * A * Yin + beta * Yin + gamma * Z
+ * on w columns. Yin, Z, Yout are device blocks of A's dtype (n x w, row-major,
+ * leading dimensions ldy, ldz, ldo). Z may equal Yin or be NULL (gamma
+ * ignored). Yout must not overlap Yin; it may equal Z. If colsumsq (device,
+ * FP64 [w]) is non-NULL it receives the squared 2-norms of Yout's columns.
+ * Synchronous when colsumsq is non-NULL. */
+int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t ldy, const void *Z,
+                    int64_t ldz, void *Yout, int64_t ldo, double alpha, double beta, double gamma,
+                    double *colsumsq, void *stream);
+
+/* Algorithm 7 on the shifted operator, as called by Algorithm 8:
+ * X <- poly(A - shift I, X, lo, hi, Gamma_d), with Gamma_d (host, d+1 values,
+ * leading coefficient first). X is a device block n x w (ld), overwritten.
+ * Temporary device memory is allocated internally. Synchronous. */
+int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo,
+             double hi, const double *gamma, int32_t d, void *stream);
+
+/* Chebyshev-interpolant coefficients Gamma_d of Sec. 5 (eq. chebfun-f),
+ * computed by the library: out[0..d] leading first. 1 <= d <= 32. */
+int arr_filter_coefficients(int32_t d, double *out);
+
+/* Gram product G = X^T Y (FP64 result, device, mx x my row-major, ld my) of
+ * device blocks X (n x mx, ldx) and Y (n x my, ldy) of dtype (0 FP64, 1 FP32),
+ * accumulated in FP64 with a deterministic split reduction. Synchronous. */
+int arr_gram(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, const void *Y,
+             int64_t ldy, int32_t my, double *G, void *stream);
+
+/* Block update Y = beta * Y + alpha * X W with X device n x m (ldx, dtype),
+ * W device FP64 m x c row-major (ldw), Y device n x c (ldy, dtype). */
+int arr_block_update(int32_t dtype, int64_t n, int32_t m, int32_t c, double alpha, const void *X,
+                     int64_t ldx, const double *W, int64_t ldw, double beta, void *Y, int64_t ldy,
+                     void *stream);
+
+/* rcond(X^T X) (eq. inn-stop): 1/(||G||_1 ||G^-1||_1) for G = X^T X, or 0 if
+ * G is not numerically positive definite. X device n x w (ld, dtype).
+ * Synchronous; result in *rc (host). */
+int arr_rcond_gram(int32_t dtype, int64_t n, int32_t w, const void *X, int64_t ld, double *rc,
+                   void *stream);
+
+/* Orthonormalize the columns of the FP64 device block Z (n x m, ld) in place
+ * by Cholesky QR with a shifted first pass when needed (the orth(Z) step of
+ * Algorithm 1). Synchronous. */
+int arr_orthonormalize(int64_t n, int32_t m, double *Z, int64_t ld, void *stream);
+
+/* Symmetric eigendecomposition of a small FP64 matrix H (device, m x m
+ * row-major, read only; its symmetric part is used): evals (device [m]) in
+ * descending order and unit eigenvectors as the COLUMNS of V (device, m x m
+ * row-major): H = V diag(evals) V^T. Parallel cyclic Jacobi (the eigensolve of
+ * Algorithm 1). Synchronous. */
+int arr_syev(int32_t m, double *H, double *evals, double *V, void *stream);
+
+/* One augmented Rayleigh-Ritz projection (Algorithm 5 with the deflation
+ * projection of Sec. 6) on the FP64 device block X (n x w, ld): builds
+ * [X, AX, ..., A^p X], projects out Qc (device n x nc, ldq; nc may be 0),
+ * orthonormalizes, projects A, and writes the w leading Ritz values (host,
+ * descending) to ritz_vals and the Ritz vectors to Y (device n x w, ldy).
+ * Temporary device memory is allocated internally. Synchronous. */
+int arr_augmented_rr(const arr_dev_csr_t *A, int64_t w, const double *X, int64_t ld, int32_t p,
+                     const double *Qc, int64_t ldq, int32_t nc, double *Y, int64_t ldy,
+                     double *ritz_vals, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARR_H_ */

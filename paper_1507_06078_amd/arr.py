@@ -1,0 +1,279 @@
+"""Thin ctypes binding of libarr.so (include/arr.h). Argument marshalling only:
+every step of the solver runs in the HIP library. Device buffers for the
+step-level calls are torch tensors on a ROCm device (torch is used for device
+memory and streams only).
+
+Loading fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libarr.so")
+
+ARR_OK = 0
+ARR_NOT_CONVERGED = 1
+ARR_STAGNATED = 2
+ARR_EINVAL = -1
+ARR_ENOMEM = -2
+ARR_EDEVICE = -3
+ARR_ESTATE = -4
+ARR_EBREAKDOWN = -5
+LARGEST = 0
+SMALLEST = 1
+FP64 = 0
+MIXED = 1
+
+
+class ArrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"arr error {code}: {msg}")
+        self.code = code
+
+
+class arr_csr_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class arr_dev_csr_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+
+
+class arr_options_t(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("p0", ctypes.c_int32), ("p_max", ctypes.c_int32),
+                ("d0", ctypes.c_int32), ("d_max", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("maxit1", ctypes.c_int32), ("maxit2", ctypes.c_int32), ("tol1", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("paper_faithful", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("device", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("mixed_switch", ctypes.c_double), ("verbose", ctypes.c_int32)]
+
+
+class arr_stats_t(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("arr_calls", ctypes.c_int32),
+                ("poly_calls", ctypes.c_int32), ("final_p", ctypes.c_int32), ("final_d", ctypes.c_int32),
+                ("n_locked", ctypes.c_int32), ("fp32_outer", ctypes.c_int32),
+                ("spmm_degrees", ctypes.c_int64), ("spmm_cols", ctypes.c_int64),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("norm_est", ctypes.c_double),
+                ("maxres", ctypes.c_double), ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double),
+                ("t_filter", ctypes.c_double), ("t_arr", ctypes.c_double), ("t_dense", ctypes.c_double)]
+
+
+EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
+           "arr_get_eigpairs", "arr_get_stats", "arr_last_error", "arr_last_global_error", "arr_destroy",
+           "arr_filter_step", "arr_poly", "arr_filter_coefficients", "arr_gram", "arr_block_update",
+           "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libarr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1507_06078_amd/build.py "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.arr_options_default.argtypes = [P(arr_options_t)]
+    L.arr_options_default.restype = None
+    L.arr_create.argtypes = [P(arr_csr_t), i64, i32, i32, f64, P(vp)]
+    L.arr_create_ex.argtypes = [P(arr_csr_t), i64, i32, i32, f64, P(arr_options_t), P(vp)]
+    L.arr_set_initial_block.argtypes = [vp, vp, i64]
+    L.arr_solve.argtypes = [vp]
+    L.arr_get_eigpairs.argtypes = [vp, vp, vp, i64, vp]
+    L.arr_get_stats.argtypes = [vp, P(arr_stats_t)]
+    L.arr_last_error.argtypes = [vp]
+    L.arr_last_error.restype = ctypes.c_char_p
+    L.arr_last_global_error.argtypes = []
+    L.arr_last_global_error.restype = ctypes.c_char_p
+    L.arr_destroy.argtypes = [vp]
+    L.arr_destroy.restype = None
+    L.arr_filter_step.argtypes = [P(arr_dev_csr_t), i64, vp, i64, vp, i64, vp, i64, f64, f64, f64, vp, vp]
+    L.arr_poly.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, vp, i32, vp]
+    L.arr_filter_coefficients.argtypes = [i32, vp]
+    L.arr_gram.argtypes = [i32, i64, vp, i64, i32, vp, i64, i32, vp, vp]
+    L.arr_block_update.argtypes = [i32, i64, i32, i32, f64, vp, i64, vp, i64, f64, vp, i64, vp]
+    L.arr_rcond_gram.argtypes = [i32, i64, i32, vp, i64, vp, vp]
+    L.arr_orthonormalize.argtypes = [i64, i32, vp, i64, vp]
+    L.arr_syev.argtypes = [i32, vp, vp, vp, vp]
+    L.arr_augmented_rr.argtypes = [P(arr_dev_csr_t), i64, vp, i64, i32, vp, i64, i32, vp, i64, vp, vp]
+    for name in EXPORTS:
+        if name not in ("arr_options_default", "arr_destroy", "arr_last_error", "arr_last_global_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int, handle=None) -> int:
+    if code < 0:
+        L = lib()
+        msg = (L.arr_last_error(handle) if handle else L.arr_last_global_error()) or b""
+        raise ArrError(code, msg.decode(errors="replace"))
+    return code
+
+
+# ---- whole-solve API -------------------------------------------------------
+
+def arr_options_default() -> arr_options_t:
+    o = arr_options_t()
+    lib().arr_options_default(ctypes.byref(o))
+    return o
+
+
+class Handle:
+    """Owns an arr_handle_t; keeps the host CSR arrays alive only during create."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().arr_destroy(self.ptr)
+            self.ptr = None
+
+
+def _host_csr(csr) -> tuple[arr_csr_t, tuple]:
+    rowptr = np.ascontiguousarray(csr.rowptr, dtype=np.int64)
+    colind = np.ascontiguousarray(csr.colind, dtype=np.int32)
+    val = np.ascontiguousarray(csr.val, dtype=np.float64)
+    c = arr_csr_t(int(csr.n), int(rowptr[-1]), rowptr.ctypes.data, colind.ctypes.data, val.ctypes.data)
+    return c, (rowptr, colind, val)
+
+
+def arr_create(csr, n: int, k: int, which: int, tol: float, opts: arr_options_t | None = None) -> Handle:
+    c, keep = _host_csr(csr)
+    h = ctypes.c_void_p()
+    if opts is None:
+        code = lib().arr_create(ctypes.byref(c), int(n), int(k), int(which), float(tol), ctypes.byref(h))
+    else:
+        code = lib().arr_create_ex(ctypes.byref(c), int(n), int(k), int(which), float(tol), ctypes.byref(opts),
+                                   ctypes.byref(h))
+    _check(code)
+    del keep
+    return Handle(h.value)
+
+
+def arr_set_initial_block(h: Handle, X0: np.ndarray) -> None:
+    X0 = np.ascontiguousarray(X0, dtype=np.float64)
+    _check(lib().arr_set_initial_block(h.ptr, X0.ctypes.data, X0.shape[1]), h.ptr)
+
+
+def arr_solve(h: Handle) -> int:
+    return _check(lib().arr_solve(h.ptr), h.ptr)
+
+
+def arr_get_eigpairs(h: Handle, k: int, n: int, vectors: bool = True):
+    ev = np.zeros(k)
+    res = np.zeros(k)
+    X = np.zeros((n, k)) if vectors else None
+    _check(lib().arr_get_eigpairs(h.ptr, ev.ctypes.data, X.ctypes.data if vectors else None, k, res.ctypes.data),
+           h.ptr)
+    return ev, X, res
+
+
+def arr_get_stats(h: Handle) -> dict:
+    s = arr_stats_t()
+    _check(lib().arr_get_stats(h.ptr, ctypes.byref(s)), h.ptr)
+    return {name: getattr(s, name) for name, _ in arr_stats_t._fields_}
+
+
+def arr_filter_coefficients(d: int) -> np.ndarray:
+    out = np.zeros(d + 1)
+    _check(lib().arr_filter_coefficients(int(d), out.ctypes.data))
+    return out
+
+
+# ---- step-level API on device tensors ---------------------------------------
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _ld(t):
+    return 0 if t is None else int(t.stride(0))
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return 0
+    if t.dtype == torch.float32:
+        return 1
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class DeviceCSR:
+    """A CSR matrix resident on the device (torch tensors) plus its descriptor."""
+
+    def __init__(self, csr, dtype=None, device="cuda"):
+        import torch
+        dtype = dtype or torch.float64
+        self.n = int(csr.n)
+        self.rowptr = torch.as_tensor(np.asarray(csr.rowptr, dtype=np.int64)).to(device)
+        self.colind = torch.as_tensor(np.asarray(csr.colind, dtype=np.int32)).to(device)
+        self.val = torch.as_tensor(np.asarray(csr.val, dtype=np.float64)).to(device=device, dtype=dtype)
+        self.desc = arr_dev_csr_t(self.n, int(self.colind.numel()), self.rowptr.data_ptr(),
+                                  self.colind.data_ptr(), self.val.data_ptr(), _dtype_code(self.val))
+
+
+def arr_filter_step(A: DeviceCSR, Yin, Z, Yout, alpha: float, beta: float, gamma: float, colsumsq=None):
+    w = int(Yout.shape[1])
+    _check(lib().arr_filter_step(ctypes.byref(A.desc), w, _ptr(Yin), _ld(Yin), _ptr(Z), _ld(Z), _ptr(Yout),
+                                 _ld(Yout), float(alpha), float(beta), float(gamma), _ptr(colsumsq), _stream()))
+
+
+def arr_poly(A: DeviceCSR, X, shift: float, lo: float, hi: float, gamma: np.ndarray):
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    _check(lib().arr_poly(ctypes.byref(A.desc), int(X.shape[1]), _ptr(X), _ld(X), float(shift), float(lo),
+                          float(hi), g.ctypes.data, len(g) - 1, _stream()))
+
+
+def arr_gram(X, Y, G):
+    _check(lib().arr_gram(_dtype_code(X), int(X.shape[0]), _ptr(X), _ld(X), int(X.shape[1]), _ptr(Y), _ld(Y),
+                          int(Y.shape[1]), _ptr(G), _stream()))
+
+
+def arr_block_update(X, W, Y, alpha: float = 1.0, beta: float = 0.0):
+    _check(lib().arr_block_update(_dtype_code(X), int(X.shape[0]), int(X.shape[1]), int(Y.shape[1]), float(alpha),
+                                  _ptr(X), _ld(X), _ptr(W), _ld(W), float(beta), _ptr(Y), _ld(Y), _stream()))
+
+
+def arr_rcond_gram(X) -> float:
+    rc = ctypes.c_double()
+    _check(lib().arr_rcond_gram(_dtype_code(X), int(X.shape[0]), int(X.shape[1]), _ptr(X), _ld(X),
+                                ctypes.addressof(rc), _stream()))
+    return rc.value
+
+
+def arr_orthonormalize(Z):
+    _check(lib().arr_orthonormalize(int(Z.shape[0]), int(Z.shape[1]), _ptr(Z), _ld(Z), _stream()))
+
+
+def arr_syev(H, evals, V):
+    _check(lib().arr_syev(int(H.shape[0]), _ptr(H), _ptr(evals), _ptr(V), _stream()))
+
+
+def arr_augmented_rr(A: DeviceCSR, X, p: int, Qc, Y) -> np.ndarray:
+    w = int(X.shape[1])
+    vals = np.zeros(w)
+    nc = 0 if Qc is None else int(Qc.shape[1])
+    _check(lib().arr_augmented_rr(ctypes.byref(A.desc), w, _ptr(X), _ld(X), int(p), _ptr(Qc), _ld(Qc), nc,
+                                  _ptr(Y), _ld(Y), vals.ctypes.data, _stream()))
+    return vals

@@ -1,0 +1,305 @@
+// extern "C" entry points declared in include/arr.h. Each one converts
+// exceptions into return codes and keeps the message for arr_last_error /
+// arr_last_global_error.
+#include <cstring>
+#include <memory>
+
+#include "solver.h"
+
+struct arr_solver {
+  std::unique_ptr<arr::Solver> s;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F>
+int guarded(std::string *err, F &&f) {
+  try {
+    return f();
+  } catch (const arr::Error &e) {
+    g_err = e.what();
+    if (err) *err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    if (err) *err = g_err;
+    return ARR_ENOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    if (err) *err = e.what();
+    return ARR_EDEVICE;
+  }
+}
+
+template <typename T>
+arr::DevCSR<T> dev_csr(const arr_dev_csr_t *A) {
+  ARR_REQUIRE(A && A->rowptr && A->n > 0, "device CSR is NULL or empty");
+  return arr::DevCSR<T>{A->n, A->nnz, A->rowptr, A->colind, static_cast<const T *>(A->val)};
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+void arr_options_default(arr_options_t *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->w = 0;
+  o->p0 = 1;
+  o->p_max = 3;
+  o->d0 = 3;
+  o->d_max = 15;
+  o->maxit = 30;
+  o->maxit1 = 10;
+  o->maxit2 = 5;
+  o->tol1 = 0.0;
+  o->precision = ARR_FP64;
+  o->paper_faithful = 0;
+  o->lanczos_steps = 100;
+  o->device = 0;
+  o->seed = 2;
+  o->mixed_switch = 1e-5;
+}
+
+int arr_create_ex(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,
+                  const arr_options_t *opts, arr_handle_t *out) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    arr_options_t o;
+    if (opts)
+      o = *opts;
+    else
+      arr_options_default(&o);
+    auto h = std::make_unique<arr_solver>();
+    h->s = std::make_unique<arr::Solver>(csr, n, k, (int)which, tol, o);
+    *out = h.release();
+    return ARR_OK;
+  });
+}
+
+int arr_create(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol, arr_handle_t *out) {
+  return arr_create_ex(csr, n, k, which, tol, nullptr, out);
+}
+
+int arr_set_initial_block(arr_handle_t h, const double *X0, int64_t ld) {
+  if (!h) return ARR_EINVAL;
+  return guarded(&h->err, [&]() {
+    h->s->set_initial_block(X0, ld);
+    return ARR_OK;
+  });
+}
+
+int arr_solve(arr_handle_t h) {
+  if (!h) return ARR_EINVAL;
+  return guarded(&h->err, [&]() { return h->s->solve(); });
+}
+
+int arr_get_eigpairs(arr_handle_t h, double *evals, double *evecs, int64_t ldv, double *resid) {
+  if (!h) return ARR_EINVAL;
+  if (!h->s->solved) {
+    h->err = "arr_get_eigpairs called before arr_solve";
+    return ARR_ESTATE;
+  }
+  return guarded(&h->err, [&]() {
+    h->s->get(evals, evecs, ldv, resid);
+    return ARR_OK;
+  });
+}
+
+int arr_get_stats(arr_handle_t h, arr_stats_t *s) {
+  if (!h || !s) return ARR_EINVAL;
+  *s = h->s->stats;
+  return ARR_OK;
+}
+
+const char *arr_last_error(arr_handle_t h) { return h ? h->err.c_str() : g_err.c_str(); }
+const char *arr_last_global_error(void) { return g_err.c_str(); }
+
+void arr_destroy(arr_handle_t h) { delete h; }
+
+// ---- step-level entry points ----------------------------------------------
+
+int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t ldy, const void *Z, int64_t ldz,
+                    void *Yout, int64_t ldo, double alpha, double beta, double gamma, double *colsumsq,
+                    void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(A && w >= 0 && ldy >= w && ldo >= w && (!Z || ldz >= w), "filter_step: bad sizes");
+    ARR_REQUIRE(Yin && Yout && Yin != Yout, "filter_step: Yin/Yout NULL or aliased");
+    hipStream_t s = as_stream(stream);
+    arr::DevBuf part;
+    double *pp = nullptr;
+    if (colsumsq) {
+      part.alloc(sizeof(double) * arr::spmm_groups(A->n) * std::max<int64_t>(1, w));
+      pp = part.as<double>();
+    }
+    int groups;
+    if (A->dtype == 0) {
+      auto M = dev_csr<double>(A);
+      groups = arr::launch_filter_spmm<double>(M, arr::Blk<const double>{(const double *)Yin, ldy, (int)w},
+                                               arr::Blk<const double>{(const double *)Z, ldz, Z ? (int)w : 0},
+                                               arr::Blk<double>{(double *)Yout, ldo, (int)w}, alpha, beta, gamma, pp, s);
+    } else {
+      ARR_REQUIRE(A->dtype == 1, "dtype must be 0 (FP64) or 1 (FP32)");
+      auto M = dev_csr<float>(A);
+      groups = arr::launch_filter_spmm<float>(M, arr::Blk<const float>{(const float *)Yin, ldy, (int)w},
+                                              arr::Blk<const float>{(const float *)Z, ldz, Z ? (int)w : 0},
+                                              arr::Blk<float>{(float *)Yout, ldo, (int)w}, alpha, beta, gamma, pp, s);
+    }
+    if (colsumsq) {
+      arr::launch_reduce_groups(pp, groups, (int)w, colsumsq, false, s);
+      ARR_HIP(hipStreamSynchronize(s));
+    }
+    return ARR_OK;
+  });
+}
+
+int arr_filter_coefficients(int32_t d, double *out) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(out && d >= 1 && d <= 32, "filter_coefficients: need 1 <= d <= 32");
+    const std::vector<double> g = arr::filter_coefficients(d);
+    std::copy(g.begin(), g.end(), out);
+    return ARR_OK;
+  });
+}
+
+int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo, double hi,
+             const double *gamma, int32_t d, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(A && X && gamma && d >= 1 && w >= 0 && ld >= w, "poly: bad arguments");
+    hipStream_t s = as_stream(stream);
+    std::vector<double> g(gamma, gamma + d + 1);
+    arr::Work wk;
+    wk.ensure_cols(A->n, (int)w);
+    const int64_t n = A->n;
+    if (A->dtype == 0) {
+      arr::DevBuf tmp(sizeof(double) * n * 2 * std::max<int64_t>(1, w));
+      double *t = tmp.as<double>();
+      arr::poly_apply<double>(dev_csr<double>(A), arr::Blk<double>{(double *)X, ld, (int)w},
+                              arr::Blk<double>{t, 2 * w, (int)w}, arr::Blk<double>{t + w, 2 * w, (int)w}, shift, lo,
+                              hi, g, wk, false, s);
+    } else {
+      arr::DevBuf tmp(sizeof(float) * n * 2 * std::max<int64_t>(1, w));
+      float *t = tmp.as<float>();
+      arr::poly_apply<float>(dev_csr<float>(A), arr::Blk<float>{(float *)X, ld, (int)w},
+                             arr::Blk<float>{t, 2 * w, (int)w}, arr::Blk<float>{t + w, 2 * w, (int)w}, shift, lo, hi,
+                             g, wk, false, s);
+    }
+    ARR_HIP(hipStreamSynchronize(s));
+    return ARR_OK;
+  });
+}
+
+int arr_gram(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, const void *Y, int64_t ldy, int32_t my,
+             double *G, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(X && Y && G && mx >= 0 && my >= 0 && ldx >= mx && ldy >= my && n >= 0, "gram: bad arguments");
+    hipStream_t s = as_stream(stream);
+    arr::DevBuf work(sizeof(double) * std::max<size_t>(1, arr::gram_work_doubles(n, mx, my)));
+    const bool sym = (X == Y && ldx == ldy && mx == my);
+    if (dtype == 0)
+      arr::launch_gram<double>(n, arr::Blk<const double>{(const double *)X, ldx, mx},
+                               arr::Blk<const double>{(const double *)Y, ldy, my}, G, work.as<double>(), sym, s);
+    else
+      arr::launch_gram<float>(n, arr::Blk<const float>{(const float *)X, ldx, mx},
+                              arr::Blk<const float>{(const float *)Y, ldy, my}, G, work.as<double>(), sym, s);
+    ARR_HIP(hipStreamSynchronize(s));
+    return ARR_OK;
+  });
+}
+
+int arr_block_update(int32_t dtype, int64_t n, int32_t m, int32_t c, double alpha, const void *X, int64_t ldx,
+                     const double *W, int64_t ldw, double beta, void *Y, int64_t ldy, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(X && W && Y && X != Y && m >= 0 && c >= 0 && ldx >= m && ldw >= c && ldy >= c, "block_update: bad arguments");
+    hipStream_t s = as_stream(stream);
+    if (dtype == 0)
+      arr::launch_update<double>(n, arr::Blk<const double>{(const double *)X, ldx, m}, W, ldw, c, alpha, beta,
+                                 arr::Blk<double>{(double *)Y, ldy, c}, s);
+    else
+      arr::launch_update<float>(n, arr::Blk<const float>{(const float *)X, ldx, m}, W, ldw, c, alpha, beta,
+                                arr::Blk<float>{(float *)Y, ldy, c}, s);
+    return ARR_OK;
+  });
+}
+
+int arr_rcond_gram(int32_t dtype, int64_t n, int32_t w, const void *X, int64_t ld, double *rc, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(X && rc && w > 0 && ld >= w, "rcond_gram: bad arguments");
+    arr::Work wk;
+    hipStream_t s = as_stream(stream);
+    if (dtype == 0)
+      *rc = arr::rcond_gram<double>(n, arr::Blk<const double>{(const double *)X, ld, w}, wk, s);
+    else
+      *rc = arr::rcond_gram<float>(n, arr::Blk<const float>{(const float *)X, ld, w}, wk, s);
+    return ARR_OK;
+  });
+}
+
+int arr_orthonormalize(int64_t n, int32_t m, double *Z, int64_t ld, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(Z && m > 0 && ld >= m && n >= m, "orthonormalize: bad arguments");
+    hipStream_t s = as_stream(stream);
+    arr::Work wk;
+    arr::DevBuf alt(sizeof(double) * n * m);
+    const arr::Blk<const double> none{nullptr, 0, 0};
+    arr::Blk<double> U = arr::orthonormalize<double>(n, arr::Blk<double>{Z, ld, m}, arr::Blk<double>{alt.as<double>(), m, m},
+                                                     none, wk, s, nullptr);
+    if (U.p != Z) arr::launch_copy<double>(n, m, Z, ld, U.p, U.ld, s);
+    ARR_HIP(hipStreamSynchronize(s));
+    return ARR_OK;
+  });
+}
+
+int arr_syev(int32_t m, double *H, double *evals, double *V, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(H && evals && V && m > 0, "syev: bad arguments");
+    hipStream_t s = as_stream(stream);
+    arr::Jacobi jac;
+    std::vector<double> ev;
+    jac.solve(m, H, V, ev, s);
+    ARR_HIP(hipMemcpyAsync(evals, ev.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
+    ARR_HIP(hipStreamSynchronize(s));
+    return ARR_OK;
+  });
+}
+
+int arr_augmented_rr(const arr_dev_csr_t *A, int64_t w, const double *X, int64_t ld, int32_t p, const double *Qc,
+                     int64_t ldq, int32_t nc, double *Y, int64_t ldy, double *ritz_vals, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(A && A->dtype == 0 && X && Y && ritz_vals && w > 0 && p >= 0 && ld >= w && ldy >= w, "augmented_rr: bad arguments");
+    ARR_REQUIRE(nc == 0 || (Qc && ldq >= nc), "augmented_rr: bad Qc");
+    const int64_t n = A->n;
+    const int m = (int)((p + 1) * w);
+    ARR_REQUIRE(m <= n, "augmented_rr: (p+1) w must not exceed n");
+    hipStream_t s = as_stream(stream);
+    auto M = dev_csr<double>(A);
+    arr::Work wk;
+    arr::DevBuf zb(sizeof(double) * n * m), ub(sizeof(double) * n * m), wb(sizeof(double) * n * m);
+    const int iw = (int)w;
+    arr::Blk<double> Z{zb.as<double>(), m, m};
+    arr::launch_copy<double>(n, iw, Z.p, m, X, ld, s);
+    const arr::Blk<const double> none{nullptr, 0, 0};
+    for (int i = 1; i <= p; ++i)
+      arr::launch_filter_spmm<double>(M, arr::Blk<const double>{Z.p + (i - 1) * iw, m, iw}, none,
+                                      arr::Blk<double>{Z.p + i * iw, m, iw}, 1.0, 0.0, 0.0, nullptr, s);
+    const arr::Blk<const double> Q{Qc, ldq, nc};
+    if (nc) arr::project_out<double>(n, Q, Z, wk, s);
+    arr::Blk<double> U = arr::orthonormalize<double>(n, Z, arr::Blk<double>{ub.as<double>(), m, m}, Q, wk, s, nullptr);
+    std::vector<double> ev;
+    arr::rayleigh_ritz<double>(M, n, arr::Blk<const double>{U.p, U.ld, m}, arr::Blk<double>{wb.as<double>(), m, m}, wk,
+                               ev, s);
+    const double *V = wk.small.as<double>() + (size_t)m * m;
+    arr::launch_update<double>(n, arr::Blk<const double>{U.p, U.ld, m}, V, m, iw, 1.0, 0.0, arr::Blk<double>{Y, ldy, iw}, s);
+    std::copy(ev.begin(), ev.begin() + iw, ritz_vals);
+    ARR_HIP(hipStreamSynchronize(s));
+    return ARR_OK;
+  });
+}
+
+}  // extern "C"

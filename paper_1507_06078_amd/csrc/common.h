@@ -1,0 +1,192 @@
+// Internal declarations of the gfx950 ARRABIT library: device buffers, kernel
+// launchers and the small helpers they share. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace arr {
+
+// Error raised by a failed HIP call or a violated precondition; the C ABI
+// turns it into a return code and a message.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define ARR_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::arr::Error(-3, std::string(#call) + " failed: " + hipGetErrorString(e_) +     \
+                                 " at " __FILE__ ":" + std::to_string(__LINE__));           \
+  } while (0)
+
+#define ARR_REQUIRE(cond, msg)                                  \
+  do {                                                          \
+    if (!(cond)) throw ::arr::Error(-1, std::string(msg));      \
+  } while (0)
+
+// Device CSR: rowptr int64 [n+1], col int32 [nnz], values in T.
+template <typename T>
+struct DevCSR {
+  int64_t n = 0, nnz = 0;
+  const int64_t *rowptr = nullptr;
+  const int32_t *col = nullptr;
+  const T *val = nullptr;
+};
+
+// A row-major view of columns [0, w) of a device block with leading
+// dimension ld.
+template <typename T>
+struct Blk {
+  T *p = nullptr;
+  int64_t ld = 0;
+  int w = 0;
+  Blk cols(int c0, int wc) const { return Blk{p + c0, ld, wc}; }
+};
+
+// Owned device allocation.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(-2, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+    }
+    bytes = b;
+  }
+  void ensure(size_t b) { if (b > bytes) alloc(b); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---- launchers (spmm.hip) ----------------------------------------------------
+
+// Yout = alpha*A*Yin + beta*Yin + gamma*Z on the w columns of the views; if
+// partial != nullptr, per-workgroup column sums of squares of Yout are written
+// to partial[g*w + c] for g < returned group count. Returns the number of
+// workgroups (rows of `partial`).
+template <typename T>
+int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, double alpha,
+                       double beta, double gamma, double *partial, hipStream_t s);
+// Groups that launch_filter_spmm / launch_colsumsq use for n rows (sizes the
+// partial buffer: groups * w doubles).
+int spmm_groups(int64_t n);
+// y = A x for one vector (Lanczos).
+template <typename T>
+void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s);
+
+// ---- launchers (gemm.hip) ----------------------------------------------------
+
+// G (FP64, mx x my, row-major, ld = my) = X^T Y with X n x mx and Y n x my.
+// `work` must hold gram_work_doubles(n, mx, my) doubles. If sym, X == Y is
+// assumed and only the upper triangle is computed, then mirrored.
+template <typename T>
+void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym,
+                 hipStream_t s);
+size_t gram_work_doubles(int64_t n, int mx, int my);
+// Y = beta*Y + alpha * X * W with W FP64 (m x c, ldw) on the device.
+template <typename T>
+void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int c, double alpha,
+                   double beta, Blk<T> Y, hipStream_t s);
+
+// ---- launchers (misc.hip) ----------------------------------------------------
+
+// Per-group column sums of squares of (P - Q diag(mu)) (Q, mu may be null),
+// written to partial[g*w + c]. Returns the group count.
+template <typename T>
+int launch_colsumsq(int64_t n, Blk<const T> P, Blk<const T> Q, const double *mu, double *partial,
+                    hipStream_t s);
+// out[c] = sum_g partial[g*w + c] (fixed order), optionally sqrt.
+void launch_reduce_groups(const double *partial, int groups, int w, double *out, bool take_sqrt,
+                          hipStream_t s);
+// X[:, c] *= scale[c] (scale FP64 on device); if inv_sqrt, X[:, c] /= sqrt(scale[c]).
+template <typename T>
+void launch_scale_columns(int64_t n, Blk<T> X, const double *scale, bool inv_sqrt, hipStream_t s);
+// dst[:, j] = src_j[:, col_j] for j < w; srcs/cols/lds are device arrays of length w.
+template <typename T>
+void launch_gather_columns(int64_t n, int w, T *dst, int64_t lddst, const T *const *srcs,
+                           const int64_t *lds, const int32_t *cols, hipStream_t s);
+template <typename TD, typename TS>
+void launch_convert(int64_t n, int w, TD *dst, int64_t lddst, const TS *src, int64_t ldsrc,
+                    hipStream_t s);
+// Gaussian N(0,1) block from a counter-based generator (Philox4x32-10 +
+// Box-Muller), entry (i, j) depends only on (seed, i, j).
+void launch_gaussian(int64_t n, int w, double *X, int64_t ld, uint64_t seed, hipStream_t s);
+template <typename T>
+void launch_fill(T *p, int64_t count, T v, hipStream_t s);
+// copy a block (same dtype)
+template <typename T>
+void launch_copy(int64_t n, int w, T *dst, int64_t lddst, const T *src, int64_t ldsrc, hipStream_t s);
+
+// ---- launchers (dense.hip): small FP64 matrices, row-major, on the device ----
+
+// In-place lower Cholesky of the m x m SPD matrix A (upper part left
+// untouched). info (device int) = 0 on success, j+1 if the pivot of column j
+// was not positive. `shift` is added to the diagonal first.
+void launch_cholesky(int m, double *A, int64_t lda, double shift, int *info, hipStream_t s);
+// Winv = L^{-T} (upper triangular, full m x m written, zeros below) for the
+// lower-triangular L (in A's lower part).
+void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t ldw, hipStream_t s);
+// rcond(G) = 1/(|G|_1 |G^-1|_1) for the m x m matrix G (device, ld m), or 0
+// if G is not numerically positive definite. work >= 3 m^2 doubles; info is a
+// device int; the result goes to *rc (device).
+void rcond_device(int m, const double *G, double *work, int *info, double *rc, hipStream_t s);
+// C = beta C + alpha A B for small device matrices with arbitrary strides:
+// A(i,k) = A[i*sai + k*sak], B(k,j) = B[k*sbk + j*sbj]; lower: skip 64 x 64
+// tiles strictly above the diagonal.
+void small_gemm(int m1, int m2, int kk, double alpha, const double *A, int64_t sai, int64_t sak, const double *B,
+                int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc, bool lower, hipStream_t s);
+// max |diag| and Frobenius norm of a small matrix -> out[0], out[1]
+void launch_diag_max(int m, const double *A, int64_t lda, double *out, hipStream_t s);
+// Symmetrize: A = (A + A^T)/2
+void launch_symmetrize(int m, double *A, int64_t lda, hipStream_t s);
+
+// Parallel cyclic Jacobi eigensolver; see dense.hip.
+struct Jacobi {
+  DevBuf bufA, bufB, bufV, bufOff, bufEval;
+  std::vector<double> h_eval;
+  int mcap = 0;
+  // H (m x m, row-major, ld = m) is read; on return the eigenvalues in
+  // descending order are in evals_host (size m) and the matching unit
+  // eigenvectors are the COLUMNS of V (m x m row-major, ld = m):
+  // H = V diag(evals) V^T.
+  void solve(int m, const double *H, double *V, std::vector<double> &evals_host, hipStream_t s,
+             int *sweeps_out = nullptr);
+};
+
+// ---- host helpers ------------------------------------------------------------
+
+// Chebyshev-interpolant coefficients Gamma_d (leading first), Sec. 5.
+std::vector<double> filter_coefficients(int d);
+// The same interpolant in the Chebyshev basis: psi_d = sum_k c[k] T_k.
+std::vector<double> filter_chebyshev_coefficients(int d);
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace arr

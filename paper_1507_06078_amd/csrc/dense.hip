@@ -1,0 +1,472 @@
+// Small FP64 dense linear algebra on the device (matrices of order up to a
+// few thousand, row-major, resident in L2 / Infinity Cache):
+//
+//  * blocked right-looking Cholesky (panel of 32: every workgroup factors the
+//    diagonal block in LDS, then solves its share of the rows below; the
+//    trailing update is a small MFMA GEMM on the lower tiles);
+//  * inverse of a lower-triangular factor (one column per thread, forward
+//    substitution), used for the Cholesky-QR basis Z R^-1 and for rcond;
+//  * rcond(G) = 1/(|G|_1 |G^-1|_1) with G^-1 = L^-T L^-1 (eq. inn-stop);
+//  * the symmetric eigensolver of the Rayleigh-Ritz step (Algorithm 1): a
+//    two-sided cyclic Jacobi method with the round-robin (circle) ordering, so
+//    every step applies m/2 disjoint rotations at once. Each 2 x 2 block of the
+//    matrix is updated by one thread from the two rotations that touch it
+//    (A' = R_I^T A_IJ R_J, double-buffered); eigenvectors are kept as the rows
+//    of V^T so their updates are coalesced. Sweeps stop when a whole sweep
+//    needs no rotation.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "common.h"
+
+namespace arr {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// C[i][j] = beta C[i][j] + alpha sum_k A(i,k) B(k,j), 0 <= i < m1, 0 <= j < m2,
+// A(i,k) = A[i*sai + k*sak], B(k,j) = B[k*sbk + j*sbj]. lower: tiles strictly
+// above the diagonal (in tile units, with row offset) are skipped.
+__global__ __launch_bounds__(256) void k_small_gemm(int m1, int m2, int kk, double alpha, const double *A,
+                                                    int64_t sai, int64_t sak, const double *B, int64_t sbk,
+                                                    int64_t sbj, double beta, double *C, int64_t ldc, int lower) {
+  const int nct = (m2 + 63) / 64;
+  const int rt = blockIdx.x / nct, ct = blockIdx.x % nct;
+  if (lower && ct > rt) return;
+  const int r0 = rt * 64, c0 = ct * 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  __shared__ double As[64][17];
+  __shared__ double Bs[16][65];
+  v4d acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kk; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e / 16, k = e % 16;
+      As[r][k] = (r0 + r < m1 && k0 + k < kk) ? A[(int64_t)(r0 + r) * sai + (int64_t)(k0 + k) * sak] : 0.0;
+      const int kb = e / 64, c = e % 64;
+      Bs[kb][c] = (k0 + kb < kk && c0 + c < m2) ? B[(int64_t)(k0 + kb) * sbk + (int64_t)(c0 + c) * sbj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const double a = As[16 * wv + li][4 * ks + lk];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) acc[g] = mfma16(a, Bs[4 * ks + lk][16 * g + li], acc[g]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int col = c0 + 16 * g + li;
+    if (col >= m2) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = r0 + 16 * wv + lk + 4 * e;
+      if (row >= m1) continue;
+      double *cp = C + (int64_t)row * ldc + col;
+      double v = alpha * acc[g][e];
+      if (beta != 0.0) v += beta * (*cp);
+      *cp = v;
+    }
+  }
+}
+
+}  // namespace
+
+void small_gemm(int m1, int m2, int kk, double alpha, const double *A, int64_t sai, int64_t sak, const double *B,
+                int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc, bool lower, hipStream_t s) {
+  if (m1 <= 0 || m2 <= 0) return;
+  const int grid = ((m1 + 63) / 64) * ((m2 + 63) / 64);
+  hipLaunchKernelGGL(k_small_gemm, dim3(grid), dim3(256), 0, s, m1, m2, kk, alpha, A, sai, sak, B, sbk, sbj, beta,
+                     C, ldc, lower ? 1 : 0);
+  ARR_HIP(hipGetLastError());
+}
+
+namespace {
+
+constexpr int kNB = 32;       // Cholesky panel width
+
+// Diagonal block J0..J0+nb of the Cholesky factorization, factored in place
+// in LDS by one workgroup. A non-positive pivot records its (1-based) column
+// in *info (first failure kept) and is replaced by 1 so the rest stays finite.
+__global__ __launch_bounds__(256) void k_chol_diag(double *A, int64_t lda, int J0, int nb, int *info) {
+  __shared__ double D[kNB][kNB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int r = e / nb, c = e % nb;
+    D[r][c] = A[(int64_t)(J0 + r) * lda + J0 + c];
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (tid == 0) {
+      const double d = D[j][j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        if (!bad) bad = J0 + j + 1;
+        D[j][j] = 1.0;
+      } else {
+        D[j][j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double djj = D[j][j];
+    for (int i = j + 1 + tid; i < nb; i += 256) D[i][j] /= djj;
+    __syncthreads();
+    for (int e = tid; e < (nb - j - 1) * (nb - j - 1); e += 256) {
+      const int i = j + 1 + e / (nb - j - 1), k = j + 1 + e % (nb - j - 1);
+      if (k <= i) D[i][k] -= D[i][j] * D[k][j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int r = e / nb, c = e % nb;
+    if (c <= r) A[(int64_t)(J0 + r) * lda + J0 + c] = D[r][c];
+  }
+  if (tid == 0 && bad && *info == 0) *info = bad;
+}
+
+// Rows below the factored diagonal block: L[i][J] = A[i][J] L_JJ^-T by forward
+// substitution, one row per thread.
+__global__ __launch_bounds__(256) void k_chol_rows(int m, double *A, int64_t lda, int J0, int nb) {
+  __shared__ double D[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int r = e / nb, c = e % nb;
+    D[r][c] = (c <= r) ? A[(int64_t)(J0 + r) * lda + J0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int i = J0 + nb + blockIdx.x * 256 + tid;
+  if (i >= m) return;
+  double *row = A + (int64_t)i * lda + J0;
+  double l[kNB];
+  for (int t = 0; t < nb; ++t) {
+    double v = row[t];
+    for (int q = 0; q < t; ++q) v -= l[q] * D[t][q];
+    l[t] = v / D[t][t];
+  }
+  for (int t = 0; t < nb; ++t) row[t] = l[t];
+}
+
+__global__ void k_add_diag(int m, double *A, int64_t lda, double shift) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) A[(int64_t)i * lda + i] += shift;
+}
+
+// Column j of L^-1 by forward substitution (thread j); written transposed as
+// row j of W = L^-T (upper triangular): W[j][i] = (L^-1)[i][j].
+__global__ void k_tri_inv_t(int m, const double *__restrict__ L, int64_t ldl, double *__restrict__ W, int64_t ldw) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double *wj = W + (int64_t)j * ldw;
+  for (int i = 0; i < j; ++i) wj[i] = 0.0;
+  // x_i = (delta_ij - sum_{q<i} L[i][q] x_q) / L[i][i], i >= j
+  for (int i = j; i < m; ++i) {
+    const double *li = L + (int64_t)i * ldl;
+    double v = (i == j) ? 1.0 : 0.0;
+    for (int q = j; q < i; ++q) v -= li[q] * wj[q];
+    wj[i] = v / li[i];
+  }
+}
+
+// out = max_j sum_i |M[i][j]| (1-norm) of a square matrix, one block.
+__device__ double block_norm1(int m, const double *M, int64_t ld, double *scratch) {
+  double best = 0.0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += fabs(M[(int64_t)i * ld + j]);
+    best = fmax(best, s);
+  }
+  scratch[threadIdx.x] = best;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) scratch[threadIdx.x] = fmax(scratch[threadIdx.x], scratch[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const double r = scratch[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_rcond_final(int m, const double *G, const double *Ginv, const int *info,
+                                                     double *rc) {
+  __shared__ double scratch[256];
+  const double a = block_norm1(m, G, m, scratch);
+  const double b = block_norm1(m, Ginv, m, scratch);
+  if (threadIdx.x == 0) {
+    double r = (a > 0.0 && b > 0.0 && isfinite(a * b)) ? 1.0 / (a * b) : 0.0;
+    if (*info != 0) r = 0.0;
+    *rc = r;
+  }
+}
+
+__global__ void k_symmetrize(int m, double *A, int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int i = (int)(idx / m), j = (int)(idx % m);
+  if (i < j) {
+    const double v = 0.5 * (A[(int64_t)i * lda + j] + A[(int64_t)j * lda + i]);
+    A[(int64_t)i * lda + j] = v;
+    A[(int64_t)j * lda + i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_diag_max(int m, const double *A, int64_t lda, double *out) {
+  __shared__ double s1[256], s2[256];
+  double mx = 0.0, fro = 0.0;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += 256) {
+    const int i = (int)(idx / m), j = (int)(idx % m);
+    const double v = A[(int64_t)i * lda + j];
+    if (i == j) mx = fmax(mx, fabs(v));
+    fro += v * v;
+  }
+  s1[threadIdx.x] = mx;
+  s2[threadIdx.x] = fro;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + off]);
+      s2[threadIdx.x] += s2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s1[0];
+    out[1] = sqrt(s2[0]);
+  }
+}
+
+// ---- Jacobi ------------------------------------------------------------------
+
+__device__ __forceinline__ int rr_player(int pos, int step, int me) {
+  // circle method: position 0 fixed, the others rotate by `step`
+  return pos == 0 ? 0 : 1 + (pos - 1 + step) % (me - 1);
+}
+
+__device__ __forceinline__ void rr_pair(int t, int step, int me, int &p, int &q) {
+  int a = rr_player(t, step, me), b = rr_player(me - 1 - t, step, me);
+  p = min(a, b);
+  q = max(a, b);
+}
+
+// Rotation annihilating a_pq (symmetric Schur decomposition of the 2 x 2
+// block, Golub & Van Loan): returns false when a_pq is negligible.
+__device__ __forceinline__ bool jac_rot(double app, double aqq, double apq, double tiny, double &c, double &s,
+                                        double &t) {
+  if (apq == 0.0 || fabs(apq) <= tiny || fabs(apq) <= 2.2e-16 * sqrt(fabs(app) * fabs(aqq))) {
+    c = 1.0;
+    s = 0.0;
+    t = 0.0;
+    return false;
+  }
+  const double tau = (aqq - app) / (2.0 * apq);
+  if (fabs(tau) > 1e150)
+    t = 0.5 / tau;
+  else
+    t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_step(int me, int step, const double *__restrict__ Ain,
+                                                     double *__restrict__ Aout, double *__restrict__ VT,
+                                                     double tiny, int *rotated) {
+  const int h = me / 2;
+  const int64_t nblk = (int64_t)h * h;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid < nblk) {
+    const int I = (int)(tid / h), J = (int)(tid % h);
+    int p, q, p2, q2;
+    rr_pair(I, step, me, p, q);
+    rr_pair(J, step, me, p2, q2);
+    double cI, sI, tI, cJ, sJ, tJ;
+    const double apq = Ain[(int64_t)p * me + q];
+    const bool rotI = jac_rot(Ain[(int64_t)p * me + p], Ain[(int64_t)q * me + q], apq, tiny, cI, sI, tI);
+    if (I == J) {
+      if (rotI) {
+        Aout[(int64_t)p * me + p] = Ain[(int64_t)p * me + p] - tI * apq;
+        Aout[(int64_t)q * me + q] = Ain[(int64_t)q * me + q] + tI * apq;
+        Aout[(int64_t)p * me + q] = 0.0;
+        Aout[(int64_t)q * me + p] = 0.0;
+        *rotated = 1;
+      } else {
+        Aout[(int64_t)p * me + p] = Ain[(int64_t)p * me + p];
+        Aout[(int64_t)q * me + q] = Ain[(int64_t)q * me + q];
+        Aout[(int64_t)p * me + q] = apq;
+        Aout[(int64_t)q * me + p] = Ain[(int64_t)q * me + p];
+      }
+      return;
+    }
+    jac_rot(Ain[(int64_t)p2 * me + p2], Ain[(int64_t)q2 * me + q2], Ain[(int64_t)p2 * me + q2], tiny, cJ, sJ, tJ);
+    const double b00 = Ain[(int64_t)p * me + p2], b01 = Ain[(int64_t)p * me + q2];
+    const double b10 = Ain[(int64_t)q * me + p2], b11 = Ain[(int64_t)q * me + q2];
+    // X = R_I^T B
+    const double x00 = cI * b00 - sI * b10, x01 = cI * b01 - sI * b11;
+    const double x10 = sI * b00 + cI * b10, x11 = sI * b01 + cI * b11;
+    // B' = X R_J
+    Aout[(int64_t)p * me + p2] = cJ * x00 - sJ * x01;
+    Aout[(int64_t)p * me + q2] = sJ * x00 + cJ * x01;
+    Aout[(int64_t)q * me + p2] = cJ * x10 - sJ * x11;
+    Aout[(int64_t)q * me + q2] = sJ * x10 + cJ * x11;
+    return;
+  }
+  const int64_t v = tid - nblk;
+  if (v >= (int64_t)h * me) return;
+  const int I = (int)(v / me), r = (int)(v % me);
+  int p, q;
+  rr_pair(I, step, me, p, q);
+  double c, s, t;
+  if (!jac_rot(Ain[(int64_t)p * me + p], Ain[(int64_t)q * me + q], Ain[(int64_t)p * me + q], tiny, c, s, t)) return;
+  const double vp = VT[(int64_t)p * me + r], vq = VT[(int64_t)q * me + r];
+  VT[(int64_t)p * me + r] = c * vp - s * vq;
+  VT[(int64_t)q * me + r] = s * vp + c * vq;
+}
+
+__global__ void k_jacobi_init(int m, int me, const double *__restrict__ H, double *__restrict__ A,
+                              double *__restrict__ VT) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)me * me) return;
+  const int i = (int)(idx / me), j = (int)(idx % me);
+  A[idx] = (i < m && j < m) ? 0.5 * (H[(int64_t)i * m + j] + H[(int64_t)j * m + i]) : 0.0;
+  VT[idx] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void k_jacobi_diag(int me, const double *A, double *d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < me) d[i] = A[(int64_t)i * me + i];
+}
+
+__global__ void k_gather_rows(int m, int me, const double *__restrict__ VT, const int *__restrict__ perm,
+                              double *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int r = (int)(idx / m), c = (int)(idx % m);
+  out[idx] = VT[(int64_t)perm[c] * me + r];
+}
+
+}  // namespace
+
+void launch_cholesky(int m, double *A, int64_t lda, double shift, int *info, hipStream_t s) {
+  launch_fill<int>(info, 1, 0, s);
+  if (m == 0) return;
+  if (shift != 0.0) {
+    hipLaunchKernelGGL(k_add_diag, dim3((m + 255) / 256), dim3(256), 0, s, m, A, lda, shift);
+    ARR_HIP(hipGetLastError());
+  }
+  for (int J0 = 0; J0 < m; J0 += kNB) {
+    const int nb = std::min(kNB, m - J0);
+    const int below = m - J0 - nb;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, A, lda, J0, nb, info);
+    ARR_HIP(hipGetLastError());
+    if (below > 0) {
+      hipLaunchKernelGGL(k_chol_rows, dim3((below + 255) / 256), dim3(256), 0, s, m, A, lda, J0, nb);
+      ARR_HIP(hipGetLastError());
+      // A22 -= L21 L21^T (lower tiles)
+      const double *L21 = A + (int64_t)(J0 + nb) * lda + J0;
+      small_gemm(below, below, nb, -1.0, L21, lda, 1, L21, 1, lda, 1.0, A + (int64_t)(J0 + nb) * lda + J0 + nb, lda,
+                 true, s);
+    }
+  }
+}
+
+void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t ldw, hipStream_t s) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_tri_inv_t, dim3((m + 63) / 64), dim3(64), 0, s, m, L, ldl, Winv, ldw);
+  ARR_HIP(hipGetLastError());
+}
+
+void launch_symmetrize(int m, double *A, int64_t lda, hipStream_t s) {
+  if (m == 0) return;
+  const int64_t tot = (int64_t)m * m;
+  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, A, lda);
+  ARR_HIP(hipGetLastError());
+}
+
+void launch_diag_max(int m, const double *A, int64_t lda, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(256), 0, s, m, A, lda, out);
+  ARR_HIP(hipGetLastError());
+}
+
+// rcond(G) for an m x m SPD candidate G (device, ld m). work: 3 m^2 doubles +
+// an int. Result written to rc (device).
+void rcond_device(int m, const double *G, double *work, int *info, double *rc, hipStream_t s) {
+  double *L = work, *Wt = work + (int64_t)m * m, *Gi = work + 2 * (int64_t)m * m;
+  ARR_HIP(hipMemcpyAsync(L, G, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
+  launch_cholesky(m, L, m, 0.0, info, s);
+  launch_tri_inv_t(m, L, m, Wt, m, s);
+  // G^-1 = L^-T L^-1 = Wt Wt^T
+  small_gemm(m, m, m, 1.0, Wt, m, 1, Wt, 1, m, 0.0, Gi, m, false, s);
+  hipLaunchKernelGGL(k_rcond_final, dim3(1), dim3(256), 0, s, m, G, Gi, info, rc);
+  ARR_HIP(hipGetLastError());
+}
+
+void Jacobi::solve(int m, const double *H, double *Vsorted, std::vector<double> &evals_host, hipStream_t s,
+                   int *sweeps_out) {
+  evals_host.assign(m, 0.0);
+  if (m == 0) return;
+  const int me = m + (m & 1);
+  if (me > mcap) {
+    bufA.alloc(sizeof(double) * me * me);
+    bufB.alloc(sizeof(double) * me * me);
+    bufV.alloc(sizeof(double) * me * me);
+    bufOff.alloc(sizeof(double) * 4 + sizeof(int) * 4 + sizeof(int) * me);
+    bufEval.alloc(sizeof(double) * me);
+    mcap = me;
+  }
+  double *A = bufA.as<double>(), *B = bufB.as<double>(), *VT = bufV.as<double>();
+  double *nrm = bufOff.as<double>();
+  int *flag = reinterpret_cast<int *>(nrm + 4);
+  int *perm = flag + 4;
+  const int64_t tot = (int64_t)me * me;
+  hipLaunchKernelGGL(k_jacobi_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, me, H, A, VT);
+  ARR_HIP(hipGetLastError());
+  launch_diag_max(me, A, me, nrm, s);
+  double hn[2];
+  ARR_HIP(hipMemcpyAsync(hn, nrm, sizeof(hn), hipMemcpyDeviceToHost, s));
+  ARR_HIP(hipStreamSynchronize(s));
+  const double tiny = std::max(1e-300, 1e-18 * hn[1]);
+  const int h = me / 2;
+  const int64_t threads = (int64_t)h * h + (int64_t)h * me;
+  const unsigned grid = (unsigned)((threads + 255) / 256);
+  int sweeps = 0;
+  if (me > 1) {
+    for (; sweeps < 60; ++sweeps) {
+      launch_fill<int>(flag, 1, 0, s);
+      for (int st = 0; st < me - 1; ++st) {
+        hipLaunchKernelGGL(k_jacobi_step, dim3(grid), dim3(256), 0, s, me, st, A, B, VT, tiny, flag);
+        std::swap(A, B);
+      }
+      ARR_HIP(hipGetLastError());
+      int hf = 0;
+      ARR_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      ARR_HIP(hipStreamSynchronize(s));
+      if (!hf) break;
+    }
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  hipLaunchKernelGGL(k_jacobi_diag, dim3((me + 255) / 256), dim3(256), 0, s, me, A, bufEval.as<double>());
+  ARR_HIP(hipGetLastError());
+  std::vector<double> d(me);
+  ARR_HIP(hipMemcpyAsync(d.data(), bufEval.as<double>(), sizeof(double) * me, hipMemcpyDeviceToHost, s));
+  ARR_HIP(hipStreamSynchronize(s));
+  std::vector<int> idx(m);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] > d[b]; });
+  for (int i = 0; i < m; ++i) evals_host[i] = d[idx[i]];
+  ARR_HIP(hipMemcpyAsync(perm, idx.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  const int64_t mm = (int64_t)m * m;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, m, me, VT, perm, Vsorted);
+  ARR_HIP(hipGetLastError());
+  ARR_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace arr

@@ -1,0 +1,94 @@
+// ARRABIT-MPM solver state (Algorithm 8) behind the C handle.
+#pragma once
+
+#include <chrono>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/arr.h"
+#include "steps.h"
+
+namespace arr {
+
+// Device blocks of one precision. Z, U, W are n x ldz: Z holds the iterate X
+// in its first w' columns and the Krylov blocks [X, AX, ..., A^p X] of the
+// augmentation (eq. S:ARR); U and W hold the orthonormal basis and A U of the
+// Rayleigh-Ritz step. Q and Q2 (n x w) hold the locked pairs Qc.
+template <typename T>
+struct Blocks {
+  DevBuf Zb, Ub, Wb, Qb, Q2b;
+  int64_t ldz = 0, ldq = 0;
+  bool ready = false;
+  void alloc(int64_t n, int64_t ldz_, int64_t ldq_) {
+    ldz = ldz_;
+    ldq = ldq_;
+    Zb.alloc(sizeof(T) * n * ldz);
+    Ub.alloc(sizeof(T) * n * ldz);
+    Wb.alloc(sizeof(T) * n * ldz);
+    Qb.alloc(sizeof(T) * n * ldq);
+    Q2b.alloc(sizeof(T) * n * ldq);
+    ready = true;
+  }
+  void release() {
+    Zb.release(); Ub.release(); Wb.release(); Qb.release(); Q2b.release();
+    ready = false;
+  }
+  Blk<T> Z(int c0, int w) const { return Blk<T>{Zb.as<T>() + c0, ldz, w}; }
+  Blk<T> U(int c0, int w) const { return Blk<T>{Ub.as<T>() + c0, ldz, w}; }
+  Blk<T> W(int c0, int w) const { return Blk<T>{Wb.as<T>() + c0, ldz, w}; }
+  Blk<T> Q(int w) const { return Blk<T>{Qb.as<T>(), ldq, w}; }
+  Blk<T> Q2(int w) const { return Blk<T>{Q2b.as<T>(), ldq, w}; }
+};
+
+class Solver {
+ public:
+  Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, const arr_options_t &o);
+  ~Solver();
+  void set_initial_block(const double *X0, int64_t ld);
+  int solve();
+  void get(double *evals, double *evecs, int64_t ldv, double *resid);
+  arr_stats_t stats{};
+  std::string err;
+  bool solved = false;
+
+ private:
+  int64_t n_;
+  int k_, which_, w_;
+  double tol_;
+  arr_options_t o_;
+  hipStream_t s_ = nullptr;
+  DevBuf rowptr_, col_, val64_, val32_;
+  DevCSR<double> A64_;
+  DevCSR<float> A32_;
+  Blocks<double> B64_;
+  Blocks<float> B32_;
+  Work wk_;
+  DevBuf desc_, mu_, outv_, x0_;
+  bool have_x0_ = false;
+  std::map<int, std::vector<double>> coef_;
+
+  // iteration state (Algorithm 8)
+  int nc_ = 0, wp_ = 0, d_ = 3, p_ = 1, j_ = 0;
+  double a_ = 0, b_ = 0, norm_ = 0, tol_t_ = 0;
+  std::vector<double> sig_c_, res_c_;
+  double best_maxres_ = 0, maxresp_ = -1, best_mu_k_ = 0, best_mu_w_ = 0;
+  int since_best_ = 0;
+  std::vector<double> out_vals_, out_res_;
+
+  const std::vector<double> &coeffs(int d);
+  void setup_interval();
+  template <typename T>
+  int outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage);
+  template <typename T>
+  void finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src, const std::vector<int64_t> &lds,
+              const std::vector<int32_t> &cols, const std::vector<double> &mu);
+  template <typename T>
+  void gather(int64_t n, int w, T *dst, int64_t lddst, const std::vector<const T *> &src,
+              const std::vector<int64_t> &lds, const std::vector<int32_t> &cols);
+  int degree_update(double mu_k, double mu_w) ;
+  double now() const;
+  std::chrono::steady_clock::time_point t0_;
+};
+
+}  // namespace arr

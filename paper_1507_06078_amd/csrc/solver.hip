@@ -1,0 +1,567 @@
+// ARRABIT-MPM driver (Algorithm 8 with the heuristics of Sec. 6).
+//
+// The host keeps only scalars -- the interval [a, b], the continuation
+// tolerance tol_t, the degree d, the augmentation count p, the Ritz values and
+// residual norms -- and makes the decisions of Sec. 6 from them. Every block
+// operation runs on the device: the filter SpMMs, normalization, deflation
+// projections, Gram products, Cholesky/rcond, Cholesky-QR, the Jacobi
+// eigensolve and the Ritz updates.
+//
+// Readings of the paper followed here (identical to the oracle's):
+//  * the k smallest pairs are the k largest of -A;
+//  * tol_1 = 1e-6 when tol <= 1e-8 (continuation), else tol;
+//  * a = Lanczos theta_min - max(residual bound, 1e-3 spread) (in place of eigs);
+//  * the ratio tests of eq. block and eq. hat-d use shifted values mu - a and
+//    absolute values; no p update in the first outer iteration;
+//  * deflated pairs are re-collected from the merged set every iteration;
+//  * rcond is exact (1/(|G|_1 |G^-1|_1)), 0 if G is not positive definite.
+#include "solver.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+#include <cstdio>
+
+namespace arr {
+
+namespace {
+
+// h[c] = sum_i V[c][i] w[i], c < j (V: j contiguous vectors of length n),
+// one workgroup per c, fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_dots(int64_t n, const double *__restrict__ V, const double *__restrict__ w,
+                                              double *__restrict__ h) {
+  __shared__ double red[256];
+  const double *v = V + (int64_t)blockIdx.x * n;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(v[i], w[i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[blockIdx.x] = red[0];
+}
+
+// w[i] -= sum_{c<j} V[c][i] h[c]
+__global__ __launch_bounds__(256) void k_sub_combination(int64_t n, int j, const double *__restrict__ V,
+                                                         const double *__restrict__ h, double *__restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = w[i];
+  for (int c = 0; c < j; ++c) s -= V[(int64_t)c * n + i] * h[c];
+  w[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_scale_vec(int64_t n, const double *__restrict__ x, const double *nrm2,
+                                                   double *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] / sqrt(*nrm2);
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+
+}  // namespace
+
+Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, const arr_options_t &o)
+    : n_(n), k_(k), which_(which), tol_(tol), o_(o) {
+  ARR_REQUIRE(csr != nullptr, "csr is NULL");
+  ARR_REQUIRE(csr->n == n && n > 0, "csr->n must equal n > 0");
+  ARR_REQUIRE(csr->rowptr && (csr->nnz == 0 || (csr->colind && csr->val)), "csr arrays are NULL");
+  ARR_REQUIRE(which == ARR_LARGEST_ALGEBRAIC || which == ARR_SMALLEST_ALGEBRAIC, "which must be LARGEST or SMALLEST");
+  ARR_REQUIRE(tol > 0.0 && std::isfinite(tol), "tol must be positive");
+  ARR_REQUIRE(k > 0 && k < n, "k must satisfy 0 < k < n");
+  w_ = o.w > 0 ? o.w : k + (int)std::lround(0.1 * k);
+  ARR_REQUIRE(w_ >= k, "block width w must be >= k");
+  ARR_REQUIRE(o.p0 >= 0 && o.p_max >= o.p0, "need 0 <= p0 <= p_max");
+  ARR_REQUIRE((int64_t)(o.p_max + 1) * w_ < n, "need (p_max + 1) * w < n (Algorithm 8)");
+  ARR_REQUIRE(o.d0 >= 1 && o.d_max >= o.d0 && o.d_max <= 64, "need 1 <= d0 <= d_max <= 64");
+  ARR_REQUIRE(o.maxit >= 1 && o.maxit1 >= 1 && o.maxit2 >= 1, "iteration limits must be >= 1");
+  ARR_REQUIRE(o.precision == ARR_FP64 || o.precision == ARR_MIXED, "unknown precision");
+  // validate CSR on the host
+  const int64_t *rp = csr->rowptr;
+  ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
+  for (int64_t i = 0; i < n; ++i) {
+    ARR_REQUIRE(rp[i + 1] >= rp[i], "rowptr must be non-decreasing");
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+      const int32_t c = csr->colind[q];
+      ARR_REQUIRE(c >= 0 && c < n, "column index out of range");
+      ARR_REQUIRE(q == rp[i] || csr->colind[q - 1] < c, "column indices must be strictly increasing within a row");
+      ARR_REQUIRE(std::isfinite(csr->val[q]), "matrix values must be finite");
+    }
+  }
+  // symmetry: every (i, c, v) has its mirror (c, i, v)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+      const int32_t c = csr->colind[q];
+      const int32_t *b = csr->colind + rp[c], *e = csr->colind + rp[c + 1];
+      const int32_t *f = std::lower_bound(b, e, (int32_t)i);
+      ARR_REQUIRE(f != e && *f == i && csr->val[rp[c] + (f - b)] == csr->val[q], "matrix is not symmetric");
+    }
+  }
+  ARR_HIP(hipSetDevice(o.device));
+  ARR_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+  const int64_t nnz = csr->nnz;
+  rowptr_.alloc(sizeof(int64_t) * (n + 1));
+  col_.alloc(sizeof(int32_t) * std::max<int64_t>(1, nnz));
+  val64_.alloc(sizeof(double) * std::max<int64_t>(1, nnz));
+  ARR_HIP(hipMemcpy(rowptr_.p, rp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+  if (nnz) {
+    ARR_HIP(hipMemcpy(col_.p, csr->colind, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    std::vector<double> v(csr->val, csr->val + nnz);
+    if (which == ARR_SMALLEST_ALGEBRAIC)
+      for (double &x : v) x = -x;
+    ARR_HIP(hipMemcpy(val64_.p, v.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
+    if (o.precision == ARR_MIXED) {
+      std::vector<float> f(v.begin(), v.end());
+      val32_.alloc(sizeof(float) * nnz);
+      ARR_HIP(hipMemcpy(val32_.p, f.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
+    }
+  }
+  A64_ = DevCSR<double>{n, nnz, rowptr_.as<int64_t>(), col_.as<int32_t>(), val64_.as<double>()};
+  if (o.precision == ARR_MIXED)
+    A32_ = DevCSR<float>{n, nnz, rowptr_.as<int64_t>(), col_.as<int32_t>(), val32_.as<float>()};
+  const int64_t ldz = round_up((int64_t)std::max(o.p_max + 1, 2) * w_, 8);
+  const int64_t ldq = round_up(w_, 8);
+  B64_.alloc(n, ldz, ldq);
+  if (o.precision == ARR_MIXED) B32_.alloc(n, ldz, ldq);
+  mu_.alloc(sizeof(double) * ldz);
+  desc_.alloc((sizeof(void *) + sizeof(int64_t) + sizeof(int32_t)) * (size_t)ldz + 64);
+  outv_.alloc(sizeof(double) * n * k);
+  wk_.ensure_cols(n, (int)ldz);
+}
+
+Solver::~Solver() {
+  if (s_) (void)hipStreamDestroy(s_);
+}
+
+double Solver::now() const {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+}
+
+const std::vector<double> &Solver::coeffs(int d) {
+  auto it = coef_.find(d);
+  if (it == coef_.end()) it = coef_.emplace(d, filter_coefficients(d)).first;
+  return it->second;
+}
+
+void Solver::set_initial_block(const double *X0, int64_t ld) {
+  ARR_REQUIRE(X0 != nullptr && ld >= w_, "initial block: NULL or ld < w");
+  x0_.alloc(sizeof(double) * n_ * w_);
+  ARR_HIP(hipMemcpy2D(x0_.p, sizeof(double) * w_, X0, sizeof(double) * ld, sizeof(double) * w_, n_,
+                      hipMemcpyHostToDevice));
+  have_x0_ = true;
+}
+
+// Interval [a, b] of Sec. 6 'Estimation of lambda_n and lambda_{k+q}':
+// a from Lanczos with full reorthogonalization started at X0[:, 0] (in place of
+// eigs), b = smallest Ritz value of the starting block.
+void Solver::setup_interval() {
+  const int64_t n = n_;
+  const int L = (int)std::min<int64_t>(o_.lanczos_steps, n);
+  DevBuf V(sizeof(double) * n * L), wv(sizeof(double) * n), h(sizeof(double) * (L + 4));
+  double *Vp = V.as<double>(), *w = wv.as<double>(), *hp = h.as<double>();
+  // v_0 = X0[:, 0] / |X0[:, 0]|
+  launch_copy<double>(n, 1, w, 1, B64_.Zb.as<double>(), B64_.ldz, s_);
+  hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s_, n, w, w, hp);
+  hipLaunchKernelGGL(k_scale_vec, dim3(blocks_for(n)), dim3(256), 0, s_, n, w, hp, Vp);
+  ARR_HIP(hipGetLastError());
+  std::vector<double> alpha, beta;
+  for (int j = 0; j < L; ++j) {
+    double *vj = Vp + (int64_t)j * n;
+    launch_spmv<double>(A64_, vj, w, s_);
+    // full reorthogonalization, twice; the first pass also yields alpha_j
+    double aj = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(256), 0, s_, n, Vp, w, hp);
+      if (pass == 0) ARR_HIP(hipMemcpyAsync(&aj, hp + j, sizeof(double), hipMemcpyDeviceToHost, s_));
+      hipLaunchKernelGGL(k_sub_combination, dim3(blocks_for(n)), dim3(256), 0, s_, n, j + 1, Vp, hp, w);
+    }
+    hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s_, n, w, w, hp + L);
+    ARR_HIP(hipGetLastError());
+    double b2 = 0.0;
+    ARR_HIP(hipMemcpyAsync(&b2, hp + L, sizeof(double), hipMemcpyDeviceToHost, s_));
+    ARR_HIP(hipStreamSynchronize(s_));
+    alpha.push_back(aj);
+    beta.push_back(std::sqrt(std::max(0.0, b2)));
+    if (beta.back() <= 1e-14 * std::max(1.0, std::fabs(aj)) || j == L - 1) break;
+    hipLaunchKernelGGL(k_scale_vec, dim3(blocks_for(n)), dim3(256), 0, s_, n, w, hp + L, Vp + (int64_t)(j + 1) * n);
+    ARR_HIP(hipGetLastError());
+  }
+  const int m = (int)alpha.size();
+  std::vector<double> T((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    T[(size_t)i * m + i] = alpha[i];
+    if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[i];
+  }
+  wk_.ensure_small(std::max(m, w_));
+  double *Td = wk_.small.as<double>(), *Vt = Td + (size_t)m * m;
+  ARR_HIP(hipMemcpyAsync(Td, T.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s_));
+  std::vector<double> th;
+  wk_.jac.solve(m, Td, Vt, th, s_);
+  double slast = 0.0;  // last component of the eigenvector of theta_min (last column)
+  ARR_HIP(hipMemcpyAsync(&slast, Vt + (size_t)(m - 1) * m + (m - 1), sizeof(double), hipMemcpyDeviceToHost, s_));
+  ARR_HIP(hipStreamSynchronize(s_));
+  const double tmin = th[m - 1], tmax = th[0];
+  const double r = std::fabs(beta[m - 1] * slast);
+  a_ = tmin - std::max(r, 1e-3 * (tmax - tmin));
+  norm_ = std::max(std::fabs(tmin), std::fabs(tmax));
+
+  // b: smallest Ritz value of the starting block
+  Blocks<double> &B = B64_;
+  launch_copy<double>(n, w_, B.Ub.as<double>(), B.ldz, B.Zb.as<double>(), B.ldz, s_);
+  const Blk<const double> none{nullptr, 0, 0};
+  Blk<double> U = orthonormalize<double>(n, B.U(0, w_), B.W(0, w_), none, wk_, s_, nullptr);
+  Blk<double> Wt = (U.p == B.Ub.as<double>()) ? B.W(0, w_) : B.U(0, w_);
+  std::vector<double> ev;
+  rayleigh_ritz<double>(A64_, n, Blk<const double>{U.p, U.ld, w_}, Wt, wk_, ev, s_);
+  b_ = ev[w_ - 1];
+}
+
+int Solver::degree_update(double mu_k, double mu_w) {
+  // eq. hat-d / eq. degree with rho_d(t) = psi_d((2t - a - b)/(b - a))
+  auto rho = [&](const std::vector<double> &g, double t) {
+    const double x = (2.0 * t - a_ - b_) / (b_ - a_);
+    double v = 0.0;
+    for (double c : g) v = v * x + c;
+    return v;
+  };
+  for (int d = 3; d <= o_.d_max; ++d) {
+    const std::vector<double> &g = coeffs(d);
+    const double num = std::fabs(rho(g, mu_w)), den = std::fabs(rho(g, mu_k));
+    if (den > 0.0 && num / den < 0.9) return d;
+  }
+  return o_.d_max;
+}
+
+template <typename T>
+void Solver::gather(int64_t n, int w, T *dst, int64_t lddst, const std::vector<const T *> &src,
+                    const std::vector<int64_t> &lds, const std::vector<int32_t> &cols) {
+  if (w == 0) return;
+  char *base = desc_.as<char>();
+  const T **dsrc = reinterpret_cast<const T **>(base);
+  int64_t *dlds = reinterpret_cast<int64_t *>(base + sizeof(void *) * B64_.ldz);
+  int32_t *dcols = reinterpret_cast<int32_t *>(base + (sizeof(void *) + sizeof(int64_t)) * B64_.ldz);
+  ARR_HIP(hipMemcpyAsync(dsrc, src.data(), sizeof(void *) * w, hipMemcpyHostToDevice, s_));
+  ARR_HIP(hipMemcpyAsync(dlds, lds.data(), sizeof(int64_t) * w, hipMemcpyHostToDevice, s_));
+  ARR_HIP(hipMemcpyAsync(dcols, cols.data(), sizeof(int32_t) * w, hipMemcpyHostToDevice, s_));
+  launch_gather_columns<T>(n, w, dst, lddst, dsrc, dlds, dcols, s_);
+  // the host vectors may be reused right away
+  ARR_HIP(hipStreamSynchronize(s_));
+}
+
+// Final output: the k leading merged pairs, re-checked with an explicit FP64
+// SpMM (eq. resi scaling).
+template <typename T>
+void Solver::finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src,
+                    const std::vector<int64_t> &lds, const std::vector<int32_t> &cols, const std::vector<double> &mu) {
+  (void)A;
+  const int64_t n = n_;
+  const int k = k_;
+  std::vector<const T *> s(src.begin(), src.begin() + k);
+  std::vector<int64_t> l(lds.begin(), lds.begin() + k);
+  std::vector<int32_t> c(cols.begin(), cols.begin() + k);
+  if (std::is_same<T, double>::value) {
+    gather<T>(n, k, reinterpret_cast<T *>(outv_.p), k, s, l, c);
+  } else {
+    gather<T>(n, k, B.W(0, k).p, B.ldz, s, l, c);
+    launch_convert<double, T>(n, k, outv_.as<double>(), k, B.W(0, k).p, B.ldz, s_);
+  }
+  // explicit FP64 residuals
+  Blk<double> X{outv_.as<double>(), k, k};
+  Blk<double> AX = B64_.U(0, k);
+  const Blk<const double> none{nullptr, 0, 0};
+  launch_filter_spmm<double>(A64_, Blk<const double>{X.p, X.ld, k}, none, AX, 1.0, 0.0, 0.0, nullptr, s_);
+  ARR_HIP(hipMemcpyAsync(mu_.p, mu.data(), sizeof(double) * k, hipMemcpyHostToDevice, s_));
+  std::vector<double> rn = residual_norms<double>(n, Blk<const double>{AX.p, AX.ld, k},
+                                                  Blk<const double>{X.p, X.ld, k}, mu_.as<double>(), wk_, s_);
+  out_vals_.assign(mu.begin(), mu.begin() + k);
+  out_res_.resize(k);
+  for (int i = 0; i < k; ++i) out_res_[i] = rn[i] / std::max(1.0, std::fabs(mu[i]));
+  if (which_ == ARR_SMALLEST_ALGEBRAIC)
+    for (double &v : out_vals_) v = -v;
+}
+
+// Outer iterations of Algorithm 8 in block precision T. Returns a status
+// (>= 0) when the solve ends, or -100 to hand over to the FP64 stage.
+template <typename T>
+int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
+  const int64_t n = n_;
+  const int k = k_, w = w_;
+  const int fp32_limit = std::max(1, o_.maxit / 2);
+  int fp32_iters = 0, fp32_since_best = 0;
+  double fp32_best = std::numeric_limits<double>::infinity();
+  for (; j_ < o_.maxit;) {
+    ++j_;
+    stats.outer_iters = j_;
+    double t = now();
+    // ---- subspace update: MPM on A - aI over [0, b - a] ----
+    Blk<T> X = B.Z(0, wp_);
+    Blk<T> Ya = B.U(0, wp_), Yb = B.U(wp_, wp_);
+    const Blk<const T> Qc{B.Qb.template as<T>(), B.ldq, nc_};
+    const std::vector<double> &g = coeffs(d_);
+    double rc = std::numeric_limits<double>::infinity();
+    wk_.ensure_cols(n, wp_);
+    for (int i1 = 0; i1 < o_.maxit1; ++i1) {
+      for (int i2 = 0; i2 < o_.maxit2; ++i2) {
+        poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, wk_, true, s_);
+        normalize_from_partial<T>(n, X, wk_, s_);
+        if (nc_) project_out<T>(n, Qc, X, wk_, s_);
+        stats.poly_calls += 1;
+        stats.spmm_degrees += d_;
+        stats.spmm_cols += (int64_t)d_ * wp_;
+      }
+      const double rcp = rc;
+      rc = rcond_gram<T>(n, Blk<const T>{X.p, X.ld, wp_}, wk_, s_);
+      const double thr = fp32_stage ? std::max(tol_t_, 1e-6) : tol_t_;
+      if (rc <= thr || rc / rcp > 0.99) break;
+    }
+    ARR_HIP(hipStreamSynchronize(s_));
+    stats.t_filter += now() - t;
+    t = now();
+    // ---- augmentation [X, AX, ..., A^p X] (eq. S:ARR) in Z ----
+    const Blk<const T> none{nullptr, 0, 0};
+    for (int i = 1; i <= p_; ++i) {
+      launch_filter_spmm<T>(A, Blk<const T>{B.Z((i - 1) * wp_, wp_).p, B.ldz, wp_}, none, B.Z(i * wp_, wp_), 1.0,
+                            0.0, 0.0, nullptr, s_);
+      stats.spmm_degrees += 1;
+      stats.spmm_cols += wp_;
+    }
+    const int m = (p_ + 1) * wp_;
+    // ---- RR on the projection onto R(Qc)^perp (Algorithm 1, Sec. 6) ----
+    const double td = now();
+    Blk<T> U = orthonormalize<T>(n, B.Z(0, m), B.U(0, m), Qc, wk_, s_, nullptr);
+    Blk<T> Pfree = (U.p == B.Zb.template as<T>()) ? B.U(0, m) : B.Z(0, m);
+    std::vector<double> ritz;
+    rayleigh_ritz<T>(A, n, Blk<const T>{U.p, U.ld, m}, B.W(0, m), wk_, ritz, s_);
+    stats.t_dense += now() - td;
+    stats.arr_calls += 1;
+    // ---- merge with (Qc, Sigma_c): keep the w leading (stable, Qc first) ----
+    std::vector<int> order(nc_ + m);
+    std::iota(order.begin(), order.end(), 0);
+    auto val = [&](int i) { return i < nc_ ? sig_c_[i] : ritz[i - nc_]; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return val(x) > val(y); });
+    order.resize(w);
+    int cnew = 0;
+    for (int i : order)
+      if (i >= nc_) cnew = std::max(cnew, i - nc_ + 1);
+    // Ritz vectors X_new = U V[:, :cnew] into the free buffer, A X_new = W V into U's
+    const double *V = wk_.small.template as<double>() + (size_t)m * m;
+    Blk<T> Xn{Pfree.p, Pfree.ld, cnew};
+    launch_update<T>(n, Blk<const T>{U.p, U.ld, m}, V, m, cnew, 1.0, 0.0, Xn, s_);
+    Blk<T> AXn{U.p, U.ld, cnew};
+    launch_update<T>(n, Blk<const T>{B.W(0, m).p, B.ldz, m}, V, m, cnew, 1.0, 0.0, AXn, s_);
+    ARR_HIP(hipMemcpyAsync(mu_.p, ritz.data(), sizeof(double) * cnew, hipMemcpyHostToDevice, s_));
+    std::vector<double> rnew = residual_norms<T>(n, Blk<const T>{AXn.p, AXn.ld, cnew},
+                                                 Blk<const T>{Xn.p, Xn.ld, cnew}, mu_.as<double>(), wk_, s_);
+    std::vector<double> mu(w), res(w);
+    std::vector<const T *> src(w);
+    std::vector<int64_t> lds(w);
+    std::vector<int32_t> cols(w);
+    for (int q = 0; q < w; ++q) {
+      const int i = order[q];
+      if (i < nc_) {
+        mu[q] = sig_c_[i];
+        res[q] = res_c_[i];
+        src[q] = B.Qb.template as<T>();
+        lds[q] = B.ldq;
+        cols[q] = i;
+      } else {
+        const int c = i - nc_;
+        mu[q] = ritz[c];
+        res[q] = rnew[c] / std::max(1.0, std::fabs(ritz[c]));
+        src[q] = Xn.p;
+        lds[q] = Xn.ld;
+        cols[q] = c;
+      }
+    }
+    double maxres = 0.0;
+    for (int q = 0; q < k; ++q) maxres = std::max(maxres, res[q]);
+    if (!(maxres == maxres)) maxres = std::numeric_limits<double>::infinity();
+    stats.maxres = maxres;
+    stats.t_arr += now() - t;
+    if (fp32_stage) stats.fp32_outer += 1;
+    if (o_.verbose) {
+      std::fprintf(stderr,
+                   "[arr] outer %d %s maxres %.3e tol_t %.1e d %d p %d locked %d width %d m %d jacobi_sweeps %d "
+                   "t %.3f s (filter %.3f arr %.3f dense %.3f)\n",
+                   j_, fp32_stage ? "fp32" : "fp64", maxres, tol_t_, d_, p_, nc_, wp_, m, wk_.last_sweeps, now(),
+                   stats.t_filter, stats.t_arr, stats.t_dense);
+      std::fflush(stderr);
+    }
+    // ---- stop rules (eq. out-stop; (i)-(iii) of Sec. 6) ----
+    if (maxres < best_maxres_) {
+      best_maxres_ = maxres;
+      best_mu_k_ = mu[k - 1];
+      best_mu_w_ = mu[w - 1];
+      since_best_ = 0;
+    } else {
+      ++since_best_;
+    }
+    int status = -1;
+    if (!fp32_stage) {
+      if (maxres <= tol_) status = ARR_OK;
+      if (status < 0 && o_.paper_faithful) {
+        int h = 0;
+        for (int q = 0; q < k; ++q) h += res[q] < 0.1 * tol_;
+        if (maxres < (1.0 + 9.0 * h / k) * tol_) status = ARR_OK;
+      }
+      if (status < 0 && since_best_ >= 3) status = ARR_STAGNATED;
+      if (status < 0 && j_ == o_.maxit) status = ARR_NOT_CONVERGED;
+    }
+    if (status >= 0) {
+      finish<T>(B, A, src, lds, cols, mu);
+      stats.final_p = p_;
+      stats.final_d = d_;
+      stats.n_locked = nc_;
+      return status;
+    }
+    // ---- continuation (eq. contin) ----
+    if (maxres <= tol_t_) {
+      tol_t_ = std::max(1e-2 * tol_t_, tol_);
+      b_ = mu[w - 1];
+    }
+    // ---- deflation (eq. defl): Qc re-collected from the merged set ----
+    const double tol_d = std::max(1e-14, tol_t_ * tol_t_);
+    std::vector<const T *> qs, xs;
+    std::vector<int64_t> ql, xl;
+    std::vector<int32_t> qcol, xcol;
+    std::vector<double> nsig, nres;
+    for (int q = 0; q < w; ++q) {
+      if (res[q] <= tol_d) {
+        qs.push_back(src[q]); ql.push_back(lds[q]); qcol.push_back(cols[q]);
+        nsig.push_back(mu[q]); nres.push_back(res[q]);
+      } else {
+        xs.push_back(src[q]); xl.push_back(lds[q]); xcol.push_back(cols[q]);
+      }
+    }
+    const int nc_new = (int)qs.size(), wp_new = (int)xs.size();
+    // new X -> W scratch, then into Z; new Qc -> Q2, then swap Q / Q2
+    gather<T>(n, wp_new, B.W(0, wp_new).p, B.ldz, xs, xl, xcol);
+    gather<T>(n, nc_new, B.Q2b.template as<T>(), B.ldq, qs, ql, qcol);
+    launch_copy<T>(n, wp_new, B.Zb.template as<T>(), B.ldz, B.W(0, wp_new).p, B.ldz, s_);
+    std::swap(B.Qb, B.Q2b);
+    nc_ = nc_new;
+    wp_ = wp_new;
+    sig_c_ = nsig;
+    res_c_ = nres;
+    // ---- augmentation blocks (eq. block) ----
+    if (maxresp_ >= 0.0) {
+      const double ratio = (mu[w - 1] - a_) / (mu[k - 1] - a_);
+      if (ratio > 0.95 && maxres / maxresp_ > 0.1) p_ = std::min(p_ + 1, o_.p_max);
+    }
+    maxresp_ = maxres;
+    // ---- degree (eq. hat-d, eq. degree) ----
+    d_ = degree_update(best_mu_k_, best_mu_w_);
+    if (wp_ == 0) {  // every pair locked
+      std::vector<const T *> s2;
+      std::vector<int64_t> l2;
+      std::vector<int32_t> c2;
+      for (int q = 0; q < nc_; ++q) { s2.push_back(B.Qb.template as<T>()); l2.push_back(B.ldq); c2.push_back(q); }
+      finish<T>(B, A, s2, l2, c2, sig_c_);
+      stats.final_p = p_;
+      stats.final_d = d_;
+      stats.n_locked = nc_;
+      return maxres <= tol_ ? ARR_OK : ARR_NOT_CONVERGED;
+    }
+    if (fp32_stage) {
+      ++fp32_iters;
+      if (maxres < fp32_best * 0.5) {
+        fp32_best = maxres;
+        fp32_since_best = 0;
+      } else {
+        ++fp32_since_best;
+      }
+      if (maxres <= o_.mixed_switch || fp32_since_best >= 2 || fp32_iters >= fp32_limit) return -100;
+    }
+  }
+  return ARR_NOT_CONVERGED;
+}
+
+int Solver::solve() {
+  t0_ = std::chrono::steady_clock::now();
+  stats = arr_stats_t{};
+  solved = false;
+  ARR_HIP(hipSetDevice(o_.device));
+  if (have_x0_)
+    launch_copy<double>(n_, w_, B64_.Zb.as<double>(), B64_.ldz, x0_.as<double>(), w_, s_);
+  else
+    launch_gaussian(n_, w_, B64_.Zb.as<double>(), B64_.ldz, o_.seed, s_);
+  ARR_HIP(hipStreamSynchronize(s_));
+  // state of Algorithm 8
+  d_ = o_.d0;
+  p_ = o_.p0;
+  j_ = 0;
+  nc_ = 0;
+  wp_ = w_;
+  sig_c_.clear();
+  res_c_.clear();
+  best_maxres_ = std::numeric_limits<double>::infinity();
+  maxresp_ = -1.0;
+  since_best_ = 0;
+  tol_t_ = o_.tol1 > 0 ? std::max(o_.tol1, tol_) : (tol_ <= 1e-8 ? 1e-6 : tol_);
+  setup_interval();
+  ARR_HIP(hipStreamSynchronize(s_));
+  stats.t_setup = now();
+  if (o_.verbose) {
+    std::fprintf(stderr, "[arr] setup n %lld k %d w %d a %.6e b %.6e |A| %.6e t %.3f s\n", (long long)n_, k_, w_, a_,
+                 b_, norm_, stats.t_setup);
+    std::fflush(stderr);
+  }
+  int status;
+  if (o_.precision == ARR_MIXED) {
+    launch_convert<float, double>(n_, w_, B32_.Zb.as<float>(), B32_.ldz, B64_.Zb.as<double>(), B64_.ldz, s_);
+    status = outer<float>(B32_, A32_, true);
+    if (status == -100) {
+      // hand the iterate and the locked pairs to the FP64 stage
+      launch_convert<double, float>(n_, wp_, B64_.Zb.as<double>(), B64_.ldz, B32_.Zb.as<float>(), B32_.ldz, s_);
+      if (nc_)
+        launch_convert<double, float>(n_, nc_, B64_.Qb.as<double>(), B64_.ldq, B32_.Qb.as<float>(), B32_.ldq, s_);
+      // the FP64 stage re-derives its stagnation reference
+      best_maxres_ = std::numeric_limits<double>::infinity();
+      since_best_ = 0;
+      status = outer<double>(B64_, A64_, false);
+    }
+  } else {
+    status = outer<double>(B64_, A64_, false);
+  }
+  ARR_HIP(hipStreamSynchronize(s_));
+  stats.t_total = now();
+  stats.status = status;
+  stats.a = which_ == ARR_SMALLEST_ALGEBRAIC ? -a_ : a_;
+  stats.b = which_ == ARR_SMALLEST_ALGEBRAIC ? -b_ : b_;
+  stats.norm_est = norm_;
+  solved = true;
+  return status;
+}
+
+void Solver::get(double *evals, double *evecs, int64_t ldv, double *resid) {
+  ARR_REQUIRE(solved, "arr_get_eigpairs called before a successful arr_solve");
+  const int k = k_;
+  if (evals) std::copy(out_vals_.begin(), out_vals_.end(), evals);
+  if (resid) std::copy(out_res_.begin(), out_res_.end(), resid);
+  if (evecs) {
+    ARR_REQUIRE(ldv >= k, "ldv must be >= k");
+    ARR_HIP(hipMemcpy2D(evecs, sizeof(double) * ldv, outv_.p, sizeof(double) * k, sizeof(double) * k, n_,
+                        hipMemcpyDeviceToHost));
+    // sign convention: the entry of largest magnitude is positive
+    for (int c = 0; c < k; ++c) {
+      double best = -1.0, sgn = 1.0;
+      for (int64_t i = 0; i < n_; ++i) {
+        const double v = evecs[i * ldv + c];
+        if (std::fabs(v) > best) {
+          best = std::fabs(v);
+          sgn = v < 0 ? -1.0 : 1.0;
+        }
+      }
+      if (sgn < 0)
+        for (int64_t i = 0; i < n_; ++i) evecs[i * ldv + c] = -evecs[i * ldv + c];
+    }
+  }
+}
+
+template int Solver::outer<double>(Blocks<double> &, const DevCSR<double> &, bool);
+template int Solver::outer<float>(Blocks<float> &, const DevCSR<float> &, bool);
+
+}  // namespace arr

@@ -1,0 +1,50 @@
+// Device building blocks of the ARRABIT iteration (see steps.hip).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace arr {
+
+// Scratch shared by the building blocks; grows on demand.
+struct Work {
+  DevBuf partial;  // per-workgroup column partial sums
+  DevBuf colv;     // per-column results
+  DevBuf gramw;    // split-K partial tiles of the Gram products
+  DevBuf small;    // small dense matrices (several m x m)
+  DevBuf proj;     // Qc^T X coefficients of the deflation projection
+  DevBuf info;     // device ints / scalars
+  Jacobi jac;
+  int groups = 0;
+  int last_sweeps = 0;
+  void ensure_cols(int64_t n, int w);
+  void ensure_gram(int64_t n, int mx, int my);
+  void ensure_small(int m);
+};
+
+template <typename T>
+void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
+                const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s);
+template <typename T>
+void normalize_from_partial(int64_t n, Blk<T> X, Work &wk, hipStream_t s);
+template <typename T>
+void normalize(int64_t n, Blk<T> X, Work &wk, hipStream_t s);
+template <typename T>
+void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s);
+template <typename T>
+double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s);
+// Orthonormal basis of R(Z) (and orthogonal to Q when Q.w > 0); Z and Zalt
+// are n x m buffers used alternately; returns the one holding the result.
+template <typename T>
+Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk, hipStream_t s, int *passes);
+// W = A U, H = U^T W, eigendecomposition of H: evals (descending, host) and the
+// eigenvectors as columns of the m x m matrix at wk.small + m*m.
+template <typename T>
+void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work &wk, std::vector<double> &evals,
+                   hipStream_t s);
+template <typename T>
+std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, const double *mu_dev, Work &wk,
+                                   hipStream_t s);
+
+}  // namespace arr

@@ -1,0 +1,209 @@
+// Building blocks of the ARRABIT iteration on the device, shared by the
+// solver driver and the step-level C entry points:
+//  * poly_apply   -- Algorithm 7 on the shifted operator (Horner form), one
+//                    fused SpMM launch per degree, the column norms of the last
+//                    degree accumulated in its epilogue;
+//  * normalize    -- x_i = x_i / ||x_i|| (multi-power method, Sec. 3);
+//  * project_out  -- X - Qc (Qc^T X) (Sec. 6, deflation);
+//  * rcond_gram   -- rcond(X^T X) (eq. inn-stop);
+//  * orthonormalize -- Cholesky QR, repeated, with a diagonal shift when the
+//                    Gram is not numerically positive definite (the orth(Z)
+//                    step of Algorithm 1);
+//  * rayleigh_ritz -- H = U^T (A U), eigendecomposition, leading Ritz pairs.
+#include <algorithm>
+#include <cmath>
+
+#include "steps.h"
+
+namespace arr {
+
+void Work::ensure_cols(int64_t n, int w) {
+  const size_t need = (size_t)spmm_groups(n) * (size_t)std::max(w, 1);
+  partial.ensure(sizeof(double) * need);
+  colv.ensure(sizeof(double) * std::max(w, 1));
+  if (!info.p) info.alloc(256);
+}
+
+void Work::ensure_gram(int64_t n, int mx, int my) {
+  gramw.ensure(sizeof(double) * std::max<size_t>(1, gram_work_doubles(n, mx, my)));
+  if (!info.p) info.alloc(256);
+}
+
+void Work::ensure_small(int m) {
+  const size_t per = (size_t)m * m;
+  small.ensure(sizeof(double) * std::max<size_t>(1, 6 * per + 64));
+  if (!info.p) info.alloc(256);
+}
+
+template <typename T>
+void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
+                const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s) {
+  const int d = (int)g.size() - 1;
+  ARR_REQUIRE(d >= 1, "poly: degree must be >= 1");
+  ARR_REQUIRE(hi != lo, "poly: empty interval");
+  const int w = X.w;
+  double *partial = want_norms ? wk.partial.as<double>() : nullptr;
+  const double c0 = (lo + hi) / (lo - hi), c1 = 2.0 / (hi - lo);
+  const Blk<const T> Xc{X.p, X.ld, w};
+  const Blk<const T> none{nullptr, 0, 0};
+  // Y_1 = c0 Y_0 + c1 (A - shift I) Y_0 + g1 X with Y_0 = g0 X
+  const double al1 = c1 * g[0], be1 = g[0] * (c0 - c1 * shift) + g[1];
+  const double al = c1, be = c0 - c1 * shift;
+  if (d == 1) {
+    wk.groups = launch_filter_spmm<T>(A, Xc, none, Ya, al1, be1, 0.0, partial, s);
+    launch_copy<T>(A.n, w, X.p, X.ld, Ya.p, Ya.ld, s);
+    return;
+  }
+  launch_filter_spmm<T>(A, Xc, none, Ya, al1, be1, 0.0, nullptr, s);
+  Blk<T> cur = Ya, nxt = Yb;
+  for (int j = 2; j < d; ++j) {
+    launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, Xc, nxt, al, be, g[j], nullptr, s);
+    std::swap(cur, nxt);
+  }
+  // last degree writes X in place (Z = X is read row-locally before the store)
+  wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, Xc, X, al, be, g[d], partial, s);
+}
+
+template <typename T>
+void normalize_from_partial(int64_t n, Blk<T> X, Work &wk, hipStream_t s) {
+  launch_reduce_groups(wk.partial.as<double>(), wk.groups, X.w, wk.colv.as<double>(), false, s);
+  launch_scale_columns<T>(n, X, wk.colv.as<double>(), true, s);
+}
+
+template <typename T>
+void normalize(int64_t n, Blk<T> X, Work &wk, hipStream_t s) {
+  const Blk<const T> none{nullptr, 0, 0};
+  wk.groups = launch_colsumsq<T>(n, Blk<const T>{X.p, X.ld, X.w}, none, nullptr, wk.partial.as<double>(), s);
+  normalize_from_partial<T>(n, X, wk, s);
+}
+
+template <typename T>
+void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s) {
+  if (Q.w == 0 || X.w == 0) return;
+  wk.ensure_gram(n, Q.w, X.w);
+  wk.proj.ensure(sizeof(double) * (size_t)Q.w * X.w);
+  double *C = wk.proj.as<double>();
+  launch_gram<T>(n, Q, Blk<const T>{X.p, X.ld, X.w}, C, wk.gramw.as<double>(), false, s);
+  launch_update<T>(n, Q, C, X.w, X.w, -1.0, 1.0, X, s);
+}
+
+template <typename T>
+double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s) {
+  const int w = X.w;
+  wk.ensure_gram(n, w, w);
+  wk.ensure_small(w);
+  double *G = wk.small.as<double>();
+  double *work = G + (size_t)w * w;
+  double *rc = work + 3 * (size_t)w * w;
+  launch_gram<T>(n, X, X, G, wk.gramw.as<double>(), true, s);
+  rcond_device(w, G, work, wk.info.as<int>(), rc, s);
+  double h = 0.0;
+  ARR_HIP(hipMemcpyAsync(&h, rc, sizeof(double), hipMemcpyDeviceToHost, s));
+  ARR_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+// One Cholesky-QR pass: G = Z^T Z (+ shift I), G = L L^T, Zout = Z L^-T.
+// Returns the (1-based) failing pivot column or 0.
+template <typename T>
+static int cholqr_pass(int64_t n, Blk<const T> Z, Blk<T> Zout, double shift_rel, Work &wk, hipStream_t s,
+                       double *gnorm_out) {
+  const int m = Z.w;
+  double *G = wk.small.as<double>();
+  double *Wt = G + (size_t)m * m;
+  double *nrm = Wt + (size_t)m * m;  // 2 doubles
+  launch_gram<T>(n, Z, Z, G, wk.gramw.as<double>(), true, s);
+  double shift = 0.0;
+  if (shift_rel > 0.0) {
+    launch_diag_max(m, G, m, nrm, s);
+    double hn[2];
+    ARR_HIP(hipMemcpyAsync(hn, nrm, sizeof(hn), hipMemcpyDeviceToHost, s));
+    ARR_HIP(hipStreamSynchronize(s));
+    shift = shift_rel * hn[1];
+    if (gnorm_out) *gnorm_out = hn[1];
+  }
+  launch_cholesky(m, G, m, shift, wk.info.as<int>(), s);
+  int info = 0;
+  ARR_HIP(hipMemcpyAsync(&info, wk.info.as<int>(), sizeof(int), hipMemcpyDeviceToHost, s));
+  ARR_HIP(hipStreamSynchronize(s));
+  if (info) return info;
+  launch_tri_inv_t(m, G, m, Wt, m, s);
+  launch_update<T>(n, Z, Wt, m, m, 1.0, 0.0, Zout, s);
+  return 0;
+}
+
+template <typename T>
+Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk, hipStream_t s, int *passes) {
+  const int m = Z.w;
+  wk.ensure_gram(n, m, m);
+  wk.ensure_small(m);
+  if (Q.w) wk.ensure_gram(n, Q.w, m);
+  // shifted pass constant (shifted Cholesky QR): 11 (m n + m (m+1)) u |Z|^2
+  const double u = std::is_same<T, float>::value ? 5.96e-8 : 1.11e-16;
+  const double shift_rel = 11.0 * ((double)m * (double)n + (double)m * (m + 1)) * u;
+  Blk<T> cur = Z, nxt = Zalt;
+  int done_plain = 0, total = 0;
+  // up to 2 plain passes after any shifted ones; at most 6 in all
+  while (done_plain < 2 && total < 6) {
+    if (Q.w) project_out<T>(n, Q, cur, wk, s);
+    int info = cholqr_pass<T>(n, Blk<const T>{cur.p, cur.ld, m}, nxt, 0.0, wk, s, nullptr);
+    if (info) {
+      info = cholqr_pass<T>(n, Blk<const T>{cur.p, cur.ld, m}, nxt, shift_rel, wk, s, nullptr);
+      if (info) throw Error(-5, "Cholesky QR broke down even with a diagonal shift");
+      done_plain = 0;
+    } else {
+      ++done_plain;
+    }
+    std::swap(cur, nxt);
+    ++total;
+  }
+  if (passes) *passes = total;
+  return cur;
+}
+
+template <typename T>
+void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work &wk, std::vector<double> &evals,
+                   hipStream_t s) {
+  const int m = U.w;
+  const Blk<const T> none{nullptr, 0, 0};
+  launch_filter_spmm<T>(A, U, none, W, 1.0, 0.0, 0.0, nullptr, s);
+  wk.ensure_gram(n, m, m);
+  wk.ensure_small(m);
+  double *H = wk.small.as<double>();
+  double *V = H + (size_t)m * m;
+  launch_gram<T>(n, U, Blk<const T>{W.p, W.ld, m}, H, wk.gramw.as<double>(), false, s);
+  launch_symmetrize(m, H, m, s);
+  wk.jac.solve(m, H, V, evals, s, &wk.last_sweeps);
+}
+
+template <typename T>
+std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, const double *mu_dev, Work &wk,
+                                   hipStream_t s) {
+  const int w = X.w;
+  std::vector<double> r(w);
+  if (w == 0) return r;
+  wk.ensure_cols(n, w);
+  const int groups = launch_colsumsq<T>(n, AX, X, mu_dev, wk.partial.as<double>(), s);
+  launch_reduce_groups(wk.partial.as<double>(), groups, w, wk.colv.as<double>(), true, s);
+  ARR_HIP(hipMemcpyAsync(r.data(), wk.colv.as<double>(), sizeof(double) * w, hipMemcpyDeviceToHost, s));
+  ARR_HIP(hipStreamSynchronize(s));
+  return r;
+}
+
+#define ARR_INST(T)                                                                                              \
+  template void poly_apply<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, double, double, double,                 \
+                              const std::vector<double> &, Work &, bool, hipStream_t);                           \
+  template void normalize_from_partial<T>(int64_t, Blk<T>, Work &, hipStream_t);                                 \
+  template void normalize<T>(int64_t, Blk<T>, Work &, hipStream_t);                                              \
+  template void project_out<T>(int64_t, Blk<const T>, Blk<T>, Work &, hipStream_t);                             \
+  template double rcond_gram<T>(int64_t, Blk<const T>, Work &, hipStream_t);                                     \
+  template Blk<T> orthonormalize<T>(int64_t, Blk<T>, Blk<T>, Blk<const T>, Work &, hipStream_t, int *);          \
+  template void rayleigh_ritz<T>(const DevCSR<T> &, int64_t, Blk<const T>, Blk<T>, Work &, std::vector<double> &, \
+                                 hipStream_t);                                                                   \
+  template std::vector<double> residual_norms<T>(int64_t, Blk<const T>, Blk<const T>, const double *, Work &,    \
+                                                 hipStream_t);
+ARR_INST(double)
+ARR_INST(float)
+#undef ARR_INST
+
+}  // namespace arr

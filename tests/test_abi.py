@@ -1,0 +1,81 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/arr.h declares, validates its inputs on the host, and its host-side
+filter coefficients (Sec. 5) agree with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import arrabit as O
+from paper_1507_06078_amd import arr, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "arr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(arr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = arr.lib()
+    names = declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(arr.EXPORTS) == names
+
+
+def test_options_defaults_are_the_papers():
+    o = arr.arr_options_default()
+    assert (o.p0, o.p_max, o.d0, o.d_max, o.maxit, o.maxit1, o.maxit2) == (1, 3, 3, 15, 30, 10, 5)
+    assert o.precision == arr.FP64 and o.lanczos_steps == 100
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 11, 15])
+def test_library_coefficients_match_oracle(d):
+    """The library derives Gamma_d from the discrete Chebyshev transform; the
+    oracle solves the Vandermonde system. Same polynomial."""
+    g_lib = arr.arr_filter_coefficients(d)
+    if d == 1:
+        # psi_1 interpolates (-1, 0) and (1, 1): (t + 1)/2
+        np.testing.assert_allclose(g_lib, [0.5, 0.5], atol=1e-15)
+        return
+    g_or = O.interpolant_coefficients(d)
+    np.testing.assert_allclose(g_lib, g_or, rtol=1e-9, atol=1e-9 * np.abs(g_or).max())
+
+
+def _bad(csr_mut, **kw):
+    A = W.laplacian_2d(8)
+    rowptr, colind, val = A.rowptr.copy(), A.colind.copy(), A.val.copy()
+    csr_mut(rowptr, colind, val)
+    B = W.CSR(A.n, rowptr, colind, val)
+    args = dict(n=A.n, k=4, which=arr.SMALLEST, tol=1e-8)
+    args.update(kw)
+    with pytest.raises(arr.ArrError) as e:
+        arr.arr_create(B, args["n"], args["k"], args["which"], args["tol"])
+    assert e.value.code == arr.ARR_EINVAL
+    return str(e.value)
+
+
+def test_create_rejects_invalid_input_on_host():
+    def asym(r, c, v):
+        v[1] += 0.5
+    assert "symmetric" in _bad(asym)
+    def oob(r, c, v):
+        c[3] = 10_000
+    assert "range" in _bad(oob)
+    def unsorted(r, c, v):
+        c[0], c[1] = c[1], c[0]
+    assert "increasing" in _bad(unsorted)
+    def nan(r, c, v):
+        v[0] = np.nan
+    assert "finite" in _bad(nan)
+    _bad(lambda r, c, v: None, k=0)
+    _bad(lambda r, c, v: None, tol=-1.0)
+    _bad(lambda r, c, v: None, n=63)
+    # (p_max + 1) w < n fails: n = 64, k = 60
+    _bad(lambda r, c, v: None, k=60)

@@ -1,0 +1,252 @@
+"""GPU parity of each step of the path, called through the C ABI, against the
+FP64 oracle (or the definition the oracle pins). Sizes span several tiles and
+ragged tails; edge cases: width 1, widths one past a tile, empty rows, ld > w."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import arrabit as O
+from paper_1507_06078_amd import arr, workloads as W
+
+
+def dev(x, dtype=None):
+    dtype = dtype or torch.float64
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def with_empty_rows(n=700, seed=3):
+    """Symmetric matrix with fully empty rows (no diagonal either)."""
+    rng = np.random.default_rng(seed)
+    S = sp.random(n, n, density=0.01, random_state=seed, format="csr")
+    S = S + S.T
+    keep = np.ones(n)
+    keep[rng.choice(n, 60, replace=False)] = 0.0
+    D = sp.diags(keep)
+    S = sp.csr_matrix(D @ S @ D)
+    S.eliminate_zeros()
+    return W.from_scipy(S, "empty_rows")
+
+
+MATS = {
+    "lap3d_12V": lambda: W.laplacian_3d(12, potential_seed=1),
+    "powerlaw_4000": lambda: W.powerlaw_random(4000, seed=7, cap=300),
+    "empty_rows": with_empty_rows,
+}
+
+
+@pytest.mark.parametrize("mat", list(MATS))
+@pytest.mark.parametrize("w", [1, 30, 64, 65, 240, 300])
+def test_filter_step_fp64(mat, w):
+    A = MATS[mat]()
+    S = A.to_scipy()
+    Ad = arr.DeviceCSR(A)
+    rng = np.random.default_rng(w)
+    ld = w + 3
+    Yin = rng.standard_normal((A.n, ld))
+    Z = rng.standard_normal((A.n, ld))
+    out = np.full((A.n, ld + 1), 7.0)
+    Yd, Zd, Od = dev(Yin), dev(Z), dev(out)
+    ss = torch.zeros(w, dtype=torch.float64, device="cuda")
+    al, be, ga = 0.37, -1.25, 0.5
+    arr.arr_filter_step(Ad, Yd[:, :w], Zd[:, :w], Od[:, :w], al, be, ga, colsumsq=ss)
+    torch.cuda.synchronize()
+    got = Od.cpu().numpy()
+    ref = al * (S @ Yin[:, :w]) + be * Yin[:, :w] + ga * Z[:, :w]
+    bound = abs(al) * (abs(S) @ np.abs(Yin[:, :w])) + abs(be) * np.abs(Yin[:, :w]) + abs(ga) * np.abs(Z[:, :w])
+    assert np.all(np.abs(got[:, :w] - ref) <= 64 * 1.2e-16 * bound + 1e-300)
+    assert np.all(got[:, w:] == 7.0)  # columns beyond w untouched
+    np.testing.assert_allclose(ss.cpu().numpy(), (ref ** 2).sum(axis=0), rtol=1e-12)
+
+
+@pytest.mark.parametrize("w", [1, 33, 240])
+def test_filter_step_fp32_and_no_z(w):
+    A = W.powerlaw_random(3000, seed=9, cap=500)
+    S = A.to_scipy()
+    Ad = arr.DeviceCSR(A, dtype=torch.float32)
+    rng = np.random.default_rng(1)
+    Yin = rng.standard_normal((A.n, w)).astype(np.float32)
+    Yd = dev(Yin, torch.float32)
+    Od = torch.zeros_like(Yd)
+    arr.arr_filter_step(Ad, Yd, None, Od, 2.0, 0.25, 0.0)
+    torch.cuda.synchronize()
+    S32 = sp.csr_matrix((A.val.astype(np.float32).astype(np.float64), A.colind, A.rowptr), shape=S.shape)
+    Y64 = Yin.astype(np.float64)
+    ref = 2.0 * (S32 @ Y64) + 0.25 * Y64
+    bound = 2.0 * (abs(S32) @ np.abs(Y64)) + 0.25 * np.abs(Y64)
+    assert np.all(np.abs(Od.cpu().numpy() - ref) <= 600 * 6e-8 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("d", [3, 8, 15])
+def test_poly_matches_oracle_fp64(d):
+    """Algorithm 7 on the shifted operator, as Algorithm 8 calls it."""
+    A = W.laplacian_3d(12, potential_seed=1)
+    S = -A.to_scipy()  # the working operator of a smallest-eigenvalue solve
+    lam = np.linalg.eigvalsh(S.toarray())
+    a, b = lam[0] - 0.01, lam[-40]
+    X = W.gaussian_block(A.n, 37, seed=4)
+    g = O.interpolant_coefficients(d)
+    ref = O.poly(O.shifted(S, a), X, 0.0, b - a, g)
+    Ad = arr.DeviceCSR(A.negated())
+    Xd = dev(X)
+    arr.arr_poly(Ad, Xd, a, 0.0, b - a, arr.arr_filter_coefficients(d))
+    got = Xd.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_poly_fp32_error_is_small():
+    A = W.laplacian_3d(12, potential_seed=1).negated()
+    S = A.to_scipy()
+    lam = np.linalg.eigvalsh(S.toarray())
+    a, b = lam[0] - 0.01, lam[-40]
+    X = W.gaussian_block(A.n, 16, seed=4)
+    g = O.interpolant_coefficients(8)
+    ref = O.poly(O.shifted(S, a), X, 0.0, b - a, g)
+    Xd = dev(X, torch.float32)
+    arr.arr_poly(arr.DeviceCSR(A, dtype=torch.float32), Xd, a, 0.0, b - a, arr.arr_filter_coefficients(8))
+    err = np.abs(Xd.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-4, err
+
+
+@pytest.mark.parametrize("n,mx,my", [(5003, 1, 1), (5003, 17, 65), (777, 64, 64), (20011, 130, 200), (33, 5, 3)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gram(n, mx, my, dtype):
+    rng = np.random.default_rng(n + mx)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    X = rng.standard_normal((n, mx + 2))
+    Y = rng.standard_normal((n, my + 1))
+    if dtype == "f32":
+        X, Y = X.astype(np.float32).astype(np.float64), Y.astype(np.float32).astype(np.float64)
+    Xd, Yd = dev(X, tdt), dev(Y, tdt)
+    G = torch.zeros((mx, my), dtype=torch.float64, device="cuda")
+    arr.arr_gram(Xd[:, :mx], Yd[:, :my], G)
+    ref = X[:, :mx].T @ Y[:, :my]
+    bound = np.abs(X[:, :mx]).T @ np.abs(Y[:, :my])
+    assert np.all(np.abs(G.cpu().numpy() - ref) <= 1e-14 * np.sqrt(n) * bound + 1e-300)
+    # symmetric product (same buffer): exactly symmetric
+    Gs = torch.zeros((mx, mx), dtype=torch.float64, device="cuda")
+    arr.arr_gram(Xd[:, :mx], Xd[:, :mx], Gs)
+    gs = Gs.cpu().numpy()
+    assert np.array_equal(gs, gs.T)
+    ref_s = X[:, :mx].T @ X[:, :mx]
+    assert np.all(np.abs(gs - ref_s) <= 1e-14 * np.sqrt(n) * (np.abs(X[:, :mx]).T @ np.abs(X[:, :mx])))
+
+
+@pytest.mark.parametrize("n,m,c", [(5003, 1, 1), (5003, 16, 65), (4097, 17, 64), (20011, 480, 240), (70, 100, 3)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_block_update(n, m, c, dtype):
+    rng = np.random.default_rng(m * c)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    X = rng.standard_normal((n, m))
+    Wm = rng.standard_normal((m, c + 2))
+    Y0 = rng.standard_normal((n, c + 1))
+    if dtype == "f32":
+        X, Y0 = X.astype(np.float32).astype(np.float64), Y0.astype(np.float32).astype(np.float64)
+    Xd, Wd, Yd = dev(X, tdt), dev(Wm), dev(Y0, tdt)
+    arr.arr_block_update(Xd, Wd[:, :c], Yd[:, :c], alpha=-0.5, beta=2.0)
+    torch.cuda.synchronize()
+    ref = 2.0 * Y0[:, :c] - 0.5 * X @ Wm[:, :c]
+    bound = 2.0 * np.abs(Y0[:, :c]) + 0.5 * np.abs(X) @ np.abs(Wm[:, :c])
+    eps = 1.2e-16 if dtype == "f64" else 6e-8
+    got = Yd.double().cpu().numpy()
+    assert np.all(np.abs(got[:, :c] - ref) <= 4 * m * eps * bound + 1e-300)
+    assert np.array_equal(got[:, c:], Y0[:, c:])
+
+
+def test_rcond_matches_oracle():
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((3001, 40))
+    assert abs(arr.arr_rcond_gram(dev(X)) / O.rcond_gram(X) - 1) < 1e-10
+    # ill conditioned: two nearly parallel columns
+    Xi = X.copy()
+    Xi[:, 1] = Xi[:, 0] + 1e-5 * Xi[:, 1]
+    r_or, r_gpu = O.rcond_gram(Xi), arr.arr_rcond_gram(dev(Xi))
+    assert abs(r_gpu / r_or - 1) < 1e-4
+    # exactly dependent: not positive definite numerically (both tiny or zero)
+    Xs = X.copy()
+    Xs[:, 3] = Xs[:, 2]
+    assert arr.arr_rcond_gram(dev(Xs)) < 1e-14 and O.rcond_gram(Xs) < 1e-14
+
+
+@pytest.mark.parametrize("kind", ["random", "ill", "krylov"])
+def test_orthonormalize(kind):
+    rng = np.random.default_rng(11)
+    n, m = 6007, 96
+    Z = rng.standard_normal((n, m))
+    if kind == "ill":
+        Z[:, m // 2:] = Z[:, : m // 2] + 1e-7 * rng.standard_normal((n, m // 2))
+    if kind == "krylov":
+        A = W.laplacian_3d(18, potential_seed=2).to_scipy()  # n = 5832
+        n = A.shape[0]
+        X = rng.standard_normal((n, 32))
+        for _ in range(20):  # nearly dependent columns, like the MPM iterate
+            X = A @ X
+            X /= np.linalg.norm(X, axis=0)
+        Z = np.hstack([X, A @ X, A @ (A @ X)])
+        m = Z.shape[1]
+    Zd = dev(Z)
+    arr.arr_orthonormalize(Zd)
+    U = Zd.cpu().numpy()
+    assert np.abs(U.T @ U - np.eye(m)).max() < 1e-12
+    # R(Z) is contained in R(U)
+    assert np.linalg.norm(Z - U @ (U.T @ Z)) <= 1e-9 * np.linalg.norm(Z)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 31, 64, 100, 257])
+def test_syev_random(m):
+    rng = np.random.default_rng(m)
+    Hm = rng.standard_normal((m, m))
+    Hm = Hm + Hm.T
+    _check_syev(Hm)
+
+
+def test_syev_degenerate_and_zero():
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    lam = np.array([3.0] * 5 + [1.0] * 10 + [0.0] * 20 + [-2.0] * 5)
+    _check_syev(Q @ np.diag(lam) @ Q.T)
+    _check_syev(np.zeros((12, 12)))
+    _check_syev(np.diag(np.arange(9.0)))
+
+
+def _check_syev(Hm):
+    m = Hm.shape[0]
+    Hd = dev(Hm)
+    ev = torch.zeros(m, dtype=torch.float64, device="cuda")
+    V = torch.zeros((m, m), dtype=torch.float64, device="cuda")
+    arr.arr_syev(Hd, ev, V)
+    e, Vh = ev.cpu().numpy(), V.cpu().numpy()
+    nrm = max(1.0, np.abs(Hm).max())
+    ref = np.sort(np.linalg.eigvalsh(Hm))[::-1]
+    assert np.all(np.diff(e) <= 0)
+    assert np.abs(e - ref).max() <= 1e-13 * m * nrm
+    assert np.abs(Hm @ Vh - Vh * e[None, :]).max() <= 1e-12 * m * nrm
+    assert np.abs(Vh.T @ Vh - np.eye(m)).max() <= 1e-13 * m
+
+
+@pytest.mark.parametrize("p", [0, 1, 2])
+@pytest.mark.parametrize("deflate", [False, True])
+def test_augmented_rr_matches_oracle(p, deflate):
+    A = W.laplacian_3d(12, potential_seed=1).negated()
+    S = A.to_scipy()
+    w = 24
+    X = W.gaussian_block(A.n, w, seed=8)
+    Qc = None
+    if deflate:
+        lam, Qf = np.linalg.eigh(S.toarray())
+        Qc = Qf[:, -4:].copy()
+        X = O.project_out(Qc, X)
+    Yo, so = O.augmented_rr(S, X, p, Qc)
+    Yd = torch.zeros((A.n, w), dtype=torch.float64, device="cuda")
+    vals = arr.arr_augmented_rr(arr.DeviceCSR(A), dev(X), p, None if Qc is None else dev(Qc), Yd)
+    assert np.abs(vals - so[:w]).max() <= 1e-10 * max(1.0, np.abs(so).max())
+    Y = Yd.cpu().numpy()
+    # Ritz pairs: orthonormal, Galerkin residuals match the oracle's in size
+    assert np.abs(Y.T @ Y - np.eye(w)).max() < 1e-11
+    r_gpu = np.linalg.norm(S @ Y - Y * vals[None, :], axis=0)
+    r_or = np.linalg.norm(S @ Yo[:, :w] - Yo[:, :w] * so[None, :w], axis=0)
+    assert np.all(r_gpu <= r_or * (1 + 1e-6) + 1e-10)
+    if deflate:
+        assert np.abs(Qc.T @ Y).max() < 1e-10
