@@ -91,6 +91,7 @@ typedef struct {
   uint64_t seed;         /* seed of the device Gaussian starting block                     */
   double mixed_switch;   /* ARR_MIXED: leave FP32 once maxres <= this (default 1e-5)       */
   int32_t verbose;       /* 1: one line per outer iteration on stderr                      */
+  int32_t timing;        /* 1: time filter SpMM launches with HIP events (stats)           */
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -111,7 +112,15 @@ typedef struct {
   double t_setup;        /* interval estimation                         */
   double t_filter;       /* subspace update (filter, normalize, project, rcond) */
   double t_arr;          /* augmentation + RR + residuals               */
-  double t_dense;        /* small dense work inside t_arr (Cholesky, eigensolve) */
+  double t_dense;        /* orthonormalization + Rayleigh-Ritz inside t_arr */
+  /* HIP-event timing of the filter SpMM launches of the most time-consuming
+   * kernel variant (set when arr_options_t.timing = 1): launch count, summed
+   * kernel milliseconds, summed algorithmic bytes (CSR read once, the gathered
+   * input block counted once, the recurrence block and the output block). */
+  int64_t spmm_launches;
+  double spmm_ms;
+  double spmm_bytes;
+  int32_t spmm_cols_per_lane; /* kernel variant: columns per lane (1, 2, 4, 8, 16) */
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

@@ -51,7 +51,7 @@ class arr_options_t(ctypes.Structure):
                 ("maxit1", ctypes.c_int32), ("maxit2", ctypes.c_int32), ("tol1", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("paper_faithful", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("device", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("mixed_switch", ctypes.c_double), ("verbose", ctypes.c_int32)]
+                ("mixed_switch", ctypes.c_double), ("verbose", ctypes.c_int32), ("timing", ctypes.c_int32)]
 
 
 class arr_stats_t(ctypes.Structure):
@@ -61,7 +61,9 @@ class arr_stats_t(ctypes.Structure):
                 ("spmm_degrees", ctypes.c_int64), ("spmm_cols", ctypes.c_int64),
                 ("a", ctypes.c_double), ("b", ctypes.c_double), ("norm_est", ctypes.c_double),
                 ("maxres", ctypes.c_double), ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double),
-                ("t_filter", ctypes.c_double), ("t_arr", ctypes.c_double), ("t_dense", ctypes.c_double)]
+                ("t_filter", ctypes.c_double), ("t_arr", ctypes.c_double), ("t_dense", ctypes.c_double),
+                ("spmm_launches", ctypes.c_int64), ("spmm_ms", ctypes.c_double), ("spmm_bytes", ctypes.c_double),
+                ("spmm_cols_per_lane", ctypes.c_int32)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",

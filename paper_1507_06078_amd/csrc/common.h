@@ -94,6 +94,20 @@ struct DevBuf {
 template <typename T>
 int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, double alpha,
                        double beta, double gamma, double *partial, hipStream_t s);
+// Optional HIP-event timing of filter SpMM launches, per kernel variant
+// (columns per lane). Installed per thread by the solver.
+struct SpmmTimer {
+  struct Pending { hipEvent_t a, b; int cls; double bytes; };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  int64_t launches[5] = {0, 0, 0, 0, 0};
+  double ms[5] = {0, 0, 0, 0, 0}, bytes[5] = {0, 0, 0, 0, 0};
+  hipEvent_t get();
+  void flush();  // waits for the recorded events and accumulates
+  void reset();
+  ~SpmmTimer();
+};
+SpmmTimer *&spmm_timer();
 // Groups that launch_filter_spmm / launch_colsumsq use for n rows (sizes the
 // partial buffer: groups * w doubles).
 int spmm_groups(int64_t n);

@@ -484,6 +484,12 @@ int Solver::solve() {
   stats = arr_stats_t{};
   solved = false;
   ARR_HIP(hipSetDevice(o_.device));
+  SpmmTimer timer;
+  struct Install {
+    SpmmTimer *prev;
+    explicit Install(SpmmTimer *t) : prev(spmm_timer()) { spmm_timer() = t; }
+    ~Install() { spmm_timer() = prev; }
+  } install(o_.timing ? &timer : nullptr);
   if (have_x0_)
     launch_copy<double>(n_, w_, B64_.Zb.as<double>(), B64_.ldz, x0_.as<double>(), w_, s_);
   else
@@ -528,6 +534,16 @@ int Solver::solve() {
   }
   ARR_HIP(hipStreamSynchronize(s_));
   stats.t_total = now();
+  if (o_.timing) {
+    timer.flush();
+    int best = 0;
+    for (int c = 1; c < 5; ++c)
+      if (timer.ms[c] > timer.ms[best]) best = c;
+    stats.spmm_launches = timer.launches[best];
+    stats.spmm_ms = timer.ms[best];
+    stats.spmm_bytes = timer.bytes[best];
+    stats.spmm_cols_per_lane = 1 << best;
+  }
   stats.status = status;
   stats.a = which_ == ARR_SMALLEST_ALGEBRAIC ? -a_ : a_;
   stats.b = which_ == ARR_SMALLEST_ALGEBRAIC ? -b_ : b_;

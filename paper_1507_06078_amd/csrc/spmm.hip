@@ -144,6 +144,46 @@ void launch_nj(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout
 
 }  // namespace
 
+SpmmTimer *&spmm_timer() {
+  static thread_local SpmmTimer *t = nullptr;
+  return t;
+}
+
+hipEvent_t SpmmTimer::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  ARR_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void SpmmTimer::flush() {
+  for (Pending &p : pending) {
+    ARR_HIP(hipEventSynchronize(p.b));
+    float t = 0.f;
+    ARR_HIP(hipEventElapsedTime(&t, p.a, p.b));
+    launches[p.cls] += 1;
+    ms[p.cls] += t;
+    bytes[p.cls] += p.bytes;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+void SpmmTimer::reset() {
+  flush();
+  for (int i = 0; i < 5; ++i) launches[i] = 0, ms[i] = 0, bytes[i] = 0;
+}
+
+SpmmTimer::~SpmmTimer() {
+  for (Pending &p : pending) pool.push_back(p.a), pool.push_back(p.b);
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
 int spmm_groups(int64_t n) {
   // 8 workgroups of 4 waves per CU on 256 CUs; a multiple of the XCD count.
   int64_t need = (n + kWaves - 1) / kWaves;
@@ -160,10 +200,22 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   ARR_REQUIRE(Yin.p != Yout.p, "filter_spmm: Yout must not alias Yin");
   const int groups = spmm_groups(A.n);
   if (A.n == 0 || w == 0) return groups;
+  SpmmTimer *timer = spmm_timer();
   // Column chunks of at most 1024 (16 slots per lane).
   for (int c0 = 0; c0 < w; c0 += 1024) {
     const int wc = std::min(1024, w - c0);
     const T al = (T)alpha, be = (T)beta, ga = (T)gamma;
+    const int cls = wc <= 64 ? 0 : wc <= 128 ? 1 : wc <= 256 ? 2 : wc <= 512 ? 3 : 4;
+    SpmmTimer::Pending pend{};
+    if (timer) {
+      pend.a = timer->get();
+      pend.b = timer->get();
+      pend.cls = cls;
+      // algorithmic bytes: CSR once, gathered Yin once, Z, Yout
+      pend.bytes = (double)(sizeof(T) + 4) * A.nnz + 8.0 * (A.n + 1) +
+                   (double)sizeof(T) * A.n * wc * (2.0 + (Z.p ? 1.0 : 0.0));
+      ARR_HIP(hipEventRecord(pend.a, s));
+    }
     if (wc <= 64)
       launch_nj<T, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
     else if (wc <= 128)
@@ -174,6 +226,10 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
       launch_nj<T, 8>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
     else
       launch_nj<T, 16>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+    if (timer) {
+      ARR_HIP(hipEventRecord(pend.b, s));
+      timer->pending.push_back(pend);
+    }
   }
   ARR_HIP(hipGetLastError());
   return groups;
