@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--mixed-switch", type=float, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -82,6 +83,8 @@ def main():
     o.w = w
     o.precision = arr.MIXED if args.precision == "mixed" else arr.FP64
     o.timing = 1
+    if args.mixed_switch is not None:
+        o.mixed_switch = args.mixed_switch
     o.verbose = 1 if args.verbose else 0
     h = arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o)
     print(f"[bench] handle ready (n={A.n}, nnz={A.nnz}); warmup {args.warmup}, steps {args.steps}",

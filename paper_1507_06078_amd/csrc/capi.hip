@@ -63,7 +63,7 @@ void arr_options_default(arr_options_t *o) {
   o->lanczos_steps = 100;
   o->device = 0;
   o->seed = 2;
-  o->mixed_switch = 1e-5;
+  o->mixed_switch = 1e-4;
 }
 
 int arr_create_ex(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,

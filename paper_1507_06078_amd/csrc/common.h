@@ -124,10 +124,11 @@ template <typename T>
 void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym,
                  hipStream_t s);
 size_t gram_work_doubles(int64_t n, int mx, int my);
-// Y = beta*Y + alpha * X * W with W FP64 (m x c, ldw) on the device.
+// Y = beta*Y + alpha * X * W with W FP64 (m x c, ldw) on the device; w_upper:
+// W is upper triangular (its zero blocks are skipped). Y must not alias X.
 template <typename T>
 void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int c, double alpha,
-                   double beta, Blk<T> Y, hipStream_t s);
+                   double beta, Blk<T> Y, hipStream_t s, bool w_upper = false);
 
 // ---- launchers (misc.hip) ----------------------------------------------------
 
@@ -165,10 +166,11 @@ void launch_copy(int64_t n, int w, T *dst, int64_t lddst, const T *src, int64_t 
 // was not positive. `shift` is added to the diagonal first.
 void launch_cholesky(int m, double *A, int64_t lda, double shift, int *info, hipStream_t s);
 // Winv = L^{-T} (upper triangular, full m x m written, zeros below) for the
-// lower-triangular L (in A's lower part).
-void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t ldw, hipStream_t s);
+// lower-triangular L (in A's lower part). scratch >= 2 m^2 doubles.
+void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t ldw, double *scratch,
+                      hipStream_t s);
 // rcond(G) = 1/(|G|_1 |G^-1|_1) for the m x m matrix G (device, ld m), or 0
-// if G is not numerically positive definite. work >= 3 m^2 doubles; info is a
+// if G is not numerically positive definite. work >= 5 m^2 doubles; info is a
 // device int; the result goes to *rc (device).
 void rcond_device(int m, const double *G, double *work, int *info, double *rc, hipStream_t s);
 // C = beta C + alpha A B for small device matrices with arbitrary strides:

@@ -4,16 +4,18 @@
 //  * blocked right-looking Cholesky (panel of 32: every workgroup factors the
 //    diagonal block in LDS, then solves its share of the rows below; the
 //    trailing update is a small MFMA GEMM on the lower tiles);
-//  * inverse of a lower-triangular factor (one column per thread, forward
-//    substitution), used for the Cholesky-QR basis Z R^-1 and for rcond;
+//  * inverse of a lower-triangular factor (diagonal blocks in LDS, then
+//    recursive doubling with batched MFMA GEMMs), used for the Cholesky-QR
+//    basis Z R^-1 and for rcond;
 //  * rcond(G) = 1/(|G|_1 |G^-1|_1) with G^-1 = L^-T L^-1 (eq. inn-stop);
 //  * the symmetric eigensolver of the Rayleigh-Ritz step (Algorithm 1): a
-//    two-sided cyclic Jacobi method with the round-robin (circle) ordering, so
-//    every step applies m/2 disjoint rotations at once. Each 2 x 2 block of the
-//    matrix is updated by one thread from the two rotations that touch it
-//    (A' = R_I^T A_IJ R_J, double-buffered); eigenvectors are kept as the rows
-//    of V^T so their updates are coalesced. Sweeps stop when a whole sweep
-//    needs no rotation.
+//    two-sided block Jacobi method. Indices are grouped in blocks of 16; each
+//    step pairs the blocks by the round-robin (circle) ordering, diagonalizes
+//    every 32 x 32 pair subproblem completely in LDS (scalar cyclic Jacobi, 16
+//    rotations at a time), then applies the 32 x 32 rotations to the whole
+//    matrix (A' = R_t^T A R_u blockwise, double-buffered) and to the
+//    eigenvectors (kept as rows of V^T so updates are coalesced). Sweeps stop
+//    when no subproblem needed a rotation.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -161,20 +163,124 @@ __global__ void k_add_diag(int m, double *A, int64_t lda, double shift) {
   if (i < m) A[(int64_t)i * lda + i] += shift;
 }
 
-// Column j of L^-1 by forward substitution (thread j); written transposed as
-// row j of W = L^-T (upper triangular): W[j][i] = (L^-1)[i][j].
-__global__ void k_tri_inv_t(int m, const double *__restrict__ L, int64_t ldl, double *__restrict__ W, int64_t ldw) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  double *wj = W + (int64_t)j * ldw;
-  for (int i = 0; i < j; ++i) wj[i] = 0.0;
-  // x_i = (delta_ij - sum_{q<i} L[i][q] x_q) / L[i][i], i >= j
-  for (int i = j; i < m; ++i) {
-    const double *li = L + (int64_t)i * ldl;
-    double v = (i == j) ? 1.0 : 0.0;
-    for (int q = j; q < i; ++q) v -= li[q] * wj[q];
-    wj[i] = v / li[i];
+// Inverse of the lower-triangular L (m x m), built in two phases:
+//  1. every 32 x 32 diagonal block is inverted in LDS by one workgroup
+//     (one column per thread, forward substitution);
+//  2. recursive doubling: for blocks A = [lo, lo+s) and C = [lo+s, lo+2s)
+//     with both inverses known, the off-diagonal block of the inverse of
+//     [A 0; B C] is -C^-1 B A^-1; all pairs of one level are merged by two
+//     batched GEMM launches (T = B A^-1, X = -C^-1 T).
+// The result Li (lower, zeros above) is finally transposed into W = L^-T.
+constexpr int kTB = 32;
+
+__global__ __launch_bounds__(64) void k_trinv_diag(int m, const double *__restrict__ L, int64_t ldl,
+                                                   double *__restrict__ Li, int64_t ldi) {
+  __shared__ double D[kTB][kTB + 1];
+  __shared__ double X[kTB][kTB + 1];
+  const int b0 = blockIdx.x * kTB;
+  const int nb = min(kTB, m - b0);
+  for (int e = threadIdx.x; e < kTB * kTB; e += 64) {
+    const int r = e / kTB, c = e % kTB;
+    D[r][c] = (r < nb && c <= r) ? L[(int64_t)(b0 + r) * ldl + b0 + c] : 0.0;
   }
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j < nb) {
+    for (int i = 0; i < nb; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      if (i >= j) {
+        for (int q = j; q < i; ++q) v -= D[i][q] * X[q][j];
+        v /= D[i][i];
+      } else {
+        v = 0.0;
+      }
+      X[i][j] = v;
+    }
+  }
+  __syncthreads();
+  // write the diagonal block and clear the row segment to its right
+  for (int e = threadIdx.x; e < nb * kTB; e += 64) {
+    const int r = e / kTB, c = e % kTB;
+    if (c < nb) Li[(int64_t)(b0 + r) * ldi + b0 + c] = X[r][c];
+  }
+}
+
+// One merge level (block size s): pair p covers A = [2ps, 2ps+s), C = [2ps+s,
+// min(2ps+2s, m)). mode 0: T = B A^-1 (T stored at Ti with the same row/col
+// offsets as B); mode 1: Li[C rows][A cols] = -C^-1 T.
+__global__ __launch_bounds__(256) void k_trinv_merge(int m, int s, int mode, const double *__restrict__ L,
+                                                     int64_t ldl, double *Li, int64_t ldi, double *T) {
+  const int p = blockIdx.y;
+  const int lo = 2 * p * s, mid = lo + s, hi = min(lo + 2 * s, m);
+  if (mid >= m) return;
+  const int rows = hi - mid, cols = s;
+  const int ntc = (cols + 63) / 64;
+  const int rt = blockIdx.x / ntc, ct = blockIdx.x % ntc;
+  const int r0 = rt * 64, c0 = ct * 64;
+  if (r0 >= rows) return;
+  const int kk = mode == 0 ? s : rows;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  __shared__ double As[64][17];
+  __shared__ double Bs[16][65];
+  v4d acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kk; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e / 16, k = e % 16;
+      const int gr = r0 + r, gk = k0 + k;
+      double av = 0.0;
+      if (gr < rows && gk < kk) {
+        if (mode == 0)
+          av = L[(int64_t)(mid + gr) * ldl + lo + gk];   // B = L[C rows][A cols]
+        else
+          av = (gk <= gr) ? Li[(int64_t)(mid + gr) * ldi + mid + gk] : 0.0;  // C^-1 (lower)
+      }
+      As[r][k] = av;
+      const int kb = e / 64, c = e % 64;
+      const int gkb = k0 + kb, gc = c0 + c;
+      double bv = 0.0;
+      if (gkb < kk && gc < cols) {
+        if (mode == 0)
+          bv = (gc <= gkb) ? Li[(int64_t)(lo + gkb) * ldi + lo + gc] : 0.0;  // A^-1 (lower)
+        else
+          bv = T[(int64_t)(mid + gkb) * ldi + lo + gc];
+      }
+      Bs[kb][c] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const double a = As[16 * wv + li][4 * ks + lk];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) acc[g] = mfma16(a, Bs[4 * ks + lk][16 * g + li], acc[g]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int col = c0 + 16 * g + li;
+    if (col >= cols) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = r0 + 16 * wv + lk + 4 * e;
+      if (row >= rows) continue;
+      if (mode == 0)
+        T[(int64_t)(mid + row) * ldi + lo + col] = acc[g][e];
+      else
+        Li[(int64_t)(mid + row) * ldi + lo + col] = -acc[g][e];
+    }
+  }
+}
+
+// W[j][i] = Li[i][j] for i >= j, 0 for i < j.
+__global__ void k_lower_to_upper_t(int m, const double *__restrict__ Li, int64_t ldi, double *__restrict__ W,
+                                   int64_t ldw) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int j = (int)(idx / m), i = (int)(idx % m);
+  W[(int64_t)j * ldw + i] = (i >= j) ? Li[(int64_t)i * ldi + j] : 0.0;
 }
 
 // out = max_j sum_i |M[i][j]| (1-norm) of a square matrix, one block.
@@ -277,58 +383,176 @@ __device__ __forceinline__ bool jac_rot(double app, double aqq, double apq, doub
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_jacobi_step(int me, int step, const double *__restrict__ Ain,
-                                                     double *__restrict__ Aout, double *__restrict__ VT,
-                                                     double tiny, int *rotated) {
-  const int h = me / 2;
-  const int64_t nblk = (int64_t)h * h;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid < nblk) {
-    const int I = (int)(tid / h), J = (int)(tid % h);
-    int p, q, p2, q2;
-    rr_pair(I, step, me, p, q);
-    rr_pair(J, step, me, p2, q2);
-    double cI, sI, tI, cJ, sJ, tJ;
-    const double apq = Ain[(int64_t)p * me + q];
-    const bool rotI = jac_rot(Ain[(int64_t)p * me + p], Ain[(int64_t)q * me + q], apq, tiny, cI, sI, tI);
-    if (I == J) {
-      if (rotI) {
-        Aout[(int64_t)p * me + p] = Ain[(int64_t)p * me + p] - tI * apq;
-        Aout[(int64_t)q * me + q] = Ain[(int64_t)q * me + q] + tI * apq;
-        Aout[(int64_t)p * me + q] = 0.0;
-        Aout[(int64_t)q * me + p] = 0.0;
-        *rotated = 1;
-      } else {
-        Aout[(int64_t)p * me + p] = Ain[(int64_t)p * me + p];
-        Aout[(int64_t)q * me + q] = Ain[(int64_t)q * me + q];
-        Aout[(int64_t)p * me + q] = apq;
-        Aout[(int64_t)q * me + p] = Ain[(int64_t)q * me + p];
-      }
-      return;
-    }
-    jac_rot(Ain[(int64_t)p2 * me + p2], Ain[(int64_t)q2 * me + q2], Ain[(int64_t)p2 * me + q2], tiny, cJ, sJ, tJ);
-    const double b00 = Ain[(int64_t)p * me + p2], b01 = Ain[(int64_t)p * me + q2];
-    const double b10 = Ain[(int64_t)q * me + p2], b11 = Ain[(int64_t)q * me + q2];
-    // X = R_I^T B
-    const double x00 = cI * b00 - sI * b10, x01 = cI * b01 - sI * b11;
-    const double x10 = sI * b00 + cI * b10, x11 = sI * b01 + cI * b11;
-    // B' = X R_J
-    Aout[(int64_t)p * me + p2] = cJ * x00 - sJ * x01;
-    Aout[(int64_t)p * me + q2] = sJ * x00 + cJ * x01;
-    Aout[(int64_t)q * me + p2] = cJ * x10 - sJ * x11;
-    Aout[(int64_t)q * me + q2] = sJ * x10 + cJ * x11;
-    return;
+// ---- block Jacobi --------------------------------------------------------------
+// Index blocks of kBJ = 16; a subproblem is the 32 x 32 principal submatrix of
+// a pair of blocks (P, Q); the pairs of one step come from the round-robin
+// ordering of the me / 16 blocks.
+constexpr int kBJ = 16;
+constexpr int kBJ2 = 2 * kBJ;
+constexpr int kInnerSweeps = 2;  // inner sweeps per subproblem and outer step
+
+__device__ __forceinline__ int bj_index(int r, int P, int Q) { return r < kBJ ? P * kBJ + r : Q * kBJ + (r - kBJ); }
+
+// Diagonalize the subproblem of pair t in LDS by cyclic Jacobi (circle
+// ordering, 16 rotations at a time); write the accumulated rotation R
+// (S_final = R^T S R) to Rbuf + t * 32 * 32. Sets *rotated if the first inner
+// sweep needed any rotation.
+__global__ __launch_bounds__(256) void k_bj_solve(int me, int nb, int step, const double *__restrict__ A,
+                                                  double *__restrict__ Rbuf, double tiny, int *rotated) {
+  __shared__ double S[2][kBJ2][kBJ2 + 1];
+  __shared__ double R[kBJ2][kBJ2 + 1];
+  __shared__ double cs[kBJ2 / 2][3];
+  __shared__ int act[kBJ2 / 2];
+  __shared__ int any;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  int P, Q;
+  rr_pair(t, step, nb, P, Q);
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int r = e / kBJ2, c = e % kBJ2;
+    S[0][r][c] = A[(int64_t)bj_index(r, P, Q) * me + bj_index(c, P, Q)];
+    R[r][c] = (r == c) ? 1.0 : 0.0;
   }
-  const int64_t v = tid - nblk;
-  if (v >= (int64_t)h * me) return;
-  const int I = (int)(v / me), r = (int)(v % me);
-  int p, q;
-  rr_pair(I, step, me, p, q);
-  double c, s, t;
-  if (!jac_rot(Ain[(int64_t)p * me + p], Ain[(int64_t)q * me + q], Ain[(int64_t)p * me + q], tiny, c, s, t)) return;
-  const double vp = VT[(int64_t)p * me + r], vq = VT[(int64_t)q * me + r];
-  VT[(int64_t)p * me + r] = c * vp - s * vq;
-  VT[(int64_t)q * me + r] = s * vp + c * vq;
+  int cur = 0, first_any = 0;
+  for (int sw = 0; sw < kInnerSweeps; ++sw) {
+    if (tid == 0) any = 0;
+    __syncthreads();
+    for (int st = 0; st < kBJ2 - 1; ++st) {
+      if (tid < kBJ2 / 2) {
+        int p, q;
+        rr_pair(tid, st, kBJ2, p, q);
+        double c, sn, tv;
+        const bool r = jac_rot(S[cur][p][p], S[cur][q][q], S[cur][p][q], tiny, c, sn, tv);
+        cs[tid][0] = c;
+        cs[tid][1] = sn;
+        cs[tid][2] = tv;
+        act[tid] = r ? 1 : 0;
+        if (r) any = 1;
+      }
+      __syncthreads();
+      {
+        const int I = tid / (kBJ2 / 2), J = tid % (kBJ2 / 2);
+        int p, q, p2, q2;
+        rr_pair(I, st, kBJ2, p, q);
+        rr_pair(J, st, kBJ2, p2, q2);
+        double(*Si)[kBJ2 + 1] = S[cur];
+        double(*So)[kBJ2 + 1] = S[cur ^ 1];
+        if (I == J) {
+          if (act[I]) {
+            const double apq = Si[p][q], tv = cs[I][2];
+            So[p][p] = Si[p][p] - tv * apq;
+            So[q][q] = Si[q][q] + tv * apq;
+            So[p][q] = 0.0;
+            So[q][p] = 0.0;
+          } else {
+            So[p][p] = Si[p][p];
+            So[q][q] = Si[q][q];
+            So[p][q] = Si[p][q];
+            So[q][p] = Si[q][p];
+          }
+        } else {
+          const double cI = cs[I][0], sI = cs[I][1], cJ = cs[J][0], sJ = cs[J][1];
+          const double b00 = Si[p][p2], b01 = Si[p][q2], b10 = Si[q][p2], b11 = Si[q][q2];
+          const double x00 = cI * b00 - sI * b10, x01 = cI * b01 - sI * b11;
+          const double x10 = sI * b00 + cI * b10, x11 = sI * b01 + cI * b11;
+          So[p][p2] = cJ * x00 - sJ * x01;
+          So[p][q2] = sJ * x00 + cJ * x01;
+          So[q][p2] = cJ * x10 - sJ * x11;
+          So[q][q2] = sJ * x10 + cJ * x11;
+        }
+      }
+      for (int e = tid; e < (kBJ2 / 2) * kBJ2; e += 256) {
+        const int I = e / kBJ2, r = e % kBJ2;
+        if (act[I]) {
+          int p, q;
+          rr_pair(I, st, kBJ2, p, q);
+          const double c = cs[I][0], sn = cs[I][1];
+          const double rp = R[r][p], rq = R[r][q];
+          R[r][p] = c * rp - sn * rq;
+          R[r][q] = sn * rp + c * rq;
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    const int a = any;
+    if (sw == 0) first_any = a;
+    __syncthreads();
+    if (!a) break;
+  }
+  double *out = Rbuf + (int64_t)t * kBJ2 * kBJ2;
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) out[e] = R[e / kBJ2][e % kBJ2];
+  if (tid == 0 && first_any) *rotated = 1;
+}
+
+// A_out[g_t, g_u] = R_t^T A_in[g_t, g_u] R_u for every pair of pairs (t, u).
+__device__ void bj_update(int blk, int me, int nb, int step, const double *__restrict__ Ain,
+                          double *__restrict__ Aout, const double *__restrict__ Rbuf) {
+  __shared__ double X[kBJ2][kBJ2 + 1], Rt[kBJ2][kBJ2 + 1], Ru[kBJ2][kBJ2 + 1], Y[kBJ2][kBJ2 + 1];
+  const int np = nb / 2;
+  const int t = blk / np, u = blk % np, tid = threadIdx.x;
+  int Pt, Qt, Pu, Qu;
+  rr_pair(t, step, nb, Pt, Qt);
+  rr_pair(u, step, nb, Pu, Qu);
+  const double *rt = Rbuf + (int64_t)t * kBJ2 * kBJ2, *ru = Rbuf + (int64_t)u * kBJ2 * kBJ2;
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int r = e / kBJ2, c = e % kBJ2;
+    X[r][c] = Ain[(int64_t)bj_index(r, Pt, Qt) * me + bj_index(c, Pu, Qu)];
+    Rt[r][c] = rt[e];
+    Ru[r][c] = ru[e];
+  }
+  __syncthreads();
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int r = e / kBJ2, c = e % kBJ2;
+    double v = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kBJ2; ++k) v = fma(Rt[k][r], X[k][c], v);
+    Y[r][c] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int r = e / kBJ2, c = e % kBJ2;
+    double v = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kBJ2; ++k) v = fma(Y[r][k], Ru[k][c], v);
+    Aout[(int64_t)bj_index(r, Pt, Qt) * me + bj_index(c, Pu, Qu)] = v;
+  }
+}
+
+// VT[g_t, c0:c0+64] = R_t^T VT[g_t, c0:c0+64] (eigenvectors kept as rows).
+__device__ void bj_vupdate(int blk, int me, int nb, int step, double *__restrict__ VT,
+                           const double *__restrict__ Rbuf) {
+  __shared__ double W[kBJ2][65], Rt[kBJ2][kBJ2 + 1];
+  const int nchunk = (me + 63) / 64;
+  const int t = blk / nchunk, c0 = (blk % nchunk) * 64, tid = threadIdx.x;
+  int P, Q;
+  rr_pair(t, step, nb, P, Q);
+  const double *rt = Rbuf + (int64_t)t * kBJ2 * kBJ2;
+  for (int e = tid; e < kBJ2 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    W[r][c] = (c0 + c < me) ? VT[(int64_t)bj_index(r, P, Q) * me + c0 + c] : 0.0;
+  }
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) Rt[e / kBJ2][e % kBJ2] = rt[e];
+  __syncthreads();
+  for (int e = tid; e < kBJ2 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    if (c0 + c >= me) continue;
+    double v = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kBJ2; ++k) v = fma(Rt[k][r], W[k][c], v);
+    VT[(int64_t)bj_index(r, P, Q) * me + c0 + c] = v;
+  }
+}
+
+// One launch applies the rotations of a step to the matrix (first np^2
+// workgroups) and to the eigenvectors (the rest).
+__global__ __launch_bounds__(256) void k_bj_apply(int me, int nb, int step, const double *__restrict__ Ain,
+                                                  double *__restrict__ Aout, double *__restrict__ VT,
+                                                  const double *__restrict__ Rbuf) {
+  const int np = nb / 2;
+  if ((int)blockIdx.x < np * np)
+    bj_update(blockIdx.x, me, nb, step, Ain, Aout, Rbuf);
+  else
+    bj_vupdate(blockIdx.x - np * np, me, nb, step, VT, Rbuf);
 }
 
 __global__ void k_jacobi_init(int m, int me, const double *__restrict__ H, double *__restrict__ A,
@@ -378,9 +602,23 @@ void launch_cholesky(int m, double *A, int64_t lda, double shift, int *info, hip
   }
 }
 
-void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t ldw, hipStream_t s) {
+void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t ldw, double *scratch,
+                      hipStream_t s) {
   if (m == 0) return;
-  hipLaunchKernelGGL(k_tri_inv_t, dim3((m + 63) / 64), dim3(64), 0, s, m, L, ldl, Winv, ldw);
+  double *Li = scratch, *T = Li + (size_t)m * m;
+  const int nblk = (m + kTB - 1) / kTB;
+  hipLaunchKernelGGL(k_trinv_diag, dim3(nblk), dim3(64), 0, s, m, L, ldl, Li, (int64_t)m);
+  ARR_HIP(hipGetLastError());
+  for (int bs = kTB; bs < m; bs *= 2) {
+    const int pairs = (m + 2 * bs - 1) / (2 * bs);
+    const int tiles = ((bs + 63) / 64) * ((bs + 63) / 64);
+    hipLaunchKernelGGL(k_trinv_merge, dim3(tiles, pairs), dim3(256), 0, s, m, bs, 0, L, ldl, Li, (int64_t)m, T);
+    hipLaunchKernelGGL(k_trinv_merge, dim3(tiles, pairs), dim3(256), 0, s, m, bs, 1, L, ldl, Li, (int64_t)m, T);
+    ARR_HIP(hipGetLastError());
+  }
+  const int64_t tot = (int64_t)m * m;
+  hipLaunchKernelGGL(k_lower_to_upper_t, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, Li, (int64_t)m,
+                     Winv, ldw);
   ARR_HIP(hipGetLastError());
 }
 
@@ -396,33 +634,36 @@ void launch_diag_max(int m, const double *A, int64_t lda, double *out, hipStream
   ARR_HIP(hipGetLastError());
 }
 
-// rcond(G) for an m x m SPD candidate G (device, ld m). work: 3 m^2 doubles +
-// an int. Result written to rc (device).
+// rcond(G) for an m x m SPD candidate G (device, ld m). work: 5 m^2 doubles.
+// Result written to rc (device).
 void rcond_device(int m, const double *G, double *work, int *info, double *rc, hipStream_t s) {
   double *L = work, *Wt = work + (int64_t)m * m, *Gi = work + 2 * (int64_t)m * m;
+  double *scratch = work + 3 * (int64_t)m * m;
   ARR_HIP(hipMemcpyAsync(L, G, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
   launch_cholesky(m, L, m, 0.0, info, s);
-  launch_tri_inv_t(m, L, m, Wt, m, s);
+  launch_tri_inv_t(m, L, m, Wt, m, scratch, s);
   // G^-1 = L^-T L^-1 = Wt Wt^T
   small_gemm(m, m, m, 1.0, Wt, m, 1, Wt, 1, m, 0.0, Gi, m, false, s);
   hipLaunchKernelGGL(k_rcond_final, dim3(1), dim3(256), 0, s, m, G, Gi, info, rc);
   ARR_HIP(hipGetLastError());
 }
 
-void Jacobi::solve(int m, const double *H, double *Vsorted, std::vector<double> &evals_host, hipStream_t s,
+void Jacobi::solve(int m, const double *H, double *V, std::vector<double> &evals_host, hipStream_t s,
                    int *sweeps_out) {
   evals_host.assign(m, 0.0);
   if (m == 0) return;
-  const int me = m + (m & 1);
+  const int me = (m + kBJ2 - 1) / kBJ2 * kBJ2;  // padded with decoupled zero rows/columns
+  const int nb = me / kBJ, np = nb / 2;
   if (me > mcap) {
     bufA.alloc(sizeof(double) * me * me);
     bufB.alloc(sizeof(double) * me * me);
     bufV.alloc(sizeof(double) * me * me);
     bufOff.alloc(sizeof(double) * 4 + sizeof(int) * 4 + sizeof(int) * me);
-    bufEval.alloc(sizeof(double) * me);
+    bufEval.alloc(sizeof(double) * (me + (size_t)np * kBJ2 * kBJ2));
     mcap = me;
   }
   double *A = bufA.as<double>(), *B = bufB.as<double>(), *VT = bufV.as<double>();
+  double *Rbuf = bufEval.as<double>() + me;
   double *nrm = bufOff.as<double>();
   int *flag = reinterpret_cast<int *>(nrm + 4);
   int *perm = flag + 4;
@@ -434,23 +675,21 @@ void Jacobi::solve(int m, const double *H, double *Vsorted, std::vector<double> 
   ARR_HIP(hipMemcpyAsync(hn, nrm, sizeof(hn), hipMemcpyDeviceToHost, s));
   ARR_HIP(hipStreamSynchronize(s));
   const double tiny = std::max(1e-300, 1e-18 * hn[1]);
-  const int h = me / 2;
-  const int64_t threads = (int64_t)h * h + (int64_t)h * me;
-  const unsigned grid = (unsigned)((threads + 255) / 256);
+  const int nchunk = (me + 63) / 64;
   int sweeps = 0;
-  if (me > 1) {
-    for (; sweeps < 60; ++sweeps) {
-      launch_fill<int>(flag, 1, 0, s);
-      for (int st = 0; st < me - 1; ++st) {
-        hipLaunchKernelGGL(k_jacobi_step, dim3(grid), dim3(256), 0, s, me, st, A, B, VT, tiny, flag);
-        std::swap(A, B);
-      }
-      ARR_HIP(hipGetLastError());
-      int hf = 0;
-      ARR_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-      ARR_HIP(hipStreamSynchronize(s));
-      if (!hf) break;
+  for (; sweeps < 40; ++sweeps) {
+    launch_fill<int>(flag, 1, 0, s);
+    const int steps = nb > 1 ? nb - 1 : 1;
+    for (int st = 0; st < steps; ++st) {
+      hipLaunchKernelGGL(k_bj_solve, dim3(np), dim3(256), 0, s, me, nb, st, A, Rbuf, tiny, flag);
+      hipLaunchKernelGGL(k_bj_apply, dim3(np * np + np * nchunk), dim3(256), 0, s, me, nb, st, A, B, VT, Rbuf);
+      std::swap(A, B);
     }
+    ARR_HIP(hipGetLastError());
+    int hf = 0;
+    ARR_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ARR_HIP(hipStreamSynchronize(s));
+    if (!hf) break;
   }
   if (sweeps_out) *sweeps_out = sweeps;
   hipLaunchKernelGGL(k_jacobi_diag, dim3((me + 255) / 256), dim3(256), 0, s, me, A, bufEval.as<double>());
@@ -464,7 +703,7 @@ void Jacobi::solve(int m, const double *H, double *Vsorted, std::vector<double> 
   for (int i = 0; i < m; ++i) evals_host[i] = d[idx[i]];
   ARR_HIP(hipMemcpyAsync(perm, idx.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
   const int64_t mm = (int64_t)m * m;
-  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, m, me, VT, perm, Vsorted);
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, m, me, VT, perm, V);
   ARR_HIP(hipGetLastError());
   ARR_HIP(hipStreamSynchronize(s));
 }

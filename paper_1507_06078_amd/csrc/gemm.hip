@@ -92,8 +92,10 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X
     okx[f] = cx + 16 * f + li < mx;
     oky[f] = cy + 16 * f + li < my;
   }
-  for (int64_t r = r0 + 4 * wv; r < r1; r += 32) {
-    double a[2][4], b[2][4];
+  // software pipeline: the loads of the next 32-row step are in flight while
+  // the matrix cores consume the current one
+  double a[2][4], b[2][4];
+  auto load = [&](int64_t r, double (&la)[2][4], double (&lb)[2][4]) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int64_t row = r + 16 * u + lk;
@@ -102,16 +104,31 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X
       const T *yr = Y + row * ldy + cy + li;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        a[u][f] = (rok && okx[f]) ? (double)xr[16 * f] : 0.0;
-        b[u][f] = (rok && oky[f]) ? (double)yr[16 * f] : 0.0;
+        la[u][f] = (rok && okx[f]) ? (double)xr[16 * f] : 0.0;
+        lb[u][f] = (rok && oky[f]) ? (double)yr[16 * f] : 0.0;
       }
     }
+  };
+  int64_t r = r0 + 4 * wv;
+  if (r < r1) load(r, a, b);
+  for (; r < r1; r += 32) {
+    double na[2][4], nb[2][4];
+    if (r + 32 < r1) load(r + 32, na, nb);
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[f][g] = mfma16(a[u][f], b[u][g], acc[f][g]);
+    if (r + 32 < r1) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          a[u][f] = na[u][f];
+          b[u][f] = nb[u][f];
+        }
+    }
   }
 
   __shared__ double red[64 * 64];
@@ -163,7 +180,7 @@ __global__ void k_mirror_upper(int m, double *G) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__ X, int64_t ldx, int m,
                                                 const double *__restrict__ W, int64_t ldw, int c, double alpha,
-                                                double beta, T *Y, int64_t ldy, int nct, int64_t nrt) {
+                                                double beta, T *Y, int64_t ldy, int nct, int64_t nrt, int w_upper) {
   // tile order: XCD x gets workgroups b = x + 8 t; t walks the column tiles of
   // one row band before moving to the next band of that XCD.
   const int xcd = blockIdx.x % kXcd;
@@ -176,6 +193,8 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  // W upper triangular: rows k > c0 + 63 of this column tile are zero
+  const int kend = w_upper ? min(m, c0 + 64) : m;
 
   __shared__ double Xs[64][17];
   __shared__ double Ws[16][65];
@@ -184,26 +203,28 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
 #pragma unroll
   for (int g = 0; g < 4; ++g) acc[g] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < m; k0 += 16) {
-    {  // X tile: 64 rows x 16 k
-      const int rr = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 4;
-      const int64_t row = r0 + rr;
+  const int xr_ = threadIdx.x >> 2, xk = (threadIdx.x & 3) * 4;   // X tile: 64 rows x 16 k
+  const int wk_ = threadIdx.x >> 4, wc = (threadIdx.x & 15) * 4;  // W tile: 16 k x 64 cols
+  const int64_t xrow = r0 + xr_;
+  double xv[4], wvv[4];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kk = k0 + kq + q;
-        Xs[rr][kq + q] = (row < n && kk < m) ? (double)X[row * ldx + kk] : 0.0;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int kk = k0 + xk + q;
+      xv[q] = (xrow < n && kk < kend) ? (double)X[xrow * ldx + kk] : 0.0;
+      const int kw = k0 + wk_, cc = c0 + wc + q;
+      wvv[q] = (kw < kend && cc < c) ? W[(int64_t)kw * ldw + cc] : 0.0;
     }
-    {  // W tile: 16 k x 64 cols
-      const int kr = threadIdx.x >> 4, cq = (threadIdx.x & 15) * 4;
-      const int kk = k0 + kr;
+  };
+  if (kend > 0) load(0);
+  for (int k0 = 0; k0 < kend; k0 += 16) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int cc = c0 + cq + q;
-        Ws[kr][cq + q] = (kk < m && cc < c) ? W[(int64_t)kk * ldw + cc] : 0.0;
-      }
+    for (int q = 0; q < 4; ++q) {
+      Xs[xr_][xk + q] = xv[q];
+      Ws[wk_][wc + q] = wvv[q];
     }
     __syncthreads();
+    if (k0 + 16 < kend) load(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const double a = Xs[16 * wv + li][4 * ks + lk];
@@ -257,7 +278,7 @@ void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *w
 
 template <typename T>
 void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int c, double alpha, double beta,
-                   Blk<T> Y, hipStream_t s) {
+                   Blk<T> Y, hipStream_t s, bool w_upper) {
   const int m = X.w;
   if (n == 0 || c == 0) return;
   const int nct = (c + 63) / 64;
@@ -265,7 +286,7 @@ void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int 
   const int64_t bands_per_xcd = (nrt + kXcd - 1) / kXcd;
   const int64_t grid = bands_per_xcd * nct * kXcd;
   hipLaunchKernelGGL((k_update<T>), dim3((unsigned)grid), dim3(256), 0, s, n, X.p, X.ld, m, W, ldw, c, alpha,
-                     beta, Y.p, Y.ld, nct, nrt);
+                     beta, Y.p, Y.ld, nct, nrt, w_upper ? 1 : 0);
   ARR_HIP(hipGetLastError());
 }
 
@@ -274,8 +295,8 @@ template void launch_gram<double>(int64_t, Blk<const double>, Blk<const double>,
 template void launch_gram<float>(int64_t, Blk<const float>, Blk<const float>, double *, double *, bool,
                                  hipStream_t);
 template void launch_update<double>(int64_t, Blk<const double>, const double *, int64_t, int, double, double,
-                                    Blk<double>, hipStream_t);
+                                    Blk<double>, hipStream_t, bool);
 template void launch_update<float>(int64_t, Blk<const float>, const double *, int64_t, int, double, double,
-                                   Blk<float>, hipStream_t);
+                                   Blk<float>, hipStream_t, bool);
 
 }  // namespace arr

@@ -27,21 +27,26 @@ namespace arr {
 
 namespace {
 
-// h[c] = sum_i V[c][i] w[i], c < j (V: j contiguous vectors of length n),
-// one workgroup per c, fixed-order tree reduction.
-__global__ __launch_bounds__(256) void k_dots(int64_t n, const double *__restrict__ V, const double *__restrict__ w,
-                                              double *__restrict__ h) {
+// Partial dot products of the Lanczos reorthogonalization:
+// part[r * nvec + c] = sum over rows of chunk r of V[c][i] w[i] (V: nvec
+// contiguous vectors of length n). Summed per c in a fixed order afterwards.
+constexpr int kDotChunks = 128;
+__global__ __launch_bounds__(256) void k_dots_partial(int64_t n, const double *__restrict__ V, int nvec,
+                                                      const double *__restrict__ w, int64_t chunk,
+                                                      double *__restrict__ part) {
   __shared__ double red[256];
-  const double *v = V + (int64_t)blockIdx.x * n;
+  const int c = blockIdx.y, r = blockIdx.x;
+  const double *v = V + (int64_t)c * n;
+  const int64_t i0 = (int64_t)r * chunk, i1 = min(n, i0 + chunk);
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(v[i], w[i], s);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s = fma(v[i], w[i], s);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) h[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[(int64_t)r * nvec + c] = red[0];
 }
 
 // w[i] -= sum_{c<j} V[c][i] h[c]
@@ -61,6 +66,14 @@ __global__ __launch_bounds__(256) void k_scale_vec(int64_t n, const double *__re
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+
+// h[c] = V[c] . w for c < nvec, deterministic; part >= kDotChunks * nvec doubles.
+void multi_dot(int64_t n, const double *V, int nvec, const double *w, double *part, double *h, hipStream_t s) {
+  const int64_t chunk = (n + kDotChunks - 1) / kDotChunks;
+  hipLaunchKernelGGL(k_dots_partial, dim3(kDotChunks, nvec), dim3(256), 0, s, n, V, nvec, w, chunk, part);
+  ARR_HIP(hipGetLastError());
+  launch_reduce_groups(part, kDotChunks, nvec, h, false, s);
+}
 
 }  // namespace
 
@@ -160,11 +173,12 @@ void Solver::set_initial_block(const double *X0, int64_t ld) {
 void Solver::setup_interval() {
   const int64_t n = n_;
   const int L = (int)std::min<int64_t>(o_.lanczos_steps, n);
-  DevBuf V(sizeof(double) * n * L), wv(sizeof(double) * n), h(sizeof(double) * (L + 4));
-  double *Vp = V.as<double>(), *w = wv.as<double>(), *hp = h.as<double>();
+  DevBuf V(sizeof(double) * n * L), wv(sizeof(double) * n), h(sizeof(double) * (L + 4)),
+      part(sizeof(double) * kDotChunks * (L + 1));
+  double *Vp = V.as<double>(), *w = wv.as<double>(), *hp = h.as<double>(), *pp = part.as<double>();
   // v_0 = X0[:, 0] / |X0[:, 0]|
   launch_copy<double>(n, 1, w, 1, B64_.Zb.as<double>(), B64_.ldz, s_);
-  hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s_, n, w, w, hp);
+  multi_dot(n, w, 1, w, pp, hp, s_);
   hipLaunchKernelGGL(k_scale_vec, dim3(blocks_for(n)), dim3(256), 0, s_, n, w, hp, Vp);
   ARR_HIP(hipGetLastError());
   std::vector<double> alpha, beta;
@@ -174,11 +188,11 @@ void Solver::setup_interval() {
     // full reorthogonalization, twice; the first pass also yields alpha_j
     double aj = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(256), 0, s_, n, Vp, w, hp);
+      multi_dot(n, Vp, j + 1, w, pp, hp, s_);
       if (pass == 0) ARR_HIP(hipMemcpyAsync(&aj, hp + j, sizeof(double), hipMemcpyDeviceToHost, s_));
       hipLaunchKernelGGL(k_sub_combination, dim3(blocks_for(n)), dim3(256), 0, s_, n, j + 1, Vp, hp, w);
     }
-    hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s_, n, w, w, hp + L);
+    multi_dot(n, w, 1, w, pp, hp + L, s_);
     ARR_HIP(hipGetLastError());
     double b2 = 0.0;
     ARR_HIP(hipMemcpyAsync(&b2, hp + L, sizeof(double), hipMemcpyDeviceToHost, s_));

@@ -31,7 +31,7 @@ void Work::ensure_gram(int64_t n, int mx, int my) {
 
 void Work::ensure_small(int m) {
   const size_t per = (size_t)m * m;
-  small.ensure(sizeof(double) * std::max<size_t>(1, 6 * per + 64));
+  small.ensure(sizeof(double) * std::max<size_t>(1, 6 * per + 128));
   if (!info.p) info.alloc(256);
 }
 
@@ -94,7 +94,7 @@ double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s) {
   wk.ensure_small(w);
   double *G = wk.small.as<double>();
   double *work = G + (size_t)w * w;
-  double *rc = work + 3 * (size_t)w * w;
+  double *rc = work + 5 * (size_t)w * w;
   launch_gram<T>(n, X, X, G, wk.gramw.as<double>(), true, s);
   rcond_device(w, G, work, wk.info.as<int>(), rc, s);
   double h = 0.0;
@@ -112,6 +112,7 @@ static int cholqr_pass(int64_t n, Blk<const T> Z, Blk<T> Zout, double shift_rel,
   double *G = wk.small.as<double>();
   double *Wt = G + (size_t)m * m;
   double *nrm = Wt + (size_t)m * m;  // 2 doubles
+  double *scratch = nrm + 64;        // 2 m^2 doubles
   launch_gram<T>(n, Z, Z, G, wk.gramw.as<double>(), true, s);
   double shift = 0.0;
   if (shift_rel > 0.0) {
@@ -127,8 +128,8 @@ static int cholqr_pass(int64_t n, Blk<const T> Z, Blk<T> Zout, double shift_rel,
   ARR_HIP(hipMemcpyAsync(&info, wk.info.as<int>(), sizeof(int), hipMemcpyDeviceToHost, s));
   ARR_HIP(hipStreamSynchronize(s));
   if (info) return info;
-  launch_tri_inv_t(m, G, m, Wt, m, s);
-  launch_update<T>(n, Z, Wt, m, m, 1.0, 0.0, Zout, s);
+  launch_tri_inv_t(m, G, m, Wt, m, scratch, s);
+  launch_update<T>(n, Z, Wt, m, m, 1.0, 0.0, Zout, s, true);
   return 0;
 }
 

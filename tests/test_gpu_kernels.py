@@ -159,6 +159,8 @@ def test_rcond_matches_oracle():
     rng = np.random.default_rng(5)
     X = rng.standard_normal((3001, 40))
     assert abs(arr.arr_rcond_gram(dev(X)) / O.rcond_gram(X) - 1) < 1e-10
+    Xw = rng.standard_normal((4001, 200)) * np.logspace(0, 3, 200)[None, :]
+    assert abs(arr.arr_rcond_gram(dev(Xw)) / O.rcond_gram(Xw) - 1) < 1e-8
     # ill conditioned: two nearly parallel columns
     Xi = X.copy()
     Xi[:, 1] = Xi[:, 0] + 1e-5 * Xi[:, 1]
@@ -170,10 +172,10 @@ def test_rcond_matches_oracle():
     assert arr.arr_rcond_gram(dev(Xs)) < 1e-14 and O.rcond_gram(Xs) < 1e-14
 
 
-@pytest.mark.parametrize("kind", ["random", "ill", "krylov"])
+@pytest.mark.parametrize("kind", ["random", "ill", "krylov", "wide"])
 def test_orthonormalize(kind):
     rng = np.random.default_rng(11)
-    n, m = 6007, 96
+    n, m = 6007, (300 if kind == "wide" else 96)
     Z = rng.standard_normal((n, m))
     if kind == "ill":
         Z[:, m // 2:] = Z[:, : m // 2] + 1e-7 * rng.standard_normal((n, m // 2))
