@@ -92,6 +92,7 @@ typedef struct {
   double mixed_switch;   /* ARR_MIXED: leave FP32 once maxres <= this (default 1e-4)       */
   int32_t verbose;       /* 1: one line per outer iteration on stderr                      */
   int32_t timing;        /* 1: time filter SpMM launches with HIP events (stats)           */
+  int32_t keep_vectors;  /* served requests: keep eigenvectors on the host (default 1)    */
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -162,6 +163,43 @@ int arr_get_stats(arr_handle_t h, arr_stats_t *s);
 const char *arr_last_error(arr_handle_t h);
 const char *arr_last_global_error(void);
 void arr_destroy(arr_handle_t h);
+
+/* ---- serving: continuous batching of many solves on one GPU -------------
+ *
+ * A server owns a device arena of hbm_budget_bytes. Submitted requests (each a
+ * handle made by arr_create / arr_create_ex, not yet solved) wait in a FIFO
+ * queue; the head is admitted as soon as fewer than max_slots requests run and
+ * a contiguous block of its footprint (arr_footprint) is free in the arena.
+ * An admitted request runs Algorithm 8 with all its state resident in its
+ * block, on its own stream, concurrently with the other admitted requests;
+ * when it finishes its results are copied to host memory (eigenvalues and
+ * residuals always, eigenvectors if keep_vectors) and its block is returned.
+ * The caller keeps ownership of the handle and must not use or destroy it
+ * until arr_wait (or arr_poll) reports the request done; arr_get_eigpairs and
+ * arr_get_stats then work as after arr_solve. A request's results do not
+ * depend on which other requests ran beside it. */
+typedef struct arr_server *arr_server_t;
+typedef struct {
+  uint64_t hbm_budget_bytes; /* device arena; 0 -> 80% of the free device memory */
+  int32_t max_slots;         /* requests solved concurrently; 0 -> 4             */
+  int32_t device;            /* HIP device ordinal                               */
+} arr_server_opts_t;
+
+void arr_server_opts_default(arr_server_opts_t *o);
+int arr_server_create(const arr_server_opts_t *o, arr_server_t *out);
+/* Device bytes a solve of h reserves (matrix, blocks, work). */
+int arr_footprint(arr_handle_t h, uint64_t *bytes);
+/* Queue h; non-blocking. ARR_ENOMEM if its footprint exceeds the budget. */
+int arr_submit(arr_server_t s, arr_handle_t h, uint64_t *ticket);
+/* *done = 1 once the request has finished (successfully or not). */
+int arr_poll(arr_server_t s, uint64_t ticket, int *done);
+/* Block until the request finishes; returns its arr_solve status. */
+int arr_wait(arr_server_t s, uint64_t ticket);
+/* Seconds since server creation at submission, admission and completion. */
+int arr_request_times(arr_server_t s, uint64_t ticket, double *t_submit, double *t_admit, double *t_done);
+/* Waits for the running requests; queued ones are cancelled (status
+ * ARR_ESTATE). */
+void arr_server_destroy(arr_server_t s);
 
 /* ---- step-level entry points (device pointers, for composing and testing
  * the steps of Algorithm 8). All run on `stream` (a hipStream_t, NULL for

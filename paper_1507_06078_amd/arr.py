@@ -51,7 +51,12 @@ class arr_options_t(ctypes.Structure):
                 ("maxit1", ctypes.c_int32), ("maxit2", ctypes.c_int32), ("tol1", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("paper_faithful", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("device", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("mixed_switch", ctypes.c_double), ("verbose", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("mixed_switch", ctypes.c_double), ("verbose", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("keep_vectors", ctypes.c_int32)]
+
+
+class arr_server_opts_t(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32)]
 
 
 class arr_stats_t(ctypes.Structure):
@@ -69,7 +74,9 @@ class arr_stats_t(ctypes.Structure):
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
            "arr_get_eigpairs", "arr_get_stats", "arr_last_error", "arr_last_global_error", "arr_destroy",
            "arr_filter_step", "arr_poly", "arr_filter_coefficients", "arr_gram", "arr_block_update",
-           "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr"]
+           "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
+           "arr_server_create", "arr_footprint", "arr_submit", "arr_poll", "arr_wait", "arr_request_times",
+           "arr_server_destroy"]
 
 _lib = None
 
@@ -108,8 +115,20 @@ def lib() -> ctypes.CDLL:
     L.arr_orthonormalize.argtypes = [i64, i32, vp, i64, vp]
     L.arr_syev.argtypes = [i32, vp, vp, vp, vp]
     L.arr_augmented_rr.argtypes = [P(arr_dev_csr_t), i64, vp, i64, i32, vp, i64, i32, vp, i64, vp, vp]
+    L.arr_server_opts_default.argtypes = [P(arr_server_opts_t)]
+    L.arr_server_opts_default.restype = None
+    L.arr_server_create.argtypes = [P(arr_server_opts_t), P(vp)]
+    L.arr_footprint.argtypes = [vp, P(ctypes.c_uint64)]
+    L.arr_submit.argtypes = [vp, vp, P(ctypes.c_uint64)]
+    L.arr_poll.argtypes = [vp, ctypes.c_uint64, P(ctypes.c_int)]
+    L.arr_wait.argtypes = [vp, ctypes.c_uint64]
+    L.arr_request_times.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
+    L.arr_server_destroy.argtypes = [vp]
+    L.arr_server_destroy.restype = None
+    void_fns = ("arr_options_default", "arr_destroy", "arr_last_error", "arr_last_global_error",
+                "arr_server_opts_default", "arr_server_destroy")
     for name in EXPORTS:
-        if name not in ("arr_options_default", "arr_destroy", "arr_last_error", "arr_last_global_error"):
+        if name not in void_fns:
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -189,6 +208,55 @@ def arr_get_stats(h: Handle) -> dict:
     s = arr_stats_t()
     _check(lib().arr_get_stats(h.ptr, ctypes.byref(s)), h.ptr)
     return {name: getattr(s, name) for name, _ in arr_stats_t._fields_}
+
+
+# ---- serving -------------------------------------------------------------------
+
+class Server:
+    """Owns an arr_server_t (continuous batching of solves on one GPU)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 4, device: int = 0):
+        o = arr_server_opts_t()
+        lib().arr_server_opts_default(ctypes.byref(o))
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.max_slots = int(max_slots)
+        o.device = int(device)
+        p = ctypes.c_void_p()
+        _check(lib().arr_server_create(ctypes.byref(o), ctypes.byref(p)))
+        self.ptr = p.value
+
+    def submit(self, h: Handle) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().arr_submit(self.ptr, h.ptr, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _check(lib().arr_poll(self.ptr, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> int:
+        return _check(lib().arr_wait(self.ptr, ctypes.c_uint64(ticket)))
+
+    def times(self, ticket: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().arr_request_times(self.ptr, ctypes.c_uint64(ticket), ctypes.addressof(a), ctypes.addressof(b),
+                                       ctypes.addressof(c)))
+        return a.value, b.value, c.value
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().arr_server_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        self.close()
+
+
+def arr_footprint(h: Handle) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().arr_footprint(h.ptr, ctypes.byref(b)), h.ptr)
+    return b.value
 
 
 def arr_filter_coefficients(d: int) -> np.ndarray:

@@ -4,11 +4,15 @@
 #include <cstring>
 #include <memory>
 
-#include "solver.h"
+#include "server.h"
 
 struct arr_solver {
   std::unique_ptr<arr::Solver> s;
   std::string err;
+};
+
+struct arr_server {
+  std::unique_ptr<arr::Server> s;
 };
 
 namespace {
@@ -64,6 +68,9 @@ void arr_options_default(arr_options_t *o) {
   o->device = 0;
   o->seed = 2;
   o->mixed_switch = 1e-4;
+  o->verbose = 0;
+  o->timing = 0;
+  o->keep_vectors = 1;
 }
 
 int arr_create_ex(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,
@@ -122,6 +129,77 @@ const char *arr_last_error(arr_handle_t h) { return h ? h->err.c_str() : g_err.c
 const char *arr_last_global_error(void) { return g_err.c_str(); }
 
 void arr_destroy(arr_handle_t h) { delete h; }
+
+// ---- serving -------------------------------------------------------------------
+
+void arr_server_opts_default(arr_server_opts_t *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->hbm_budget_bytes = 0;
+  o->max_slots = 4;
+  o->device = 0;
+}
+
+int arr_server_create(const arr_server_opts_t *o, arr_server_t *out) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    arr_server_opts_t d;
+    if (o)
+      d = *o;
+    else
+      arr_server_opts_default(&d);
+    ARR_REQUIRE(d.max_slots >= 0, "max_slots must be >= 0");
+    auto s = std::make_unique<arr_server>();
+    s->s = std::make_unique<arr::Server>(d);
+    *out = s.release();
+    return ARR_OK;
+  });
+}
+
+int arr_footprint(arr_handle_t h, uint64_t *bytes) {
+  if (!h || !bytes) return ARR_EINVAL;
+  return guarded(&h->err, [&]() {
+    *bytes = h->s->footprint();
+    return ARR_OK;
+  });
+}
+
+int arr_submit(arr_server_t s, arr_handle_t h, uint64_t *ticket) {
+  if (!s || !h || !ticket) return ARR_EINVAL;
+  return guarded(nullptr, [&]() {
+    *ticket = s->s->submit(h->s.get());
+    return ARR_OK;
+  });
+}
+
+int arr_poll(arr_server_t s, uint64_t ticket, int *done) {
+  if (!s || !done) return ARR_EINVAL;
+  return guarded(nullptr, [&]() {
+    *done = s->s->poll(ticket, nullptr) ? 1 : 0;
+    return ARR_OK;
+  });
+}
+
+int arr_wait(arr_server_t s, uint64_t ticket) {
+  if (!s) return ARR_EINVAL;
+  return guarded(nullptr, [&]() {
+    std::string e;
+    const int st = s->s->wait(ticket, &e);
+    if (st < 0) throw arr::Error(st, e.empty() ? std::string("request failed") : e);
+    return st;
+  });
+}
+
+int arr_request_times(arr_server_t s, uint64_t ticket, double *t_submit, double *t_admit, double *t_done) {
+  if (!s) return ARR_EINVAL;
+  return guarded(nullptr, [&]() {
+    s->s->times(ticket, t_submit, t_admit, t_done);
+    return ARR_OK;
+  });
+}
+
+void arr_server_destroy(arr_server_t s) { delete s; }
 
 // ---- step-level entry points ----------------------------------------------
 

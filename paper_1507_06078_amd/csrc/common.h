@@ -51,23 +51,53 @@ struct Blk {
   Blk cols(int c0, int wc) const { return Blk{p + c0, ld, wc}; }
 };
 
-// Owned device allocation.
+// Bump allocator over one pre-reserved device block. While a pool is
+// installed for the calling thread (see device_pool()), every DevBuf
+// allocation of that thread is carved from it and never returned
+// individually: the whole block goes back at once when its owner is done.
+struct Pool {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  void *take(size_t b) {
+    b = (b + 255) / 256 * 256;
+    if (used + b > cap)
+      throw Error(-2, "device pool exhausted: need " + std::to_string(used + b) + " of " + std::to_string(cap) +
+                          " reserved bytes");
+    void *p = base + used;
+    used += b;
+    return p;
+  }
+};
+Pool *&device_pool();
+
+// Owned device allocation (hipMalloc, or a slice of the thread's pool).
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  bool pooled = false;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), pooled(o.pooled) { o.p = nullptr; o.bytes = 0; }
   DevBuf &operator=(DevBuf &&o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; pooled = o.pooled;
+      o.p = nullptr; o.bytes = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t b) {
     release();
     if (b == 0) return;
+    if (Pool *pool = device_pool()) {
+      p = pool->take(b);
+      bytes = b;
+      pooled = true;
+      return;
+    }
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) {
       p = nullptr;
@@ -75,12 +105,14 @@ struct DevBuf {
       throw Error(-2, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
     }
     bytes = b;
+    pooled = false;
   }
   void ensure(size_t b) { if (b > bytes) alloc(b); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !pooled) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    pooled = false;
   }
   template <typename T> T *as() const { return static_cast<T *>(p); }
 };
@@ -124,6 +156,8 @@ template <typename T>
 void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym,
                  hipStream_t s);
 size_t gram_work_doubles(int64_t n, int mx, int my);
+// Upper bound of gram_work_doubles over all mx, my <= m_max.
+size_t gram_work_bound(int64_t n, int m_max);
 // Y = beta*Y + alpha * X * W with W FP64 (m x c, ldw) on the device; w_upper:
 // W is upper triangular (its zero blocks are skipped). Y must not alias X.
 template <typename T>
@@ -188,6 +222,9 @@ struct Jacobi {
   DevBuf bufA, bufB, bufV, bufOff, bufEval;
   std::vector<double> h_eval;
   int mcap = 0;
+  // Device bytes of the buffers for matrices of order <= m, and allocation.
+  static size_t reserve_bytes(int m);
+  void reserve(int m);
   // H (m x m, row-major, ld = m) is read; on return the eigenvalues in
   // descending order are in evals_host (size m) and the matching unit
   // eigenvectors are the COLUMNS of V (m x m row-major, ld = m):

@@ -648,20 +648,34 @@ void rcond_device(int m, const double *G, double *work, int *info, double *rc, h
   ARR_HIP(hipGetLastError());
 }
 
+static size_t jac_pad(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t Jacobi::reserve_bytes(int m) {
+  const size_t me = (size_t)(std::max(m, 1) + kBJ2 - 1) / kBJ2 * kBJ2;
+  const size_t np = me / kBJ / 2;
+  return 3 * jac_pad(sizeof(double) * me * me) + jac_pad(sizeof(double) * 4 + sizeof(int) * 4 + sizeof(int) * me) +
+         jac_pad(sizeof(double) * (me + np * kBJ2 * kBJ2));
+}
+
+void Jacobi::reserve(int m) {
+  const int me = (std::max(m, 1) + kBJ2 - 1) / kBJ2 * kBJ2;
+  if (me <= mcap) return;
+  const int np = me / kBJ / 2;
+  bufA.alloc(sizeof(double) * me * me);
+  bufB.alloc(sizeof(double) * me * me);
+  bufV.alloc(sizeof(double) * me * me);
+  bufOff.alloc(sizeof(double) * 4 + sizeof(int) * 4 + sizeof(int) * me);
+  bufEval.alloc(sizeof(double) * (me + (size_t)np * kBJ2 * kBJ2));
+  mcap = me;
+}
+
 void Jacobi::solve(int m, const double *H, double *V, std::vector<double> &evals_host, hipStream_t s,
                    int *sweeps_out) {
   evals_host.assign(m, 0.0);
   if (m == 0) return;
   const int me = (m + kBJ2 - 1) / kBJ2 * kBJ2;  // padded with decoupled zero rows/columns
   const int nb = me / kBJ, np = nb / 2;
-  if (me > mcap) {
-    bufA.alloc(sizeof(double) * me * me);
-    bufB.alloc(sizeof(double) * me * me);
-    bufV.alloc(sizeof(double) * me * me);
-    bufOff.alloc(sizeof(double) * 4 + sizeof(int) * 4 + sizeof(int) * me);
-    bufEval.alloc(sizeof(double) * (me + (size_t)np * kBJ2 * kBJ2));
-    mcap = me;
-  }
+  reserve(m);
   double *A = bufA.as<double>(), *B = bufB.as<double>(), *VT = bufV.as<double>();
   double *Rbuf = bufEval.as<double>() + me;
   double *nrm = bufOff.as<double>();

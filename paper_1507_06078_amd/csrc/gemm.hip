@@ -47,9 +47,6 @@ GramPlan gram_plan(int64_t n, int mx, int my, bool sym) {
   int64_t want = std::max<int64_t>(1, (2048 + p.ntiles - 1) / p.ntiles);
   // at least 256 rows per split so each wave streams a useful amount
   want = std::min<int64_t>(want, std::max<int64_t>(1, n / 256));
-  // bound the partial buffer to ~64M doubles
-  const int64_t cap = std::max<int64_t>(1, (int64_t)(64ll << 20) / std::max<int64_t>(1, (int64_t)mx * my));
-  want = std::min<int64_t>(want, cap);
   p.nsplit = (int)want;
   p.chunk = round_up((n + p.nsplit - 1) / p.nsplit, 16);
   if (p.chunk == 0) p.chunk = 16;
@@ -250,6 +247,16 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
 }
 
 }  // namespace
+
+size_t gram_work_bound(int64_t n, int m_max) {
+  // nsplit <= ceil(2048 / ntiles) and mx * my <= 4096 * tx * ty, so the partial
+  // tiles of any product with mx, my <= m_max fit in (4096 + t^2) 64 x 64
+  // tiles; nsplit is also at most max(1, n / 256).
+  const size_t t = (size_t)(m_max + 63) / 64;
+  const size_t by_tiles = (4096 + t * t) * 4096;
+  const size_t by_rows = (size_t)std::max<int64_t>(1, n / 256) * t * t * 4096;
+  return std::min(by_tiles, by_rows);
+}
 
 size_t gram_work_doubles(int64_t n, int mx, int my) {
   const GramPlan p = gram_plan(n, mx, my, false);

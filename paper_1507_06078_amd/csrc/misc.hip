@@ -155,6 +155,11 @@ void colsumsq_nj(int64_t n, Blk<const T> P, Blk<const T> Q, const double *mu, do
 
 }  // namespace
 
+Pool *&device_pool() {
+  static thread_local Pool *p = nullptr;
+  return p;
+}
+
 template <typename T>
 int launch_colsumsq(int64_t n, Blk<const T> P, Blk<const T> Q, const double *mu, double *partial, hipStream_t s) {
   const int w = P.w;

@@ -1,0 +1,217 @@
+// Serving loop: continuous batching of eigensolve requests on one GPU.
+//
+//  * Admission by device footprint: the server owns one device arena (the
+//    HBM budget, allocated once). A queued request is admitted, in strict
+//    FIFO order, as soon as a solve slot is free and a contiguous arena block
+//    of its exact footprint (Solver::footprint(): blocks, matrix, work) can be
+//    carved out. Inside its block the request's solver bump-allocates (a
+//    per-thread Pool), so no hipMalloc/hipFree -- which would synchronize the
+//    whole device -- runs while other requests compute.
+//  * Device-resident state: an admitted request keeps its CSR, iterate,
+//    Krylov blocks and Ritz state in its block until it finishes; its results
+//    are then copied to host memory and the block returns to the arena.
+//  * Overlap: every admitted request runs its Algorithm 8 state machine in a
+//    worker thread on its own HIP stream, so the kernels of different
+//    requests execute concurrently; requests that arrive while others run join
+//    as soon as a slot and memory free up.
+//  * Determinism: no kernel uses atomics in a reduction, so a request's
+//    result does not depend on what else is running.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "server.h"
+
+namespace arr {
+
+bool Arena::alloc(size_t bytes, size_t &off) {
+  bytes = (bytes + 255) / 256 * 256;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= bytes) {
+      off = it->first;
+      const size_t rest = it->second - bytes;
+      free_.erase(it);
+      if (rest) free_[off + bytes] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void Arena::release(size_t off, size_t bytes) {
+  bytes = (bytes + 255) / 256 * 256;
+  auto it = free_.emplace(off, bytes).first;
+  auto next = std::next(it);
+  if (next != free_.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    free_.erase(next);
+  }
+  if (it != free_.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      free_.erase(it);
+    }
+  }
+}
+
+size_t Arena::largest_free() const {
+  size_t b = 0;
+  for (auto &kv : free_) b = std::max(b, kv.second);
+  return b;
+}
+
+Server::Server(const arr_server_opts_t &o) : o_(o) {
+  t0_ = std::chrono::steady_clock::now();
+  ARR_HIP(hipSetDevice(o.device));
+  size_t budget = o.hbm_budget_bytes;
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    ARR_HIP(hipMemGetInfo(&fr, &tot));
+    budget = fr / 10 * 8;
+  }
+  budget = budget / 256 * 256;
+  ARR_REQUIRE(budget > 0, "server: empty HBM budget");
+  arena_mem_.alloc(budget);
+  arena_.base = arena_mem_.as<char>();
+  arena_.cap = budget;
+  arena_.free_[0] = budget;
+  slots_ = o.max_slots > 0 ? o.max_slots : 4;
+  sched_ = std::thread([this] { schedule(); });
+}
+
+Server::~Server() {
+  {
+    std::unique_lock<std::mutex> lk(mu_);
+    stopping_ = true;
+    for (uint64_t id : queue_) {
+      Request &r = reqs_[id];
+      r.done = true;
+      r.status = ARR_ESTATE;
+      r.error = "cancelled: server destroyed before admission";
+    }
+    queue_.clear();
+    cv_.notify_all();
+  }
+  if (sched_.joinable()) sched_.join();
+  for (std::thread &t : workers_)
+    if (t.joinable()) t.join();
+}
+
+double Server::now() const {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+}
+
+uint64_t Server::submit(Solver *s) {
+  const size_t fp = s->footprint();
+  ARR_REQUIRE(s->device() == o_.device, "handle was created for another device");
+  if (fp > arena_.cap)
+    throw Error(-2, "request footprint " + std::to_string(fp) + " bytes exceeds the server budget " +
+                        std::to_string(arena_.cap));
+  std::unique_lock<std::mutex> lk(mu_);
+  ARR_REQUIRE(!stopping_, "server is shutting down");
+  const uint64_t id = next_id_++;
+  Request &r = reqs_[id];
+  r.solver = s;
+  r.bytes = fp;
+  r.t_submit = now();
+  queue_.push_back(id);
+  cv_.notify_all();
+  return id;
+}
+
+void Server::schedule() {
+  std::unique_lock<std::mutex> lk(mu_);
+  while (true) {
+    cv_.wait(lk, [&] { return stopping_ || (!queue_.empty() && active_ < slots_); });
+    if (stopping_) break;
+    Request &r = reqs_[queue_.front()];
+    size_t off = 0;
+    if (!arena_.alloc(r.bytes, off)) {
+      // strict FIFO: the head waits until a running request returns memory
+      cv_.wait(lk);
+      continue;
+    }
+    const uint64_t id = queue_.front();
+    queue_.pop_front();
+    r.off = off;
+    r.t_admit = now();
+    ++active_;
+    workers_.emplace_back([this, id] { work(id); });
+  }
+}
+
+void Server::work(uint64_t id) {
+  Solver *s;
+  size_t off, bytes;
+  {
+    std::unique_lock<std::mutex> lk(mu_);
+    Request &r = reqs_[id];
+    s = r.solver;
+    off = r.off;
+    bytes = r.bytes;
+  }
+  int status = 0;
+  std::string error;
+  Pool pool;
+  pool.base = arena_.base + off;
+  pool.cap = bytes;
+  try {
+    ARR_HIP(hipSetDevice(o_.device));
+    device_pool() = &pool;
+    s->ensure_device();
+    status = s->solve();
+    s->stash_results(s->keep_vectors());
+  } catch (const Error &e) {
+    status = e.code;
+    error = e.what();
+  } catch (const std::exception &e) {
+    status = ARR_EDEVICE;
+    error = e.what();
+  }
+  try {
+    s->release_device();
+  } catch (const std::exception &) {
+  }
+  device_pool() = nullptr;
+  std::unique_lock<std::mutex> lk(mu_);
+  Request &r = reqs_[id];
+  arena_.release(off, bytes);
+  r.status = status;
+  r.error = error;
+  r.t_done = now();
+  r.done = true;
+  --active_;
+  cv_.notify_all();
+}
+
+bool Server::poll(uint64_t id, int *status) {
+  std::unique_lock<std::mutex> lk(mu_);
+  auto it = reqs_.find(id);
+  ARR_REQUIRE(it != reqs_.end(), "unknown ticket");
+  if (it->second.done && status) *status = it->second.status;
+  return it->second.done;
+}
+
+int Server::wait(uint64_t id, std::string *error) {
+  std::unique_lock<std::mutex> lk(mu_);
+  auto it = reqs_.find(id);
+  ARR_REQUIRE(it != reqs_.end(), "unknown ticket");
+  cv_.wait(lk, [&] { return it->second.done; });
+  if (error) *error = it->second.error;
+  return it->second.status;
+}
+
+void Server::times(uint64_t id, double *t_submit, double *t_admit, double *t_done) {
+  std::unique_lock<std::mutex> lk(mu_);
+  auto it = reqs_.find(id);
+  ARR_REQUIRE(it != reqs_.end(), "unknown ticket");
+  if (t_submit) *t_submit = it->second.t_submit;
+  if (t_admit) *t_admit = it->second.t_admit;
+  if (t_done) *t_done = it->second.t_done;
+}
+
+}  // namespace arr

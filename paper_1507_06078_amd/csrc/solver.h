@@ -43,14 +43,25 @@ struct Blocks {
 
 class Solver {
  public:
+  // Validates the problem and keeps a host copy of the matrix; device memory
+  // is allocated by ensure_device() (called by solve() when needed).
   Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, const arr_options_t &o);
   ~Solver();
   void set_initial_block(const double *X0, int64_t ld);
   int solve();
   void get(double *evals, double *evecs, int64_t ldv, double *resid);
+  // Device bytes ensure_device() allocates (every buffer of a solve).
+  size_t footprint() const { return const_cast<Solver *>(this)->device_plan(false); }
+  void ensure_device();
+  void release_device();
+  // Copy the results to host memory (eigenvectors only if keep_vectors) so that
+  // release_device() can return the device memory.
+  void stash_results(bool keep_vectors);
   arr_stats_t stats{};
   std::string err;
   bool solved = false;
+  int device() const { return o_.device; }
+  bool keep_vectors() const { return o_.keep_vectors != 0; }
 
  private:
   int64_t n_;
@@ -65,7 +76,14 @@ class Solver {
   Blocks<float> B32_;
   Work wk_;
   DevBuf desc_, mu_, outv_, x0_;
-  bool have_x0_ = false;
+  DevBuf lz_V_, lz_w_, lz_h_, lz_part_;  // Lanczos basis and scratch
+  bool have_x0_ = false, device_ready_ = false, host_results_ = false;
+  int64_t ldz_ = 0, ldq_ = 0;
+  int lanczos_L_ = 0;
+  std::vector<int64_t> h_rowptr_;
+  std::vector<int32_t> h_col_;
+  std::vector<double> h_val_, h_x0_, h_vecs_;
+  size_t device_plan(bool allocate);
   std::map<int, std::vector<double>> coef_;
 
   // iteration state (Algorithm 8)

@@ -113,36 +113,96 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
       ARR_REQUIRE(f != e && *f == i && csr->val[rp[c] + (f - b)] == csr->val[q], "matrix is not symmetric");
     }
   }
-  ARR_HIP(hipSetDevice(o.device));
-  ARR_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
-  const int64_t nnz = csr->nnz;
-  rowptr_.alloc(sizeof(int64_t) * (n + 1));
-  col_.alloc(sizeof(int32_t) * std::max<int64_t>(1, nnz));
-  val64_.alloc(sizeof(double) * std::max<int64_t>(1, nnz));
-  ARR_HIP(hipMemcpy(rowptr_.p, rp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
-  if (nnz) {
-    ARR_HIP(hipMemcpy(col_.p, csr->colind, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
-    std::vector<double> v(csr->val, csr->val + nnz);
-    if (which == ARR_SMALLEST_ALGEBRAIC)
-      for (double &x : v) x = -x;
-    ARR_HIP(hipMemcpy(val64_.p, v.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
-    if (o.precision == ARR_MIXED) {
-      std::vector<float> f(v.begin(), v.end());
-      val32_.alloc(sizeof(float) * nnz);
-      ARR_HIP(hipMemcpy(val32_.p, f.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
-    }
+  h_rowptr_.assign(rp, rp + n + 1);
+  h_col_.assign(csr->colind, csr->colind + csr->nnz);
+  h_val_.assign(csr->val, csr->val + csr->nnz);
+  if (which == ARR_SMALLEST_ALGEBRAIC)
+    for (double &x : h_val_) x = -x;
+  ldz_ = round_up((int64_t)std::max(o.p_max + 1, 2) * w_, 8);
+  ldq_ = round_up(w_, 8);
+  lanczos_L_ = (int)std::max<int64_t>(1, std::min<int64_t>(o.lanczos_steps, n));
+}
+
+// Every device buffer of a solve, in one place: with allocate = false the
+// padded byte count is returned (the footprint a server reserves).
+size_t Solver::device_plan(bool allocate) {
+  const int64_t n = n_, nnz = (int64_t)h_col_.size();
+  const bool mixed = o_.precision == ARR_MIXED;
+  size_t total = 0;
+  auto take = [&](DevBuf &b, size_t bytes) {
+    total += (bytes + 255) / 256 * 256;
+    if (allocate) b.alloc(bytes);
+  };
+  take(rowptr_, sizeof(int64_t) * (n + 1));
+  take(col_, sizeof(int32_t) * std::max<int64_t>(1, nnz));
+  take(val64_, sizeof(double) * std::max<int64_t>(1, nnz));
+  if (mixed) take(val32_, sizeof(float) * std::max<int64_t>(1, nnz));
+  for (DevBuf *b : {&B64_.Zb, &B64_.Ub, &B64_.Wb}) take(*b, sizeof(double) * n * ldz_);
+  for (DevBuf *b : {&B64_.Qb, &B64_.Q2b}) take(*b, sizeof(double) * n * ldq_);
+  if (mixed) {
+    for (DevBuf *b : {&B32_.Zb, &B32_.Ub, &B32_.Wb}) take(*b, sizeof(float) * n * ldz_);
+    for (DevBuf *b : {&B32_.Qb, &B32_.Q2b}) take(*b, sizeof(float) * n * ldq_);
   }
+  take(mu_, sizeof(double) * ldz_);
+  take(desc_, (sizeof(void *) + sizeof(int64_t) + sizeof(int32_t)) * (size_t)ldz_ + 64);
+  take(outv_, sizeof(double) * n * k_);
+  if (have_x0_) take(x0_, sizeof(double) * n * w_);
+  const int L = lanczos_L_;
+  take(lz_V_, sizeof(double) * n * L);
+  take(lz_w_, sizeof(double) * n);
+  take(lz_h_, sizeof(double) * (L + 4));
+  take(lz_part_, sizeof(double) * 128 * (L + 1));
+  const int m_small = (int)std::max<int64_t>(ldz_, L);
+  total += wk_.reserve(n, w_, (int)ldz_, m_small, !allocate);
+  return total;
+}
+
+void Solver::ensure_device() {
+  if (device_ready_) return;
+  ARR_HIP(hipSetDevice(o_.device));
+  if (!s_) ARR_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+  device_plan(true);
+  const int64_t n = n_, nnz = (int64_t)h_col_.size();
+  ARR_HIP(hipMemcpyAsync(rowptr_.p, h_rowptr_.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s_));
+  if (nnz) {
+    ARR_HIP(hipMemcpyAsync(col_.p, h_col_.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s_));
+    ARR_HIP(hipMemcpyAsync(val64_.p, h_val_.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, s_));
+    if (o_.precision == ARR_MIXED)
+      launch_convert<float, double>(nnz, 1, val32_.as<float>(), 1, val64_.as<double>(), 1, s_);
+  }
+  if (have_x0_)
+    ARR_HIP(hipMemcpyAsync(x0_.p, h_x0_.data(), sizeof(double) * n * w_, hipMemcpyHostToDevice, s_));
   A64_ = DevCSR<double>{n, nnz, rowptr_.as<int64_t>(), col_.as<int32_t>(), val64_.as<double>()};
-  if (o.precision == ARR_MIXED)
+  if (o_.precision == ARR_MIXED)
     A32_ = DevCSR<float>{n, nnz, rowptr_.as<int64_t>(), col_.as<int32_t>(), val32_.as<float>()};
-  const int64_t ldz = round_up((int64_t)std::max(o.p_max + 1, 2) * w_, 8);
-  const int64_t ldq = round_up(w_, 8);
-  B64_.alloc(n, ldz, ldq);
-  if (o.precision == ARR_MIXED) B32_.alloc(n, ldz, ldq);
-  mu_.alloc(sizeof(double) * ldz);
-  desc_.alloc((sizeof(void *) + sizeof(int64_t) + sizeof(int32_t)) * (size_t)ldz + 64);
-  outv_.alloc(sizeof(double) * n * k);
-  wk_.ensure_cols(n, (int)ldz);
+  B64_.ldz = ldz_;
+  B64_.ldq = ldq_;
+  B32_.ldz = ldz_;
+  B32_.ldq = ldq_;
+  ARR_HIP(hipStreamSynchronize(s_));
+  device_ready_ = true;
+}
+
+void Solver::release_device() {
+  if (s_) ARR_HIP(hipStreamSynchronize(s_));
+  for (DevBuf *b : {&rowptr_, &col_, &val64_, &val32_, &B64_.Zb, &B64_.Ub, &B64_.Wb, &B64_.Qb, &B64_.Q2b, &B32_.Zb,
+                    &B32_.Ub, &B32_.Wb, &B32_.Qb, &B32_.Q2b, &mu_, &desc_, &outv_, &x0_, &lz_V_, &lz_w_, &lz_h_,
+                    &lz_part_, &wk_.partial, &wk_.colv, &wk_.gramw, &wk_.small, &wk_.proj, &wk_.info, &wk_.jac.bufA,
+                    &wk_.jac.bufB, &wk_.jac.bufV, &wk_.jac.bufOff, &wk_.jac.bufEval})
+    b->release();
+  wk_.jac.mcap = 0;
+  device_ready_ = false;
+}
+
+void Solver::stash_results(bool keep_vectors) {
+  if (!solved) return;
+  if (keep_vectors) {
+    h_vecs_.resize((size_t)n_ * k_);
+    ARR_HIP(hipMemcpy(h_vecs_.data(), outv_.p, sizeof(double) * n_ * k_, hipMemcpyDeviceToHost));
+  } else {
+    h_vecs_.clear();
+  }
+  host_results_ = true;
 }
 
 Solver::~Solver() {
@@ -161,9 +221,9 @@ const std::vector<double> &Solver::coeffs(int d) {
 
 void Solver::set_initial_block(const double *X0, int64_t ld) {
   ARR_REQUIRE(X0 != nullptr && ld >= w_, "initial block: NULL or ld < w");
-  x0_.alloc(sizeof(double) * n_ * w_);
-  ARR_HIP(hipMemcpy2D(x0_.p, sizeof(double) * w_, X0, sizeof(double) * ld, sizeof(double) * w_, n_,
-                      hipMemcpyHostToDevice));
+  ARR_REQUIRE(!device_ready_, "arr_set_initial_block must precede the first arr_solve");
+  h_x0_.resize((size_t)n_ * w_);
+  for (int64_t i = 0; i < n_; ++i) std::copy(X0 + i * ld, X0 + i * ld + w_, h_x0_.begin() + i * w_);
   have_x0_ = true;
 }
 
@@ -172,10 +232,8 @@ void Solver::set_initial_block(const double *X0, int64_t ld) {
 // eigs), b = smallest Ritz value of the starting block.
 void Solver::setup_interval() {
   const int64_t n = n_;
-  const int L = (int)std::min<int64_t>(o_.lanczos_steps, n);
-  DevBuf V(sizeof(double) * n * L), wv(sizeof(double) * n), h(sizeof(double) * (L + 4)),
-      part(sizeof(double) * kDotChunks * (L + 1));
-  double *Vp = V.as<double>(), *w = wv.as<double>(), *hp = h.as<double>(), *pp = part.as<double>();
+  const int L = lanczos_L_;
+  double *Vp = lz_V_.as<double>(), *w = lz_w_.as<double>(), *hp = lz_h_.as<double>(), *pp = lz_part_.as<double>();
   // v_0 = X0[:, 0] / |X0[:, 0]|
   launch_copy<double>(n, 1, w, 1, B64_.Zb.as<double>(), B64_.ldz, s_);
   multi_dot(n, w, 1, w, pp, hp, s_);
@@ -498,6 +556,8 @@ int Solver::solve() {
   stats = arr_stats_t{};
   solved = false;
   ARR_HIP(hipSetDevice(o_.device));
+  ensure_device();
+  host_results_ = false;
   SpmmTimer timer;
   struct Install {
     SpmmTimer *prev;
@@ -573,8 +633,13 @@ void Solver::get(double *evals, double *evecs, int64_t ldv, double *resid) {
   if (resid) std::copy(out_res_.begin(), out_res_.end(), resid);
   if (evecs) {
     ARR_REQUIRE(ldv >= k, "ldv must be >= k");
-    ARR_HIP(hipMemcpy2D(evecs, sizeof(double) * ldv, outv_.p, sizeof(double) * k, sizeof(double) * k, n_,
-                        hipMemcpyDeviceToHost));
+    if (host_results_) {
+      ARR_REQUIRE(!h_vecs_.empty(), "eigenvectors were not kept for this served request (keep_vectors = 0)");
+      for (int64_t i = 0; i < n_; ++i) std::copy(&h_vecs_[i * k], &h_vecs_[i * k] + k, evecs + i * ldv);
+    } else {
+      ARR_HIP(hipMemcpy2D(evecs, sizeof(double) * ldv, outv_.p, sizeof(double) * k, sizeof(double) * k, n_,
+                          hipMemcpyDeviceToHost));
+    }
     // sign convention: the entry of largest magnitude is positive
     for (int c = 0; c < k; ++c) {
       double best = -1.0, sgn = 1.0;

@@ -18,6 +18,11 @@ struct Work {
   Jacobi jac;
   int groups = 0;
   int last_sweeps = 0;
+  // Size every buffer for products of width <= m_max, blocks of width <= w
+  // (deflation projections) and small matrices of order <= m_small, so that a
+  // solve never allocates afterwards. Returns the bytes allocated (or, with
+  // count_only, the bytes it would allocate).
+  size_t reserve(int64_t n, int w, int m_max, int m_small, bool count_only);
   void ensure_cols(int64_t n, int w);
   void ensure_gram(int64_t n, int mx, int my);
   void ensure_small(int m);

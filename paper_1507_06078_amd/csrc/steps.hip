@@ -17,6 +17,29 @@
 
 namespace arr {
 
+static size_t pad256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t Work::reserve(int64_t n, int w, int m_max, int m_small, bool count_only) {
+  const size_t b_partial = sizeof(double) * (size_t)spmm_groups(n) * (size_t)std::max(m_max, 1);
+  const size_t b_colv = sizeof(double) * (size_t)std::max(m_max, 1);
+  const size_t b_gram = sizeof(double) * gram_work_bound(n, m_max);
+  const size_t b_small = sizeof(double) * (6 * (size_t)m_small * m_small + 128);
+  const size_t b_proj = sizeof(double) * (size_t)std::max(w, 1) * (size_t)std::max(m_max, 1);
+  const size_t b_info = 256;
+  const size_t b_jac = jac.reserve_bytes(m_small);
+  if (count_only)
+    return pad256(b_partial) + pad256(b_colv) + pad256(b_gram) + pad256(b_small) + pad256(b_proj) + pad256(b_info) +
+           b_jac;
+  partial.ensure(b_partial);
+  colv.ensure(b_colv);
+  gramw.ensure(b_gram);
+  small.ensure(b_small);
+  proj.ensure(b_proj);
+  info.ensure(b_info);
+  this->jac.reserve(m_small);
+  return 0;
+}
+
 void Work::ensure_cols(int64_t n, int w) {
   const size_t need = (size_t)spmm_groups(n) * (size_t)std::max(w, 1);
   partial.ensure(sizeof(double) * need);

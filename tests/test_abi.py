@@ -79,3 +79,24 @@ def test_create_rejects_invalid_input_on_host():
     _bad(lambda r, c, v: None, n=63)
     # (p_max + 1) w < n fails: n = 64, k = 60
     _bad(lambda r, c, v: None, k=60)
+
+
+def test_footprint_is_host_arithmetic():
+    """arr_create validates and copies on the host only; the footprint a server
+    reserves covers the FP64 blocks Z, U, W (n x ldz), Qc and its double
+    buffer (n x ldq), the matrix, the output block and the Lanczos basis."""
+    A = W.laplacian_2d(40)
+    o = arr.arr_options_default()
+    o.w = 30
+    h = arr.arr_create(A, A.n, 20, arr.SMALLEST, 1e-10, o)
+    fp = arr.arr_footprint(h)
+    n, ldz, ldq = A.n, 120, 32
+    blocks = 8 * n * (3 * ldz + 2 * ldq)
+    lanczos = 8 * n * 100
+    assert fp >= blocks + lanczos + 12 * A.nnz + 8 * n * 20
+    assert fp < 4 * (blocks + lanczos) + 300e6   # bounded work buffers on top
+    o.precision = arr.MIXED
+    h2 = arr.arr_create(A, A.n, 20, arr.SMALLEST, 1e-10, o)
+    assert arr.arr_footprint(h2) >= fp + 4 * n * (3 * ldz + 2 * ldq)
+    h.close()
+    h2.close()
