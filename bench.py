@@ -57,6 +57,94 @@ def cpu_baseline(A, k, w, spmm_cols_per_solve, a, b):
             "seconds_measured": dt}
 
 
+def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slots=8, budget=0, verbose=False):
+    """Served workload: Poisson arrivals (exponential gaps, mean 1/rate); each
+    request is a 2D or 3D (prob. 1/2) Laplacian plus a U[0,1) potential with n
+    log-uniform in n_range (n = m^2 or m^3), k ~ U{10..200}, block
+    k + max(10, round(0.2 k)), tol 1e-8 or 1e-10 (prob. 1/2), k smallest,
+    mixed precision. Matrix i uses seed 1000 + i, its starting block seed
+    2000 + i. Returns latency/throughput figures of the server."""
+    import numpy as np
+    from paper_1507_06078_amd import arr, workloads as W
+
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    specs = []
+    for i in range(n_requests):
+        n_target = float(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
+        dim3 = rng.random() < 0.5
+        k = int(rng.integers(10, 201))
+        tol = 1e-8 if rng.random() < 0.5 else 1e-10
+        specs.append((n_target, dim3, k, tol))
+    handles, ks, tols, ns = [], [], [], []
+    t_build = time.perf_counter()
+    for i, (n_target, dim3, k, tol) in enumerate(specs):
+        if dim3:
+            A = W.laplacian_3d(max(3, int(round(n_target ** (1 / 3)))), potential_seed=1000 + i)
+        else:
+            A = W.laplacian_2d_potential(max(3, int(round(n_target ** 0.5))), potential_seed=1000 + i)
+        w = k + max(10, int(round(0.2 * k)))
+        o = arr.arr_options_default()
+        o.w = w
+        o.precision = arr.MIXED
+        o.seed = 2000 + i
+        o.keep_vectors = 0
+        handles.append(arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o))
+        ks.append(k)
+        tols.append(tol)
+        ns.append(A.n)
+    t_build = time.perf_counter() - t_build
+    if verbose:
+        print(f"[serve] built {n_requests} requests in {t_build:.1f} s", file=sys.stderr, flush=True)
+    srv = arr.Server(hbm_budget_bytes=budget, max_slots=max_slots)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for i, h in enumerate(handles):
+            delay = arrivals[i] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(h))
+        status = []
+        for i, t in enumerate(tickets):
+            try:
+                status.append(srv.wait(t))
+            except arr.ArrError as e:
+                print(f"[serve] request {i} failed: {e}", file=sys.stderr, flush=True)
+                status.append(e.code)
+            if verbose and (i + 1) % 16 == 0:
+                print(f"[serve] {i + 1}/{n_requests} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+        makespan = time.perf_counter() - t0
+        times = np.array([srv.times(t) for t in tickets])
+    finally:
+        srv.close()  # waits for running requests before any handle is released
+    lat = times[:, 2] - times[:, 0]
+    queue = times[:, 1] - times[:, 0]
+    res_ok = []
+    for i, h in enumerate(handles):
+        ok = status[i] >= 0
+        if ok:
+            _, _, r = arr.arr_get_eigpairs(h, ks[i], ns[i], vectors=False)
+            ok = bool(r.max() <= tols[i])
+        res_ok.append(ok)
+        h.close()
+    tight = np.array([t <= 1e-10 for t in tols])
+    conv = np.array([s == 0 for s in status]) & np.array(res_ok)
+    k_arr = np.array(ks)
+    return {
+        "requests": n_requests, "arrival_rate_per_s": rate, "max_slots": max_slots,
+        "makespan_s": makespan, "converged": int(conv.sum()),
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "queue_wait_p50_s": float(np.percentile(queue, 50)),
+        "requests_per_s": n_requests / makespan,
+        "eigenpairs_per_s": float(k_arr[conv].sum() / makespan),
+        "eigenpairs_per_s_tol1e-10": float(k_arr[conv & tight].sum() / makespan),
+        "n_median": float(np.median(ns)), "build_s": t_build,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +154,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--mixed-switch", type=float, default=None)
+    ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -77,6 +168,17 @@ def main():
     from paper_1507_06078_amd import arr, workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serve:
+        r = served_stream(n_requests=args.serve_requests, max_slots=args.serve_slots, verbose=args.verbose)
+        out = {"metric": "served p50/p99 latency", "value": r["latency_p50_s"], "unit": "s", "n_gpus": 1,
+               "steps": 1, "warmup": 0, "ms_per_step": r["makespan_s"] * 1e3, "higher_is_better": False,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+               "config": {"workload": f"served stream: {args.serve_requests} requests, Poisson 20/s, 2D/3D "
+                                      "Laplacian + U[0,1) potential, n log-uniform [1e4, 1e6], k U{10..200}, "
+                                      "tol 1e-8/1e-10, mixed precision"},
+               "serving": r}
+        print(json.dumps(out), flush=True)
+        return
     A = W.laplacian_3d(100, potential_seed=1)
     k, w, tol = 200, 240, 1e-10
     o = arr.arr_options_default()

@@ -228,6 +228,9 @@ class Server:
     def submit(self, h: Handle) -> int:
         t = ctypes.c_uint64()
         _check(lib().arr_submit(self.ptr, h.ptr, ctypes.byref(t)))
+        # keep the handle alive while the server may use it
+        self._held = getattr(self, "_held", [])
+        self._held.append(h)
         return t.value
 
     def poll(self, ticket: int) -> bool:

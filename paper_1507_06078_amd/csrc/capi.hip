@@ -128,7 +128,17 @@ int arr_get_stats(arr_handle_t h, arr_stats_t *s) {
 const char *arr_last_error(arr_handle_t h) { return h ? h->err.c_str() : g_err.c_str(); }
 const char *arr_last_global_error(void) { return g_err.c_str(); }
 
-void arr_destroy(arr_handle_t h) { delete h; }
+void arr_destroy(arr_handle_t h) {
+  if (!h) return;
+  // a request still held by a server must finish before its solver goes away
+  if (arr::Server *srv = h->s->server) {
+    try {
+      srv->wait(h->s->ticket, nullptr);
+    } catch (...) {
+    }
+  }
+  delete h;
+}
 
 // ---- serving -------------------------------------------------------------------
 

@@ -107,7 +107,14 @@ struct DevBuf {
     bytes = b;
     pooled = false;
   }
-  void ensure(size_t b) { if (b > bytes) alloc(b); }
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    // a pooled buffer is sized once from the request's footprint; growing it
+    // would take memory the request did not reserve
+    if (pooled) throw Error(-2, "pooled device buffer of " + std::to_string(bytes) + " bytes asked to grow to " +
+                                    std::to_string(b) + " (footprint under-estimate)");
+    alloc(b);
+  }
   void release() {
     if (p && !pooled) (void)hipFree(p);
     p = nullptr;

@@ -259,9 +259,11 @@ size_t gram_work_bound(int64_t n, int m_max) {
 }
 
 size_t gram_work_doubles(int64_t n, int mx, int my) {
+  // the symmetric plan applies to square products only (launch_gram requires it)
   const GramPlan p = gram_plan(n, mx, my, false);
-  const GramPlan q = gram_plan(n, mx, my, true);
-  return (size_t)std::max(p.nsplit, q.nsplit) * (size_t)mx * (size_t)my;
+  int nsplit = p.nsplit;
+  if (mx == my) nsplit = std::max(nsplit, gram_plan(n, mx, my, true).nsplit);
+  return (size_t)nsplit * (size_t)mx * (size_t)my;
 }
 
 template <typename T>

@@ -99,6 +99,9 @@ Server::~Server() {
   if (sched_.joinable()) sched_.join();
   for (std::thread &t : workers_)
     if (t.joinable()) t.join();
+  // the handles outlive the server: drop their back-references
+  for (auto &kv : reqs_)
+    if (kv.second.solver && kv.second.solver->server == this) kv.second.solver->server = nullptr;
 }
 
 double Server::now() const {
@@ -113,9 +116,16 @@ uint64_t Server::submit(Solver *s) {
                         std::to_string(arena_.cap));
   std::unique_lock<std::mutex> lk(mu_);
   ARR_REQUIRE(!stopping_, "server is shutting down");
+  if (s->server) {
+    ARR_REQUIRE(s->server == this, "handle is held by another server");
+    auto it = reqs_.find(s->ticket);
+    ARR_REQUIRE(it == reqs_.end() || it->second.done, "handle already has a request in flight");
+  }
   const uint64_t id = next_id_++;
   Request &r = reqs_[id];
   r.solver = s;
+  s->server = this;
+  s->ticket = id;
   r.bytes = fp;
   r.t_submit = now();
   queue_.push_back(id);

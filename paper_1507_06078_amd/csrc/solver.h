@@ -61,6 +61,10 @@ class Solver {
   std::string err;
   bool solved = false;
   int device() const { return o_.device; }
+  // Set while a server holds this solver (from submission until the server is
+  // destroyed); arr_destroy waits for the request before deleting the solver.
+  class Server *server = nullptr;
+  uint64_t ticket = 0;
   bool keep_vectors() const { return o_.keep_vectors != 0; }
 
  private:
