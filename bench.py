@@ -229,7 +229,7 @@ def main():
         "max_res": float(res.max()),
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_filter_spmm<{'double' if args.precision == 'fp64' else 'float'},"
+            "kernel": f"k_filter_spmm<{'double' if last['spmm_fp64'] else 'float'},"
                       f"{last['spmm_cols_per_lane']}>",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

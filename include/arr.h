@@ -122,6 +122,7 @@ typedef struct {
   double spmm_ms;
   double spmm_bytes;
   int32_t spmm_cols_per_lane; /* kernel variant: columns per lane (1, 2, 4, 8, 16) */
+  int32_t spmm_fp64;          /* data type of that variant: 1 FP64, 0 FP32 */
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;
@@ -228,13 +229,22 @@ int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shif
 int arr_filter_coefficients(int32_t d, double *out);
 
 /* Gram product G = X^T Y (FP64 result, device, mx x my row-major, ld my) of
- * device blocks X (n x mx, ldx) and Y (n x my, ldy) of dtype (0 FP64, 1 FP32),
- * accumulated in FP64 with a deterministic split reduction. Synchronous. */
+ * device blocks X (n x mx, ldx) and Y (n x my, ldy), accumulated in FP64 with
+ * a deterministic split reduction; when X == Y (same pointer, ld and width)
+ * only the upper triangle is formed and G is exactly symmetric. dtype: 0 FP64;
+ * 1 FP32 data with FP64 products and sums; 2 FP32 data on the FP32 matrix
+ * cores, each 32-row slice summed in FP32 (for well-conditioned products, as
+ * the Rayleigh quotient of the FP32 stage). Other dtype: ARR_EINVAL.
+ * Synchronous. */
 int arr_gram(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, const void *Y,
              int64_t ldy, int32_t my, double *G, void *stream);
 
 /* Block update Y = beta * Y + alpha * X W with X device n x m (ldx, dtype),
- * W device FP64 m x c row-major (ldw), Y device n x c (ldy, dtype). */
+ * W device FP64 m x c row-major (ldw), Y device n x c (ldy, dtype). dtype: 0
+ * FP64; 1 FP32 data with FP64 products and sums; 2 FP32 data with W rounded to
+ * FP32 on the FP32 matrix cores (for a well-conditioned W, as the Ritz
+ * rotation). Other dtype: ARR_EINVAL. Y must not alias X. Asynchronous on
+ * stream. */
 int arr_block_update(int32_t dtype, int64_t n, int32_t m, int32_t c, double alpha, const void *X,
                      int64_t ldx, const double *W, int64_t ldw, double beta, void *Y, int64_t ldy,
                      void *stream);

@@ -68,7 +68,7 @@ class arr_stats_t(ctypes.Structure):
                 ("maxres", ctypes.c_double), ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double),
                 ("t_filter", ctypes.c_double), ("t_arr", ctypes.c_double), ("t_dense", ctypes.c_double),
                 ("spmm_launches", ctypes.c_int64), ("spmm_ms", ctypes.c_double), ("spmm_bytes", ctypes.c_double),
-                ("spmm_cols_per_lane", ctypes.c_int32)]
+                ("spmm_cols_per_lane", ctypes.c_int32), ("spmm_fp64", ctypes.c_int32)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
@@ -318,13 +318,15 @@ def arr_poly(A: DeviceCSR, X, shift: float, lo: float, hi: float, gamma: np.ndar
                           float(hi), g.ctypes.data, len(g) - 1, _stream()))
 
 
-def arr_gram(X, Y, G):
-    _check(lib().arr_gram(_dtype_code(X), int(X.shape[0]), _ptr(X), _ld(X), int(X.shape[1]), _ptr(Y), _ld(Y),
+def arr_gram(X, Y, G, fp32_cores: bool = False):
+    code = 2 if (fp32_cores and _dtype_code(X) == 1) else _dtype_code(X)
+    _check(lib().arr_gram(code, int(X.shape[0]), _ptr(X), _ld(X), int(X.shape[1]), _ptr(Y), _ld(Y),
                           int(Y.shape[1]), _ptr(G), _stream()))
 
 
-def arr_block_update(X, W, Y, alpha: float = 1.0, beta: float = 0.0):
-    _check(lib().arr_block_update(_dtype_code(X), int(X.shape[0]), int(X.shape[1]), int(Y.shape[1]), float(alpha),
+def arr_block_update(X, W, Y, alpha: float = 1.0, beta: float = 0.0, fp32_cores: bool = False):
+    code = 2 if (fp32_cores and _dtype_code(X) == 1) else _dtype_code(X)
+    _check(lib().arr_block_update(code, int(X.shape[0]), int(X.shape[1]), int(Y.shape[1]), float(alpha),
                                   _ptr(X), _ld(X), _ptr(W), _ld(W), float(beta), _ptr(Y), _ld(Y), _stream()))
 
 

@@ -290,12 +290,14 @@ int arr_gram(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, c
     hipStream_t s = as_stream(stream);
     arr::DevBuf work(sizeof(double) * std::max<size_t>(1, arr::gram_work_doubles(n, mx, my)));
     const bool sym = (X == Y && ldx == ldy && mx == my);
+    ARR_REQUIRE(dtype >= 0 && dtype <= 2, "gram: dtype must be 0, 1 or 2");
     if (dtype == 0)
       arr::launch_gram<double>(n, arr::Blk<const double>{(const double *)X, ldx, mx},
                                arr::Blk<const double>{(const double *)Y, ldy, my}, G, work.as<double>(), sym, s);
     else
       arr::launch_gram<float>(n, arr::Blk<const float>{(const float *)X, ldx, mx},
-                              arr::Blk<const float>{(const float *)Y, ldy, my}, G, work.as<double>(), sym, s);
+                              arr::Blk<const float>{(const float *)Y, ldy, my}, G, work.as<double>(), sym, s,
+                              dtype == 2);
     ARR_HIP(hipStreamSynchronize(s));
     return ARR_OK;
   });
@@ -306,12 +308,13 @@ int arr_block_update(int32_t dtype, int64_t n, int32_t m, int32_t c, double alph
   return guarded(nullptr, [&]() {
     ARR_REQUIRE(X && W && Y && X != Y && m >= 0 && c >= 0 && ldx >= m && ldw >= c && ldy >= c, "block_update: bad arguments");
     hipStream_t s = as_stream(stream);
+    ARR_REQUIRE(dtype >= 0 && dtype <= 2, "block_update: dtype must be 0, 1 or 2");
     if (dtype == 0)
       arr::launch_update<double>(n, arr::Blk<const double>{(const double *)X, ldx, m}, W, ldw, c, alpha, beta,
                                  arr::Blk<double>{(double *)Y, ldy, c}, s);
     else
       arr::launch_update<float>(n, arr::Blk<const float>{(const float *)X, ldx, m}, W, ldw, c, alpha, beta,
-                                arr::Blk<float>{(float *)Y, ldy, c}, s);
+                                arr::Blk<float>{(float *)Y, ldy, c}, s, false, dtype == 2);
     return ARR_OK;
   });
 }

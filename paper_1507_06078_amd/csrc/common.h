@@ -139,8 +139,10 @@ struct SpmmTimer {
   struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
-  int64_t launches[5] = {0, 0, 0, 0, 0};
-  double ms[5] = {0, 0, 0, 0, 0}, bytes[5] = {0, 0, 0, 0, 0};
+  // launch class: columns-per-lane variant (0..4 for 1..16) + 5 for FP64 data
+  static constexpr int kClasses = 10;
+  int64_t launches[kClasses] = {};
+  double ms[kClasses] = {}, bytes[kClasses] = {};
   hipEvent_t get();
   void flush();  // waits for the recorded events and accumulates
   void reset();
@@ -157,19 +159,23 @@ void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s);
 // ---- launchers (gemm.hip) ----------------------------------------------------
 
 // G (FP64, mx x my, row-major, ld = my) = X^T Y with X n x mx and Y n x my.
-// `work` must hold gram_work_doubles(n, mx, my) doubles. If sym, X == Y is
-// assumed and only the upper triangle is computed, then mirrored.
+// `work` must hold gram_work_doubles(n, mx, my) doubles. If sym, X^T Y is
+// known to be symmetric (mx == my): only its upper triangle is computed, then
+// mirrored. fp32_cores (FP32 data only): FP32 matrix cores on 32-row slices,
+// for well-conditioned products; otherwise products and sums are FP64.
 template <typename T>
 void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym,
-                 hipStream_t s);
+                 hipStream_t s, bool fp32_cores = false);
 size_t gram_work_doubles(int64_t n, int mx, int my);
 // Upper bound of gram_work_doubles over all mx, my <= m_max.
 size_t gram_work_bound(int64_t n, int m_max);
 // Y = beta*Y + alpha * X * W with W FP64 (m x c, ldw) on the device; w_upper:
 // W is upper triangular (its zero blocks are skipped). Y must not alias X.
+// fp32_cores (FP32 data only): W rounded to FP32 and FP32 matrix cores, for a
+// well-conditioned W such as an orthogonal rotation.
 template <typename T>
 void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int c, double alpha,
-                   double beta, Blk<T> Y, hipStream_t s, bool w_upper = false);
+                   double beta, Blk<T> Y, hipStream_t s, bool w_upper = false, bool fp32_cores = false);
 
 // ---- launchers (misc.hip) ----------------------------------------------------
 
@@ -222,7 +228,6 @@ void small_gemm(int m1, int m2, int kk, double alpha, const double *A, int64_t s
 // max |diag| and Frobenius norm of a small matrix -> out[0], out[1]
 void launch_diag_max(int m, const double *A, int64_t lda, double *out, hipStream_t s);
 // Symmetrize: A = (A + A^T)/2
-void launch_symmetrize(int m, double *A, int64_t lda, hipStream_t s);
 
 // Parallel cyclic Jacobi eigensolver; see dense.hip.
 struct Jacobi {

@@ -314,17 +314,6 @@ __global__ __launch_bounds__(256) void k_rcond_final(int m, const double *G, con
   }
 }
 
-__global__ void k_symmetrize(int m, double *A, int64_t lda) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m * m) return;
-  const int i = (int)(idx / m), j = (int)(idx % m);
-  if (i < j) {
-    const double v = 0.5 * (A[(int64_t)i * lda + j] + A[(int64_t)j * lda + i]);
-    A[(int64_t)i * lda + j] = v;
-    A[(int64_t)j * lda + i] = v;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_diag_max(int m, const double *A, int64_t lda, double *out) {
   __shared__ double s1[256], s2[256];
   double mx = 0.0, fro = 0.0;
@@ -619,13 +608,6 @@ void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t
   const int64_t tot = (int64_t)m * m;
   hipLaunchKernelGGL(k_lower_to_upper_t, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, Li, (int64_t)m,
                      Winv, ldw);
-  ARR_HIP(hipGetLastError());
-}
-
-void launch_symmetrize(int m, double *A, int64_t lda, hipStream_t s) {
-  if (m == 0) return;
-  const int64_t tot = (int64_t)m * m;
-  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, A, lda);
   ARR_HIP(hipGetLastError());
 }
 

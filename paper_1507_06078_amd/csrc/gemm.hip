@@ -12,13 +12,15 @@
 //    and the W tile are staged through LDS; tiles of one row band run on the
 //    same XCD one after another so the band is read from HBM once.
 //
-// FP32 blocks (mixed precision) are widened to FP64 on load, so both products
-// accumulate in FP64.
+// FP32 blocks are widened exactly and use the FP64 matrix cores too, unless the
+// caller asks for the FP32 matrix cores for a well-conditioned product.
 //
-// MFMA 16x16x4 FP64 operand layout (lane l of 64): A[i][k] with i = l % 16,
-// k = l / 16; B[k][j] with k = l / 16, j = l % 16; result D[i][j] in element
-// r of lane l for i = l / 16 + 4 r, j = l % 16 (checked on gfx950).
+// MFMA 16x16x4 operand layout (lane l of 64): A[i][k] with i = l % 16,
+// k = l / 16; B[k][j] with k = l / 16, j = l % 16. Result D[i][j] in element
+// r of lane l with j = l % 16 and i = l / 16 + 4 r for FP64 but
+// i = 4 (l / 16) + r for FP32 (both checked on gfx950).
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -27,11 +29,15 @@ namespace arr {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kXcd = 8;
 
 __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 struct GramPlan {
@@ -54,10 +60,22 @@ GramPlan gram_plan(int64_t n, int mx, int my, bool sym) {
   return p;
 }
 
-template <typename T>
+// Gram tile kernel. A workgroup owns a 64 x 64 output tile and a chunk of
+// rows; the rows stream through double-buffered LDS 32 at a time (each thread
+// moves 8 consecutive elements of X and of Y per step), and wave q accumulates
+// the 32 x 32 quadrant (q & 1, q >> 1) on the matrix cores, so no reduction
+// across waves is needed. Products run on the FP64 matrix cores (FP32 data are
+// widened exactly), except in the kMma32 variant: FP32 matrix cores over each
+// 32-row step, added into the FP64 accumulator after every step. That variant
+// is for well-conditioned products only (a Rayleigh quotient of an
+// orthonormal basis), where an FP32 rounding of each slice's sum is harmless.
+constexpr int kRS = 32;
+
+template <typename T, bool kMma32>
 __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X, int64_t ldx, int mx,
                                               const T *__restrict__ Y, int64_t ldy, int my, int ntx, int nty,
                                               int ntiles, int sym, int64_t chunk, double *__restrict__ part) {
+  static_assert(!kMma32 || std::is_same<T, float>::value, "FP32 matrix cores need FP32 data");
   const int tile = blockIdx.x % ntiles;
   const int split = blockIdx.x / ntiles;
   int tx, ty;
@@ -70,87 +88,93 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X
     tx = tile / nty;
     ty = tile % nty;
   }
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
   const int cx = tx * 64, cy = ty * 64;
   const int64_t r0 = (int64_t)split * chunk;
   const int64_t r1 = min(n, r0 + chunk);
-
-  v4d acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int qx = (wv & 1) * 32, qy = (wv >> 1) * 32;
+  __shared__ T Xs[2][kRS][65], Ys[2][kRS][65];
+  constexpr int PER = kRS * 64 / 256;
+  const int lr = tid / (64 / PER), lc = (tid % (64 / PER)) * PER;
+  T xv[PER], yv[PER];
+  auto gload = [&](int64_t rb) {
+    const int64_t row = rb + lr;
+    const bool rok = row < r1;
 #pragma unroll
-  for (int f = 0; f < 4; ++f)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) acc[f][g] = v4d{0.0, 0.0, 0.0, 0.0};
-
-  bool okx[4], oky[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    okx[f] = cx + 16 * f + li < mx;
-    oky[f] = cy + 16 * f + li < my;
-  }
-  // software pipeline: the loads of the next 32-row step are in flight while
-  // the matrix cores consume the current one
-  double a[2][4], b[2][4];
-  auto load = [&](int64_t r, double (&la)[2][4], double (&lb)[2][4]) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t row = r + 16 * u + lk;
-      const bool rok = row < r1;
-      const T *xr = X + row * ldx + cx + li;
-      const T *yr = Y + row * ldy + cy + li;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        la[u][f] = (rok && okx[f]) ? (double)xr[16 * f] : 0.0;
-        lb[u][f] = (rok && oky[f]) ? (double)yr[16 * f] : 0.0;
-      }
+    for (int q = 0; q < PER; ++q) {
+      xv[q] = (rok && cx + lc + q < mx) ? X[row * ldx + cx + lc + q] : T(0);
+      yv[q] = (rok && cy + lc + q < my) ? Y[row * ldy + cy + lc + q] : T(0);
     }
   };
-  int64_t r = r0 + 4 * wv;
-  if (r < r1) load(r, a, b);
-  for (; r < r1; r += 32) {
-    double na[2][4], nb[2][4];
-    if (r + 32 < r1) load(r + 32, na, nb);
+  auto lstore = [&](int b) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int f = 0; f < 4; ++f)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) acc[f][g] = mfma16(a[u][f], b[u][g], acc[f][g]);
-    if (r + 32 < r1) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          a[u][f] = na[u][f];
-          b[u][f] = nb[u][f];
-        }
+    for (int q = 0; q < PER; ++q) {
+      Xs[b][lr][lc + q] = xv[q];
+      Ys[b][lr][lc + q] = yv[q];
     }
+  };
+  v4d acc[2][2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) acc[f][g] = v4d{0.0, 0.0, 0.0, 0.0};
+  int buf = 0;
+  if (r0 < r1) {
+    gload(r0);
+    lstore(0);
   }
-
-  __shared__ double red[64 * 64];
-  for (int q = 0; q < 4; ++q) {
-    if (wv == q) {
+  __syncthreads();
+  for (int64_t rb = r0; rb < r1; rb += kRS) {
+    const bool more = rb + kRS < r1;
+    if (more) gload(rb + kRS);
+    if constexpr (!kMma32) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f)
+      for (int ks = 0; ks < kRS / 4; ++ks) {
+        const double a0 = (double)Xs[buf][4 * ks + lk][qx + li], a1 = (double)Xs[buf][4 * ks + lk][qx + 16 + li];
+        const double b0 = (double)Ys[buf][4 * ks + lk][qy + li], b1 = (double)Ys[buf][4 * ks + lk][qy + 16 + li];
+        acc[0][0] = mfma16(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16(a1, b1, acc[1][1]);
+      }
+    } else {
+      v4f s[2][2];
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+      for (int f = 0; f < 2; ++f)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int i = 16 * f + lk + 4 * e, j = 16 * g + li;
-            if (q == 0)
-              red[i * 64 + j] = acc[f][g][e];
-            else
-              red[i * 64 + j] += acc[f][g][e];
-          }
+        for (int g = 0; g < 2; ++g) s[f][g] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < kRS / 4; ++ks) {
+        const float a0 = Xs[buf][4 * ks + lk][qx + li], a1 = Xs[buf][4 * ks + lk][qx + 16 + li];
+        const float b0 = Ys[buf][4 * ks + lk][qy + li], b1 = Ys[buf][4 * ks + lk][qy + 16 + li];
+        s[0][0] = mfma16f(a0, b0, s[0][0]);
+        s[0][1] = mfma16f(a0, b1, s[0][1]);
+        s[1][0] = mfma16f(a1, b0, s[1][0]);
+        s[1][1] = mfma16f(a1, b1, s[1][1]);
+      }
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[f][g][e] += (double)s[f][g][e];
     }
+    if (more) lstore(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   double *out = part + (int64_t)split * mx * my;
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-    const int i = idx / 64, j = idx % 64;
-    if (cx + i < mx && cy + j < my) out[(int64_t)(cx + i) * my + cy + j] = red[idx];
-  }
+#pragma unroll
+  for (int f = 0; f < 2; ++f)
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // result layouts: FP64 MFMA row lk + 4e, FP32 MFMA row 4 lk + e
+        const int rr = kMma32 ? 4 * lk + e : lk + 4 * e;
+        const int i = cx + qx + 16 * f + rr, j = cy + qy + 16 * g + li;
+        if (i < mx && j < my) out[(int64_t)i * my + j] = acc[f][g][e];
+      }
 }
 
 // G[i][j] = sum_s part[s][i][j] in order; for sym, the upper element is used
@@ -160,21 +184,14 @@ __global__ void k_gram_reduce(const double *__restrict__ part, int nsplit, int m
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)mx * my) return;
   int i = (int)(idx / my), j = (int)(idx % my);
-  if (sym && (i / 64) > (j / 64)) { const int t = i; i = j; j = t; }
+  if (sym && i > j) { const int t = i; i = j; j = t; }  // mirror the upper triangle exactly
   const int64_t src = (int64_t)i * my + j;
   double s = 0.0;
   for (int q = 0; q < nsplit; ++q) s += part[(int64_t)q * mx * my + src];
   G[idx] = s;
 }
 
-__global__ void k_mirror_upper(int m, double *G) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m * m) return;
-  const int i = (int)(idx / m), j = (int)(idx % m);
-  if (i > j) G[idx] = G[(int64_t)j * m + i];
-}
-
-template <typename T>
+template <typename T, bool kMma32>
 __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__ X, int64_t ldx, int m,
                                                 const double *__restrict__ W, int64_t ldw, int c, double alpha,
                                                 double beta, T *Y, int64_t ldy, int nct, int64_t nrt, int w_upper) {
@@ -193,24 +210,30 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
   // W upper triangular: rows k > c0 + 63 of this column tile are zero
   const int kend = w_upper ? min(m, c0 + 64) : m;
 
-  __shared__ double Xs[64][17];
-  __shared__ double Ws[16][65];
+  // FP64 matrix cores (FP32 data widened exactly, W kept in FP64), except in
+  // the kMma32 variant for FP32 data times a well-conditioned W (an
+  // orthogonal Ritz rotation): W rounded to FP32, FP32 matrix cores.
+  static_assert(!kMma32 || std::is_same<T, float>::value, "FP32 matrix cores need FP32 data");
+  typedef typename std::conditional<kMma32, float, double>::type S;
+  typedef typename std::conditional<kMma32, v4f, v4d>::type acc_t;
+  __shared__ S Xs[64][17];
+  __shared__ S Ws[16][65];
 
-  v4d acc[4];
+  acc_t acc[4];
 #pragma unroll
-  for (int g = 0; g < 4; ++g) acc[g] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int g = 0; g < 4; ++g) acc[g] = acc_t{0, 0, 0, 0};
 
   const int xr_ = threadIdx.x >> 2, xk = (threadIdx.x & 3) * 4;   // X tile: 64 rows x 16 k
   const int wk_ = threadIdx.x >> 4, wc = (threadIdx.x & 15) * 4;  // W tile: 16 k x 64 cols
   const int64_t xrow = r0 + xr_;
-  double xv[4], wvv[4];
+  S xv[4], wvv[4];
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = k0 + xk + q;
-      xv[q] = (xrow < n && kk < kend) ? (double)X[xrow * ldx + kk] : 0.0;
+      xv[q] = (xrow < n && kk < kend) ? (S)X[xrow * ldx + kk] : S(0);
       const int kw = k0 + wk_, cc = c0 + wc + q;
-      wvv[q] = (kw < kend && cc < c) ? W[(int64_t)kw * ldw + cc] : 0.0;
+      wvv[q] = (kw < kend && cc < c) ? (S)W[(int64_t)kw * ldw + cc] : S(0);
     }
   };
   if (kend > 0) load(0);
@@ -224,9 +247,14 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
     if (k0 + 16 < kend) load(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      const double a = Xs[16 * wv + li][4 * ks + lk];
+      const S a = Xs[16 * wv + li][4 * ks + lk];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) acc[g] = mfma16(a, Ws[4 * ks + lk][16 * g + li], acc[g]);
+      for (int g = 0; g < 4; ++g) {
+        if constexpr (kMma32)
+          acc[g] = mfma16f(a, Ws[4 * ks + lk][16 * g + li], acc[g]);
+        else
+          acc[g] = mfma16(a, Ws[4 * ks + lk][16 * g + li], acc[g]);
+      }
     }
     __syncthreads();
   }
@@ -236,10 +264,10 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
     if (col >= c) continue;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t row = r0 + 16 * wv + lk + 4 * e;
+      const int64_t row = r0 + 16 * wv + (kMma32 ? 4 * lk + e : lk + 4 * e);
       if (row >= n) continue;
       T *yp = Y + row * ldy + col;
-      double v = alpha * acc[g][e];
+      double v = alpha * (double)acc[g][e];
       if (beta != 0.0) v += beta * (double)(*yp);
       *yp = (T)v;
     }
@@ -267,7 +295,8 @@ size_t gram_work_doubles(int64_t n, int mx, int my) {
 }
 
 template <typename T>
-void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym, hipStream_t s) {
+void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym, hipStream_t s,
+                 bool fp32_cores) {
   const int mx = X.w, my = Y.w;
   if (mx == 0 || my == 0) return;
   if (sym) ARR_REQUIRE(mx == my, "gram: symmetric product needs equal widths");
@@ -276,8 +305,13 @@ void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *w
     return;
   }
   const GramPlan p = gram_plan(n, mx, my, sym);
-  hipLaunchKernelGGL((k_gram<T>), dim3(p.ntiles * p.nsplit), dim3(256), 0, s, n, X.p, X.ld, mx, Y.p, Y.ld, my,
-                     p.ntx, p.nty, p.ntiles, sym ? 1 : 0, p.chunk, work);
+  const dim3 grid(p.ntiles * p.nsplit);
+  if (std::is_same<T, float>::value && fp32_cores)
+    hipLaunchKernelGGL((k_gram<float, true>), grid, dim3(256), 0, s, n, (const float *)X.p, X.ld, mx,
+                       (const float *)Y.p, Y.ld, my, p.ntx, p.nty, p.ntiles, sym ? 1 : 0, p.chunk, work);
+  else
+    hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(256), 0, s, n, X.p, X.ld, mx, Y.p, Y.ld, my, p.ntx, p.nty,
+                       p.ntiles, sym ? 1 : 0, p.chunk, work);
   ARR_HIP(hipGetLastError());
   const int64_t tot = (int64_t)mx * my;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, p.nsplit, mx,
@@ -287,25 +321,29 @@ void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *w
 
 template <typename T>
 void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int c, double alpha, double beta,
-                   Blk<T> Y, hipStream_t s, bool w_upper) {
+                   Blk<T> Y, hipStream_t s, bool w_upper, bool fp32_cores) {
   const int m = X.w;
   if (n == 0 || c == 0) return;
   const int nct = (c + 63) / 64;
   const int64_t nrt = (n + 63) / 64;
   const int64_t bands_per_xcd = (nrt + kXcd - 1) / kXcd;
   const int64_t grid = bands_per_xcd * nct * kXcd;
-  hipLaunchKernelGGL((k_update<T>), dim3((unsigned)grid), dim3(256), 0, s, n, X.p, X.ld, m, W, ldw, c, alpha,
-                     beta, Y.p, Y.ld, nct, nrt, w_upper ? 1 : 0);
+  if (std::is_same<T, float>::value && fp32_cores)
+    hipLaunchKernelGGL((k_update<float, true>), dim3((unsigned)grid), dim3(256), 0, s, n, (const float *)X.p, X.ld,
+                       m, W, ldw, c, alpha, beta, (float *)Y.p, Y.ld, nct, nrt, w_upper ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_update<T, false>), dim3((unsigned)grid), dim3(256), 0, s, n, X.p, X.ld, m, W, ldw, c,
+                       alpha, beta, Y.p, Y.ld, nct, nrt, w_upper ? 1 : 0);
   ARR_HIP(hipGetLastError());
 }
 
 template void launch_gram<double>(int64_t, Blk<const double>, Blk<const double>, double *, double *, bool,
-                                  hipStream_t);
+                                  hipStream_t, bool);
 template void launch_gram<float>(int64_t, Blk<const float>, Blk<const float>, double *, double *, bool,
-                                 hipStream_t);
+                                 hipStream_t, bool);
 template void launch_update<double>(int64_t, Blk<const double>, const double *, int64_t, int, double, double,
-                                    Blk<double>, hipStream_t, bool);
+                                    Blk<double>, hipStream_t, bool, bool);
 template void launch_update<float>(int64_t, Blk<const float>, const double *, int64_t, int, double, double,
-                                   Blk<float>, hipStream_t, bool);
+                                   Blk<float>, hipStream_t, bool, bool);
 
 }  // namespace arr

@@ -421,9 +421,9 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     // Ritz vectors X_new = U V[:, :cnew] into the free buffer, A X_new = W V into U's
     const double *V = wk_.small.template as<double>() + (size_t)m * m;
     Blk<T> Xn{Pfree.p, Pfree.ld, cnew};
-    launch_update<T>(n, Blk<const T>{U.p, U.ld, m}, V, m, cnew, 1.0, 0.0, Xn, s_);
+    launch_update<T>(n, Blk<const T>{U.p, U.ld, m}, V, m, cnew, 1.0, 0.0, Xn, s_, false, /*fp32_cores=*/true);
     Blk<T> AXn{U.p, U.ld, cnew};
-    launch_update<T>(n, Blk<const T>{B.W(0, m).p, B.ldz, m}, V, m, cnew, 1.0, 0.0, AXn, s_);
+    launch_update<T>(n, Blk<const T>{B.W(0, m).p, B.ldz, m}, V, m, cnew, 1.0, 0.0, AXn, s_, false, /*fp32_cores=*/true);
     ARR_HIP(hipMemcpyAsync(mu_.p, ritz.data(), sizeof(double) * cnew, hipMemcpyHostToDevice, s_));
     std::vector<double> rnew = residual_norms<T>(n, Blk<const T>{AXn.p, AXn.ld, cnew},
                                                  Blk<const T>{Xn.p, Xn.ld, cnew}, mu_.as<double>(), wk_, s_);
@@ -611,12 +611,13 @@ int Solver::solve() {
   if (o_.timing) {
     timer.flush();
     int best = 0;
-    for (int c = 1; c < 5; ++c)
+    for (int c = 1; c < SpmmTimer::kClasses; ++c)
       if (timer.ms[c] > timer.ms[best]) best = c;
     stats.spmm_launches = timer.launches[best];
     stats.spmm_ms = timer.ms[best];
     stats.spmm_bytes = timer.bytes[best];
-    stats.spmm_cols_per_lane = 1 << best;
+    stats.spmm_cols_per_lane = 1 << (best % 5);
+    stats.spmm_fp64 = best >= 5 ? 1 : 0;
   }
   stats.status = status;
   stats.a = which_ == ARR_SMALLEST_ALGEBRAIC ? -a_ : a_;

@@ -176,7 +176,7 @@ void SpmmTimer::flush() {
 
 void SpmmTimer::reset() {
   flush();
-  for (int i = 0; i < 5; ++i) launches[i] = 0, ms[i] = 0, bytes[i] = 0;
+  for (int i = 0; i < kClasses; ++i) launches[i] = 0, ms[i] = 0, bytes[i] = 0;
 }
 
 SpmmTimer::~SpmmTimer() {
@@ -205,7 +205,7 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   for (int c0 = 0; c0 < w; c0 += 1024) {
     const int wc = std::min(1024, w - c0);
     const T al = (T)alpha, be = (T)beta, ga = (T)gamma;
-    const int cls = wc <= 64 ? 0 : wc <= 128 ? 1 : wc <= 256 ? 2 : wc <= 512 ? 3 : 4;
+    const int cls = (wc <= 64 ? 0 : wc <= 128 ? 1 : wc <= 256 ? 2 : wc <= 512 ? 3 : 4) + (sizeof(T) == 8 ? 5 : 0);
     SpmmTimer::Pending pend{};
     if (timer) {
       pend.a = timer->get();

@@ -195,8 +195,8 @@ void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work
   wk.ensure_small(m);
   double *H = wk.small.as<double>();
   double *V = H + (size_t)m * m;
-  launch_gram<T>(n, U, Blk<const T>{W.p, W.ld, m}, H, wk.gramw.as<double>(), false, s);
-  launch_symmetrize(m, H, m, s);
+  // H = U^T (A U) is symmetric: form its upper tiles and mirror them
+  launch_gram<T>(n, U, Blk<const T>{W.p, W.ld, m}, H, wk.gramw.as<double>(), true, s, /*fp32_cores=*/true);
   wk.jac.solve(m, H, V, evals, s, &wk.last_sweeps);
 }
 

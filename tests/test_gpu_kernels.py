@@ -111,9 +111,11 @@ def test_poly_fp32_error_is_small():
 
 
 @pytest.mark.parametrize("n,mx,my", [(5003, 1, 1), (5003, 17, 65), (777, 64, 64), (20011, 130, 200), (33, 5, 3)])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32cores"])
 def test_gram(n, mx, my, dtype):
     rng = np.random.default_rng(n + mx)
+    fast = dtype == "f32cores"
+    dtype = "f32" if fast else dtype
     tdt = torch.float64 if dtype == "f64" else torch.float32
     X = rng.standard_normal((n, mx + 2))
     Y = rng.standard_normal((n, my + 1))
@@ -121,23 +123,29 @@ def test_gram(n, mx, my, dtype):
         X, Y = X.astype(np.float32).astype(np.float64), Y.astype(np.float32).astype(np.float64)
     Xd, Yd = dev(X, tdt), dev(Y, tdt)
     G = torch.zeros((mx, my), dtype=torch.float64, device="cuda")
-    arr.arr_gram(Xd[:, :mx], Yd[:, :my], G)
+    arr.arr_gram(Xd[:, :mx], Yd[:, :my], G, fp32_cores=fast)
     ref = X[:, :mx].T @ Y[:, :my]
     bound = np.abs(X[:, :mx]).T @ np.abs(Y[:, :my])
-    assert np.all(np.abs(G.cpu().numpy() - ref) <= 1e-14 * np.sqrt(n) * bound + 1e-300)
+    # FP64 products and sums, except on the FP32 matrix cores: each 32-row
+    # slice summed in FP32 (error at most gamma_32 of the slice's |x||y|), the
+    # slices added in FP64.
+    rel = 1e-14 * np.sqrt(n) + (32 * 2.0**-24 if fast else 0.0)
+    assert np.all(np.abs(G.cpu().numpy() - ref) <= rel * bound + 1e-300)
     # symmetric product (same buffer): exactly symmetric
     Gs = torch.zeros((mx, mx), dtype=torch.float64, device="cuda")
-    arr.arr_gram(Xd[:, :mx], Xd[:, :mx], Gs)
+    arr.arr_gram(Xd[:, :mx], Xd[:, :mx], Gs, fp32_cores=fast)
     gs = Gs.cpu().numpy()
     assert np.array_equal(gs, gs.T)
     ref_s = X[:, :mx].T @ X[:, :mx]
-    assert np.all(np.abs(gs - ref_s) <= 1e-14 * np.sqrt(n) * (np.abs(X[:, :mx]).T @ np.abs(X[:, :mx])))
+    assert np.all(np.abs(gs - ref_s) <= rel * (np.abs(X[:, :mx]).T @ np.abs(X[:, :mx])))
 
 
 @pytest.mark.parametrize("n,m,c", [(5003, 1, 1), (5003, 16, 65), (4097, 17, 64), (20011, 480, 240), (70, 100, 3)])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32cores"])
 def test_block_update(n, m, c, dtype):
     rng = np.random.default_rng(m * c)
+    fast = dtype == "f32cores"
+    dtype = "f32" if fast else dtype
     tdt = torch.float64 if dtype == "f64" else torch.float32
     X = rng.standard_normal((n, m))
     Wm = rng.standard_normal((m, c + 2))
@@ -145,13 +153,17 @@ def test_block_update(n, m, c, dtype):
     if dtype == "f32":
         X, Y0 = X.astype(np.float32).astype(np.float64), Y0.astype(np.float32).astype(np.float64)
     Xd, Wd, Yd = dev(X, tdt), dev(Wm), dev(Y0, tdt)
-    arr.arr_block_update(Xd, Wd[:, :c], Yd[:, :c], alpha=-0.5, beta=2.0)
+    arr.arr_block_update(Xd, Wd[:, :c], Yd[:, :c], alpha=-0.5, beta=2.0, fp32_cores=fast)
     torch.cuda.synchronize()
     ref = 2.0 * Y0[:, :c] - 0.5 * X @ Wm[:, :c]
     bound = 2.0 * np.abs(Y0[:, :c]) + 0.5 * np.abs(X) @ np.abs(Wm[:, :c])
-    eps = 1.2e-16 if dtype == "f64" else 6e-8
     got = Yd.double().cpu().numpy()
-    assert np.all(np.abs(got[:, :c] - ref) <= 4 * m * eps * bound + 1e-300)
+    if dtype == "f32" and not fast:
+        # FP64 products and sums: only the final rounding to FP32
+        assert np.all(np.abs(got[:, :c] - ref) <= (2.0**-24 + 4 * m * 1.2e-16) * bound + 1e-300)
+    else:
+        eps = 1.2e-16 if dtype == "f64" else 6e-8
+        assert np.all(np.abs(got[:, :c] - ref) <= 4 * m * eps * bound + 1e-300)
     assert np.array_equal(got[:, c:], Y0[:, c:])
 
 
