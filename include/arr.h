@@ -65,7 +65,11 @@ typedef struct {
 } arr_csr_t;
 
 /* Device CSR description used by the step-level entry points. val is a
- * device array of FP64 (dtype 0) or FP32 (dtype 1) values. */
+ * device array of FP64 (dtype 0) or FP32 (dtype 1) values; column indices
+ * strictly increase within each row. Each step call copies the matrix to the
+ * host, checks it (ARR_EINVAL on a malformed CSR) and builds, in temporary
+ * device memory, the split form its kernels read: the three central
+ * diagonals as dense arrays plus a CSR of the other entries. */
 typedef struct {
   int64_t n, nnz;
   const int64_t *rowptr; /* device [n+1] */
@@ -123,6 +127,7 @@ typedef struct {
   double spmm_bytes;
   int32_t spmm_cols_per_lane; /* kernel variant: columns per lane (1, 2, 4, 8, 16) */
   int32_t spmm_fp64;          /* data type of that variant: 1 FP64, 0 FP32 */
+  int32_t spmm_vec;           /* columns per lane load: 1, or 4 (16-byte FP32 loads) */
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;
@@ -212,7 +217,7 @@ void arr_server_destroy(arr_server_t s);
  * leading dimensions ldy, ldz, ldo). Z may equal Yin or be NULL (gamma
  * ignored). Yout must not overlap Yin; it may equal Z. If colsumsq (device,
  * FP64 [w]) is non-NULL it receives the squared 2-norms of Yout's columns.
- * Synchronous when colsumsq is non-NULL. */
+ * Synchronous. */
 int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t ldy, const void *Z,
                     int64_t ldz, void *Yout, int64_t ldo, double alpha, double beta, double gamma,
                     double *colsumsq, void *stream);

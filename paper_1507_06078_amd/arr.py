@@ -68,7 +68,8 @@ class arr_stats_t(ctypes.Structure):
                 ("maxres", ctypes.c_double), ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double),
                 ("t_filter", ctypes.c_double), ("t_arr", ctypes.c_double), ("t_dense", ctypes.c_double),
                 ("spmm_launches", ctypes.c_int64), ("spmm_ms", ctypes.c_double), ("spmm_bytes", ctypes.c_double),
-                ("spmm_cols_per_lane", ctypes.c_int32), ("spmm_fp64", ctypes.c_int32)]
+                ("spmm_cols_per_lane", ctypes.c_int32), ("spmm_fp64", ctypes.c_int32),
+                ("spmm_vec", ctypes.c_int32)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",

@@ -38,10 +38,56 @@ int guarded(std::string *err, F &&f) {
   }
 }
 
+// The caller's device CSR in the split form of the SpMM kernels: downloaded,
+// checked (row pointers, column range and order), split on the host and
+// uploaded into buffers this object owns.
 template <typename T>
-arr::DevCSR<T> dev_csr(const arr_dev_csr_t *A) {
-  ARR_REQUIRE(A && A->rowptr && A->n > 0, "device CSR is NULL or empty");
-  return arr::DevCSR<T>{A->n, A->nnz, A->rowptr, A->colind, static_cast<const T *>(A->val)};
+struct SplitDev {
+  arr::DevBuf rp, col, val, band;
+  arr::DevCSR<T> M;
+};
+
+template <typename T>
+std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
+  ARR_REQUIRE(A && A->rowptr && A->n > 0 && A->nnz >= 0, "device CSR is NULL or empty");
+  ARR_REQUIRE(A->nnz == 0 || (A->colind && A->val), "device CSR arrays are NULL");
+  const int64_t n = A->n, nnz = A->nnz;
+  std::vector<int64_t> rp(n + 1);
+  std::vector<int32_t> ci(nnz);
+  std::vector<T> vt(nnz);
+  ARR_HIP(hipMemcpy(rp.data(), A->rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+  if (nnz) {
+    ARR_HIP(hipMemcpy(ci.data(), A->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    ARR_HIP(hipMemcpy(vt.data(), A->val, sizeof(T) * nnz, hipMemcpyDeviceToHost));
+  }
+  ARR_REQUIRE(rp[0] == 0 && rp[n] == nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
+  for (int64_t i = 0; i < n; ++i) {
+    ARR_REQUIRE(rp[i] <= rp[i + 1], "rowptr must be non-decreasing");
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+      ARR_REQUIRE(ci[q] >= 0 && ci[q] < n, "column index out of range");
+      ARR_REQUIRE(q == rp[i] || ci[q - 1] < ci[q], "column indices must be strictly increasing within a row");
+    }
+  }
+  std::vector<double> v(vt.begin(), vt.end()), fval, band;
+  std::vector<int64_t> frp;
+  std::vector<int32_t> fcol;
+  arr::split_band(n, rp.data(), ci.data(), v.data(), frp, fcol, fval, band);
+  std::vector<T> fv(fval.begin(), fval.end()), bv(band.begin(), band.end());
+  auto d = std::make_unique<SplitDev<T>>();
+  const int64_t nf = (int64_t)fcol.size();
+  d->rp.alloc(sizeof(int64_t) * (n + 1));
+  d->col.alloc(sizeof(int32_t) * std::max<int64_t>(1, nf));
+  d->val.alloc(sizeof(T) * std::max<int64_t>(1, nf));
+  d->band.alloc(sizeof(T) * 3 * n);
+  ARR_HIP(hipMemcpy(d->rp.p, frp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+  if (nf) {
+    ARR_HIP(hipMemcpy(d->col.p, fcol.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice));
+    ARR_HIP(hipMemcpy(d->val.p, fv.data(), sizeof(T) * nf, hipMemcpyHostToDevice));
+  }
+  ARR_HIP(hipMemcpy(d->band.p, bv.data(), sizeof(T) * 3 * n, hipMemcpyHostToDevice));
+  d->M = arr::DevCSR<T>{n, nnz, (const int64_t *)d->rp.p, (const int32_t *)d->col.p, (const T *)d->val.p,
+                        (const T *)d->band.p};
+  return d;
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -228,21 +274,19 @@ int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t 
     }
     int groups;
     if (A->dtype == 0) {
-      auto M = dev_csr<double>(A);
-      groups = arr::launch_filter_spmm<double>(M, arr::Blk<const double>{(const double *)Yin, ldy, (int)w},
+      auto S = dev_split<double>(A);
+      groups = arr::launch_filter_spmm<double>(S->M, arr::Blk<const double>{(const double *)Yin, ldy, (int)w},
                                                arr::Blk<const double>{(const double *)Z, ldz, Z ? (int)w : 0},
                                                arr::Blk<double>{(double *)Yout, ldo, (int)w}, alpha, beta, gamma, pp, s);
     } else {
       ARR_REQUIRE(A->dtype == 1, "dtype must be 0 (FP64) or 1 (FP32)");
-      auto M = dev_csr<float>(A);
-      groups = arr::launch_filter_spmm<float>(M, arr::Blk<const float>{(const float *)Yin, ldy, (int)w},
+      auto S = dev_split<float>(A);
+      groups = arr::launch_filter_spmm<float>(S->M, arr::Blk<const float>{(const float *)Yin, ldy, (int)w},
                                               arr::Blk<const float>{(const float *)Z, ldz, Z ? (int)w : 0},
                                               arr::Blk<float>{(float *)Yout, ldo, (int)w}, alpha, beta, gamma, pp, s);
     }
-    if (colsumsq) {
-      arr::launch_reduce_groups(pp, groups, (int)w, colsumsq, false, s);
-      ARR_HIP(hipStreamSynchronize(s));
-    }
+    if (colsumsq) arr::launch_reduce_groups(pp, groups, (int)w, colsumsq, false, s);
+    ARR_HIP(hipStreamSynchronize(s));  // before the temporary buffers go
     return ARR_OK;
   });
 }
@@ -268,13 +312,15 @@ int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shif
     if (A->dtype == 0) {
       arr::DevBuf tmp(sizeof(double) * n * 2 * std::max<int64_t>(1, w));
       double *t = tmp.as<double>();
-      arr::poly_apply<double>(dev_csr<double>(A), arr::Blk<double>{(double *)X, ld, (int)w},
+      auto S = dev_split<double>(A);
+      arr::poly_apply<double>(S->M, arr::Blk<double>{(double *)X, ld, (int)w},
                               arr::Blk<double>{t, 2 * w, (int)w}, arr::Blk<double>{t + w, 2 * w, (int)w}, shift, lo,
                               hi, g, wk, false, s);
     } else {
       arr::DevBuf tmp(sizeof(float) * n * 2 * std::max<int64_t>(1, w));
       float *t = tmp.as<float>();
-      arr::poly_apply<float>(dev_csr<float>(A), arr::Blk<float>{(float *)X, ld, (int)w},
+      auto S = dev_split<float>(A);
+      arr::poly_apply<float>(S->M, arr::Blk<float>{(float *)X, ld, (int)w},
                              arr::Blk<float>{t, 2 * w, (int)w}, arr::Blk<float>{t + w, 2 * w, (int)w}, shift, lo, hi,
                              g, wk, false, s);
     }
@@ -369,7 +415,8 @@ int arr_augmented_rr(const arr_dev_csr_t *A, int64_t w, const double *X, int64_t
     const int m = (int)((p + 1) * w);
     ARR_REQUIRE(m <= n, "augmented_rr: (p+1) w must not exceed n");
     hipStream_t s = as_stream(stream);
-    auto M = dev_csr<double>(A);
+    auto S = dev_split<double>(A);
+    const arr::DevCSR<double> &M = S->M;
     arr::Work wk;
     arr::DevBuf zb(sizeof(double) * n * m), ub(sizeof(double) * n * m), wb(sizeof(double) * n * m);
     const int iw = (int)w;

@@ -32,14 +32,24 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::arr::Error(-1, std::string(msg));      \
   } while (0)
 
-// Device CSR: rowptr int64 [n+1], col int32 [nnz], values in T.
+// Device matrix in the split form the SpMM kernels read: band [3n] holds the
+// three central diagonals (band[i] = A[i][i-1], band[n+i] = A[i][i],
+// band[2n+i] = A[i][i+1]; zero where the entry is absent) and a CSR (rowptr
+// int64 [n+1], col int32, values in T) holds the remaining entries. nnz
+// counts every entry of the matrix.
 template <typename T>
 struct DevCSR {
   int64_t n = 0, nnz = 0;
   const int64_t *rowptr = nullptr;
   const int32_t *col = nullptr;
   const T *val = nullptr;
+  const T *band = nullptr;
 };
+
+// Host split of a CSR with strictly increasing columns per row into the band
+// [3n] and the CSR of the other entries (frp [n+1], fcol, fval).
+void split_band(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, std::vector<int64_t> &frp,
+                std::vector<int32_t> &fcol, std::vector<double> &fval, std::vector<double> &band);
 
 // A row-major view of columns [0, w) of a device block with leading
 // dimension ld.
@@ -139,8 +149,9 @@ struct SpmmTimer {
   struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
-  // launch class: columns-per-lane variant (0..4 for 1..16) + 5 for FP64 data
-  static constexpr int kClasses = 10;
+  // launch class: columns per lane (0..4 for 1..16) + 5 for 16-byte loads
+  // + 10 for FP64 data
+  static constexpr int kClasses = 20;
   int64_t launches[kClasses] = {};
   double ms[kClasses] = {}, bytes[kClasses] = {};
   hipEvent_t get();

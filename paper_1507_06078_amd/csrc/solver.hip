@@ -113,11 +113,13 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
       ARR_REQUIRE(f != e && *f == i && csr->val[rp[c] + (f - b)] == csr->val[q], "matrix is not symmetric");
     }
   }
-  h_rowptr_.assign(rp, rp + n + 1);
-  h_col_.assign(csr->colind, csr->colind + csr->nnz);
-  h_val_.assign(csr->val, csr->val + csr->nnz);
-  if (which == ARR_SMALLEST_ALGEBRAIC)
+  // working operator (A, or -A for the smallest end) in the split form
+  split_band(n, rp, csr->colind, csr->val, h_rowptr_, h_col_, h_val_, h_band_);
+  nnz_ = csr->nnz;
+  if (which == ARR_SMALLEST_ALGEBRAIC) {
     for (double &x : h_val_) x = -x;
+    for (double &x : h_band_) x = -x;
+  }
   ldz_ = round_up((int64_t)std::max(o.p_max + 1, 2) * w_, 8);
   ldq_ = round_up(w_, 8);
   lanczos_L_ = (int)std::max<int64_t>(1, std::min<int64_t>(o.lanczos_steps, n));
@@ -126,7 +128,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
 // Every device buffer of a solve, in one place: with allocate = false the
 // padded byte count is returned (the footprint a server reserves).
 size_t Solver::device_plan(bool allocate) {
-  const int64_t n = n_, nnz = (int64_t)h_col_.size();
+  const int64_t n = n_, nnz = (int64_t)h_col_.size();  // far entries
   const bool mixed = o_.precision == ARR_MIXED;
   size_t total = 0;
   auto take = [&](DevBuf &b, size_t bytes) {
@@ -136,7 +138,11 @@ size_t Solver::device_plan(bool allocate) {
   take(rowptr_, sizeof(int64_t) * (n + 1));
   take(col_, sizeof(int32_t) * std::max<int64_t>(1, nnz));
   take(val64_, sizeof(double) * std::max<int64_t>(1, nnz));
-  if (mixed) take(val32_, sizeof(float) * std::max<int64_t>(1, nnz));
+  take(band64_, sizeof(double) * 3 * n);
+  if (mixed) {
+    take(val32_, sizeof(float) * std::max<int64_t>(1, nnz));
+    take(band32_, sizeof(float) * 3 * n);
+  }
   for (DevBuf *b : {&B64_.Zb, &B64_.Ub, &B64_.Wb}) take(*b, sizeof(double) * n * ldz_);
   for (DevBuf *b : {&B64_.Qb, &B64_.Q2b}) take(*b, sizeof(double) * n * ldq_);
   if (mixed) {
@@ -170,11 +176,16 @@ void Solver::ensure_device() {
     if (o_.precision == ARR_MIXED)
       launch_convert<float, double>(nnz, 1, val32_.as<float>(), 1, val64_.as<double>(), 1, s_);
   }
+  ARR_HIP(hipMemcpyAsync(band64_.p, h_band_.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, s_));
+  if (o_.precision == ARR_MIXED)
+    launch_convert<float, double>(3 * n, 1, band32_.as<float>(), 1, band64_.as<double>(), 1, s_);
   if (have_x0_)
     ARR_HIP(hipMemcpyAsync(x0_.p, h_x0_.data(), sizeof(double) * n * w_, hipMemcpyHostToDevice, s_));
-  A64_ = DevCSR<double>{n, nnz, rowptr_.as<int64_t>(), col_.as<int32_t>(), val64_.as<double>()};
+  A64_ = DevCSR<double>{n, nnz_, rowptr_.as<int64_t>(), col_.as<int32_t>(), val64_.as<double>(),
+                        band64_.as<double>()};
   if (o_.precision == ARR_MIXED)
-    A32_ = DevCSR<float>{n, nnz, rowptr_.as<int64_t>(), col_.as<int32_t>(), val32_.as<float>()};
+    A32_ = DevCSR<float>{n, nnz_, rowptr_.as<int64_t>(), col_.as<int32_t>(), val32_.as<float>(),
+                         band32_.as<float>()};
   B64_.ldz = ldz_;
   B64_.ldq = ldq_;
   B32_.ldz = ldz_;
@@ -185,7 +196,7 @@ void Solver::ensure_device() {
 
 void Solver::release_device() {
   if (s_) ARR_HIP(hipStreamSynchronize(s_));
-  for (DevBuf *b : {&rowptr_, &col_, &val64_, &val32_, &B64_.Zb, &B64_.Ub, &B64_.Wb, &B64_.Qb, &B64_.Q2b, &B32_.Zb,
+  for (DevBuf *b : {&rowptr_, &col_, &val64_, &val32_, &band64_, &band32_, &B64_.Zb, &B64_.Ub, &B64_.Wb, &B64_.Qb, &B64_.Q2b, &B32_.Zb,
                     &B32_.Ub, &B32_.Wb, &B32_.Qb, &B32_.Q2b, &mu_, &desc_, &outv_, &x0_, &lz_V_, &lz_w_, &lz_h_,
                     &lz_part_, &wk_.partial, &wk_.colv, &wk_.gramw, &wk_.small, &wk_.proj, &wk_.info, &wk_.jac.bufA,
                     &wk_.jac.bufB, &wk_.jac.bufV, &wk_.jac.bufOff, &wk_.jac.bufEval})
@@ -617,7 +628,8 @@ int Solver::solve() {
     stats.spmm_ms = timer.ms[best];
     stats.spmm_bytes = timer.bytes[best];
     stats.spmm_cols_per_lane = 1 << (best % 5);
-    stats.spmm_fp64 = best >= 5 ? 1 : 0;
+    stats.spmm_vec = (best % 10) >= 5 ? 4 : 1;
+    stats.spmm_fp64 = best >= 10 ? 1 : 0;
   }
   stats.status = status;
   stats.a = which_ == ARR_SMALLEST_ALGEBRAIC ? -a_ : a_;

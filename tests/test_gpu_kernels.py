@@ -30,10 +30,19 @@ def with_empty_rows(n=700, seed=3):
     return W.from_scipy(S, "empty_rows")
 
 
+def tridiagonal(n=1001, seed=5):
+    """Only the band the kernels keep in registers: the far CSR is empty."""
+    rng = np.random.default_rng(seed)
+    off = rng.standard_normal(n - 1)
+    S = sp.diags([off, rng.standard_normal(n), off], [-1, 0, 1], format="csr")
+    return W.from_scipy(S, "tridiagonal")
+
+
 MATS = {
     "lap3d_12V": lambda: W.laplacian_3d(12, potential_seed=1),
     "powerlaw_4000": lambda: W.powerlaw_random(4000, seed=7, cap=300),
     "empty_rows": with_empty_rows,
+    "tridiagonal": tridiagonal,
 }
 
 
@@ -59,6 +68,32 @@ def test_filter_step_fp64(mat, w):
     assert np.all(np.abs(got[:, :w] - ref) <= 64 * 1.2e-16 * bound + 1e-300)
     assert np.all(got[:, w:] == 7.0)  # columns beyond w untouched
     np.testing.assert_allclose(ss.cpu().numpy(), (ref ** 2).sum(axis=0), rtol=1e-12)
+
+
+@pytest.mark.parametrize("mat", list(MATS))
+@pytest.mark.parametrize("w,ld", [(1, 1), (33, 36), (240, 240), (240, 243), (600, 604), (1000, 1000), (1100, 1104)])
+def test_filter_step_fp32(mat, w, ld):
+    """FP32 blocks: 16-byte loads when rows are 16-byte aligned (ld and w
+    multiples of 4), one column per lane otherwise; several column chunks."""
+    A = MATS[mat]()
+    Ad = arr.DeviceCSR(A, dtype=torch.float32)
+    S32 = sp.csr_matrix((A.val.astype(np.float32).astype(np.float64), A.colind, A.rowptr), shape=(A.n, A.n))
+    rng = np.random.default_rng(w + ld)
+    Yin = rng.standard_normal((A.n, ld)).astype(np.float32).astype(np.float64)
+    Z = rng.standard_normal((A.n, ld)).astype(np.float32).astype(np.float64)
+    Yd, Zd = dev(Yin, torch.float32), dev(Z, torch.float32)
+    Od = torch.full((A.n, ld), 7.0, dtype=torch.float32, device="cuda")
+    ss = torch.zeros(w, dtype=torch.float64, device="cuda")
+    al, be, ga = 0.37, -1.25, 0.5
+    arr.arr_filter_step(Ad, Yd[:, :w], Zd[:, :w], Od[:, :w], al, be, ga, colsumsq=ss)
+    got = Od.double().cpu().numpy()
+    ref = np.float32(al) * (S32 @ Yin[:, :w]) + np.float32(be) * Yin[:, :w] + np.float32(ga) * Z[:, :w]
+    bound = abs(al) * (abs(S32) @ np.abs(Yin[:, :w])) + abs(be) * np.abs(Yin[:, :w]) + abs(ga) * np.abs(Z[:, :w])
+    kmax = int(np.diff(A.rowptr).max()) + 4
+    assert np.all(np.abs(got[:, :w] - ref) <= kmax * 6e-8 * bound + 1e-30)
+    assert np.all(got[:, w:] == 7.0)
+    # column norms of the stored FP32 output, summed in FP64
+    np.testing.assert_allclose(ss.cpu().numpy(), (got[:, :w] ** 2).sum(axis=0), rtol=1e-12)
 
 
 @pytest.mark.parametrize("w", [1, 33, 240])
