@@ -30,7 +30,7 @@ WORKLOAD = ("3D 7-point Laplacian 100^3 + U[0,1) diagonal potential (seed 1), n=
 
 
 def cpu_baseline(A, k, w, spmm_cols_per_solve, a, b):
-    """Time the CPU oracle's Algorithm 7 (poly, degree 3, on the shifted
+    """Time the CPU oracle's Algorithm 7 (poly, degree 9, on the shifted
     operator as Algorithm 8 calls it) on the full workload with a 240-column
     block, and scale by the number of block-degree columns the GPU solve
     needed. This counts only the filter work the paper reports as dominant, so
@@ -42,15 +42,16 @@ def cpu_baseline(A, k, w, spmm_cols_per_solve, a, b):
 
     B = -A.to_scipy()
     X = W.gaussian_block(A.n, w, seed=2)
-    g = O.interpolant_coefficients(3)
+    d = 9
+    g = O.interpolant_coefficients(d)
     t = time.perf_counter()
     Y = O.poly(O.shifted(B, a), X, 0.0, b - a, g)
     dt = time.perf_counter() - t
     del Y
-    per_col = dt / (3 * w)
+    per_col = dt / (d * w)
     est = per_col * spmm_cols_per_solve
     return {"value": k / est, "unit": "eigenpairs/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle poly (Algorithm 7, 3 degrees, scipy CSR x {w}-column FP64 block, single thread) "
+            "sample": (f"oracle poly (Algorithm 7, {d} degrees, scipy CSR x {w}-column FP64 block, single thread) "
                        f"on the full n=1e6 workload took {dt:.2f} s; scaled to the GPU solve's "
                        f"{spmm_cols_per_solve} block-degree columns -> {est:.0f} s per solve "
                        "(filter work only: a lower bound of the oracle's solve time)"),
@@ -145,15 +146,134 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_spmm_lap3d100_traffic.md")
+SPMM_SOURCE = os.path.join(ROOT, "paper_1507_06078_amd", "csrc", "spmm.hip")
+FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the counter
+    reads for a plain copy of known size), or None when the summary is missing
+    or was taken on another version of the SpMM source."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    rec = next((json.loads(l.split(":", 1)[1]) for l in lines if l.startswith("traffic-json:")), None)
+    if not rec:
+        return None
+    sha = hashlib.sha256(open(SPMM_SOURCE, "rb").read()).hexdigest()
+    if rec.get("spmm_source_sha256") != sha or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return 1024.0 * (k["fetch_kib"] * rec["copy_fetch_factor"] + k["write_kib"] * rec["copy_write_factor"])
+
+
+def solve_run(A, k, w, tol, precision, args, label):
+    """Warmup + timed solves of one handle; returns the figures of the timed
+    solves and the eigenvalues of the last one."""
+    import torch
+    from paper_1507_06078_amd import arr
+
+    o = arr.arr_options_default()
+    o.w = w
+    o.precision = arr.MIXED if precision == "mixed" else arr.FP64
+    o.timing = 1
+    if args.mixed_switch is not None:
+        o.mixed_switch = args.mixed_switch
+    o.verbose = 1 if args.verbose else 0
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o)
+    print(f"[bench] {label}: handle ready (n={A.n}, nnz={A.nnz}); warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        st = arr.arr_solve(h)
+        print(f"[bench] {label} warmup {i}: status {st}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        st = arr.arr_solve(h)
+        stats.append(arr.arr_get_stats(h))
+        print(f"[bench] {label} step {i}: status {st} t {stats[-1]['t_total']:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ev, _, res = arr.arr_get_eigpairs(h, k, A.n, vectors=False)
+    h.close()
+    sec = (t1 - t0) / args.steps
+    ok = all(s["status"] == 0 for s in stats) and float(res.max()) <= tol
+    tot = lambda key: sum(s[key] for s in stats)
+    spmm_ms, spmm_bytes, launches = tot("spmm_ms"), tot("spmm_bytes"), tot("spmm_launches")
+    last = stats[-1]
+    achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9 if spmm_ms > 0 else None
+    vec = last["spmm_vec"]
+    kernel = (f"k_filter_spmm<{'double' if last['spmm_fp64'] else 'float'}, {vec}, "
+              f"{max(1, last['spmm_cols_per_lane'] // vec)}>")
+    traffic = measured_traffic(kernel)
+
+    def gemm(prefix, peak):
+        ms, fl, n = tot(prefix + "_ms"), tot(prefix + "_flops"), tot(prefix + "_launches")
+        if not n:
+            return None
+        tf = fl / (ms * 1e-3) / 1e12
+        return {"achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak, "launches": n,
+                "avg_launch_us": ms * 1e3 / n, "algorithmic_flops_per_launch": fl / n}
+
+    return {
+        "value": (k / sec) if ok else 0.0, "ms_per_step": sec * 1e3, "converged": ok,
+        "max_res": float(res.max()), "eigenvalues": ev,
+        "roofline": {
+            "bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic, "launches": launches, "avg_launch_us": spmm_ms * 1e3 / max(1, launches),
+            "algorithmic_bytes_per_launch": spmm_bytes / max(1, launches),
+        },
+        "gemm": {"gram_fp64_cores": gemm("gram64", FP64_MFMA_PEAK_TFLOPS),
+                 "gram_fp32_cores": gemm("gram32", FP32_MFMA_PEAK_TFLOPS),
+                 "update_fp64_cores": gemm("upd64", FP64_MFMA_PEAK_TFLOPS),
+                 "update_fp32_cores": gemm("upd32", FP32_MFMA_PEAK_TFLOPS)},
+        "solve": {key: last[key] for key in ("outer_iters", "arr_calls", "poly_calls", "final_p", "final_d",
+                                             "n_locked", "fp32_outer", "spmm_degrees", "spmm_cols", "t_total",
+                                             "t_setup", "t_filter", "t_arr", "t_dense", "a", "b")},
+    }
+
+
+def small_case_accuracy():
+    """Both precisions on the 2D 5-point Laplacian 40 x 40 (k = 20 smallest,
+    block 30, tol 1e-10) against its closed-form spectrum."""
+    import numpy as np
+    from paper_1507_06078_amd import arr, workloads as W
+
+    A, k, which, w, tol = W.workload("lap2d_40")
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    out = {"workload": "2D 5-point Laplacian 40x40, k=20 smallest, block 30, tol 1e-10"}
+    for prec in ("fp64", "mixed"):
+        o = arr.arr_options_default()
+        o.w = w
+        o.precision = arr.MIXED if prec == "mixed" else arr.FP64
+        h = arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o)
+        st = arr.arr_solve(h)
+        ev, _, res = arr.arr_get_eigpairs(h, k, A.n, vectors=False)
+        h.close()
+        out[prec] = {"status": st, "max_rel_eig_err_vs_closed_form": float(np.max(np.abs(ev - exact) / np.abs(exact))),
+                     "max_res": float(res.max())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
+                    help="headline is the FP64 path; 'both' adds the mixed path beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--mixed-switch", type=float, default=None)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with three device copies of 2 GiB (reference kernel for counter scaling)")
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -181,74 +301,49 @@ def main():
         return
     A = W.laplacian_3d(100, potential_seed=1)
     k, w, tol = 200, 240, 1e-10
-    o = arr.arr_options_default()
-    o.w = w
-    o.precision = arr.MIXED if args.precision == "mixed" else arr.FP64
-    o.timing = 1
-    if args.mixed_switch is not None:
-        o.mixed_switch = args.mixed_switch
-    o.verbose = 1 if args.verbose else 0
-    h = arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o)
-    print(f"[bench] handle ready (n={A.n}, nnz={A.nnz}); warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        st = arr.arr_solve(h)
-        print(f"[bench] warmup {i}: status {st}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(args.steps):
-        st = arr.arr_solve(h)
-        stats.append(arr.arr_get_stats(h))
-        print(f"[bench] step {i}: status {st} t {stats[-1]['t_total']:.3f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ev, _, res = arr.arr_get_eigpairs(h, k, A.n, vectors=False)
-    sec = (t1 - t0) / args.steps
-    ok = all(s["status"] == 0 for s in stats) and float(res.max()) <= tol
-    spmm_ms = sum(s["spmm_ms"] for s in stats)
-    spmm_bytes = sum(s["spmm_bytes"] for s in stats)
-    launches = sum(s["spmm_launches"] for s in stats)
-    achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9 if spmm_ms > 0 else None
-    last = stats[-1]
+    head_prec = "mixed" if args.precision == "mixed" else "fp64"
+    head = solve_run(A, k, w, tol, head_prec, args, head_prec)
     out = {
         "metric": "converged eigenpairs/s at res<=1e-10",
-        "value": (k / sec) if ok else 0.0,
+        "value": head["value"],
         "unit": "eigenpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "precision": args.precision},
-        "converged": ok,
-        "max_res": float(res.max()),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": f"k_filter_spmm<{'double' if last['spmm_fp64'] else 'float'},"
-                      f"{last['spmm_cols_per_lane']}>",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
-            "launches": launches,
-            "avg_launch_us": spmm_ms * 1e3 / max(1, launches),
-            "algorithmic_bytes_per_launch": spmm_bytes / max(1, launches),
-        },
-        "solve": {key: last[key] for key in ("outer_iters", "arr_calls", "poly_calls", "final_p", "final_d",
-                                             "n_locked", "fp32_outer", "spmm_degrees", "spmm_cols", "t_total",
-                                             "t_setup", "t_filter", "t_arr", "t_dense")},
+        "config": {"workload": WORKLOAD, "precision": head_prec},
+        "converged": head["converged"],
+        "max_res": head["max_res"],
+        "roofline": head["roofline"],
+        "gemm": head["gemm"],
+        "solve": head["solve"],
     }
-    h.close()
+    if args.precision == "both":
+        mix = solve_run(A, k, w, tol, "mixed", args, "mixed")
+        rel = np.abs(mix["eigenvalues"] - head["eigenvalues"]) / np.abs(head["eigenvalues"])
+        out["mixed"] = {
+            "value": mix["value"], "ms_per_step": mix["ms_per_step"], "dtype": "f32+f64",
+            "speedup_vs_fp64": head["ms_per_step"] / mix["ms_per_step"], "converged": mix["converged"],
+            "max_res": mix["max_res"], "max_rel_eig_diff_vs_fp64_path": float(rel.max()),
+            "roofline": mix["roofline"], "gemm": mix["gemm"], "solve": mix["solve"],
+        }
+    out["accuracy_small_case"] = small_case_accuracy()
     if not args.no_cpu_baseline:
         # interval of the working operator (-A) as the solver estimated it
-        a_w, b_w = -last["a"], -last["b"]
-        out["cpu_baseline"] = cpu_baseline(A, k, w, int(last["spmm_cols"]), a_w, b_w)
+        a_w, b_w = -head["solve"]["a"], -head["solve"]["b"]
+        out["cpu_baseline"] = cpu_baseline(A, k, w, int(head["solve"]["spmm_cols"]), a_w, b_w)
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 8
     print(json.dumps(out), flush=True)
 
 

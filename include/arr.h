@@ -128,6 +128,15 @@ typedef struct {
   int32_t spmm_cols_per_lane; /* kernel variant: columns per lane (1, 2, 4, 8, 16) */
   int32_t spmm_fp64;          /* data type of that variant: 1 FP64, 0 FP32 */
   int32_t spmm_vec;           /* columns per lane load: 1, or 4 (16-byte FP32 loads) */
+  /* HIP-event timing (timing = 1) of the dense products: Gram products X^T Y
+   * (tile kernel plus its split reduction) and block updates X W. Work is
+   * counted in algorithmic flops: 2 n mx my, n m (m + 1) for a symmetric
+   * product (upper triangle), 2 n m c for an update (n m (m + 1) when W is
+   * upper triangular, as in Cholesky QR). "64" = FP64 matrix cores
+   * (FP64 data, or FP32 data widened exactly); "32" = FP32 matrix cores. */
+  int64_t gram64_launches, gram32_launches, upd64_launches, upd32_launches;
+  double gram64_ms, gram64_flops, gram32_ms, gram32_flops;
+  double upd64_ms, upd64_flops, upd32_ms, upd32_flops;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

@@ -69,7 +69,13 @@ class arr_stats_t(ctypes.Structure):
                 ("t_filter", ctypes.c_double), ("t_arr", ctypes.c_double), ("t_dense", ctypes.c_double),
                 ("spmm_launches", ctypes.c_int64), ("spmm_ms", ctypes.c_double), ("spmm_bytes", ctypes.c_double),
                 ("spmm_cols_per_lane", ctypes.c_int32), ("spmm_fp64", ctypes.c_int32),
-                ("spmm_vec", ctypes.c_int32)]
+                ("spmm_vec", ctypes.c_int32),
+                ("gram64_launches", ctypes.c_int64), ("gram32_launches", ctypes.c_int64),
+                ("upd64_launches", ctypes.c_int64), ("upd32_launches", ctypes.c_int64),
+                ("gram64_ms", ctypes.c_double), ("gram64_flops", ctypes.c_double),
+                ("gram32_ms", ctypes.c_double), ("gram32_flops", ctypes.c_double),
+                ("upd64_ms", ctypes.c_double), ("upd64_flops", ctypes.c_double),
+                ("upd32_ms", ctypes.c_double), ("upd32_flops", ctypes.c_double)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",

@@ -143,14 +143,15 @@ struct DevBuf {
 template <typename T>
 int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, double alpha,
                        double beta, double gamma, double *partial, hipStream_t s);
-// Optional HIP-event timing of filter SpMM launches, per kernel variant
-// (columns per lane). Installed per thread by the solver.
+// Optional HIP-event timing of kernel launches, per launch class, with the
+// algorithmic work of each launch (bytes for the SpMM, flops for the GEMMs).
+// Installed per thread by the solver. SpMM classes: columns per lane (0..4
+// for 1..16) + 5 for 16-byte loads + 10 for FP64 data. GEMM classes: see
+// GemmClass.
 struct SpmmTimer {
   struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
-  // launch class: columns per lane (0..4 for 1..16) + 5 for 16-byte loads
-  // + 10 for FP64 data
   static constexpr int kClasses = 20;
   int64_t launches[kClasses] = {};
   double ms[kClasses] = {}, bytes[kClasses] = {};
@@ -158,8 +159,19 @@ struct SpmmTimer {
   void flush();  // waits for the recorded events and accumulates
   void reset();
   ~SpmmTimer();
+  // brackets one launch on stream s (no-op on a null timer)
+  struct Scope {
+    SpmmTimer *t;
+    Pending p{};
+    hipStream_t s;
+    Scope(SpmmTimer *t_, int cls, double work, hipStream_t s_);
+    ~Scope();
+  };
 };
 SpmmTimer *&spmm_timer();
+// Timer of the Gram (X^T Y) and block-update (X W) launches.
+SpmmTimer *&gemm_timer();
+enum GemmClass { kGramF64 = 0, kGramF32 = 1, kGramF32Cores = 2, kUpdF64 = 3, kUpdF32 = 4, kUpdF32Cores = 5 };
 // Groups that launch_filter_spmm / launch_colsumsq use for n rows (sizes the
 // partial buffer: groups * w doubles).
 int spmm_groups(int64_t n);

@@ -306,6 +306,11 @@ void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *w
   }
   const GramPlan p = gram_plan(n, mx, my, sym);
   const dim3 grid(p.ntiles * p.nsplit);
+  // algorithmic flops: 2 n mx my, or n m (m + 1) for the upper triangle
+  const double flops = sym ? (double)n * mx * (mx + 1) : 2.0 * n * mx * my;
+  SpmmTimer::Scope scope(gemm_timer(),
+                         std::is_same<T, double>::value ? kGramF64 : (fp32_cores ? kGramF32Cores : kGramF32),
+                         flops, s);
   if (std::is_same<T, float>::value && fp32_cores)
     hipLaunchKernelGGL((k_gram<float, true>), grid, dim3(256), 0, s, n, (const float *)X.p, X.ld, mx,
                        (const float *)Y.p, Y.ld, my, p.ntx, p.nty, p.ntiles, sym ? 1 : 0, p.chunk, work);
@@ -328,6 +333,15 @@ void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int 
   const int64_t nrt = (n + 63) / 64;
   const int64_t bands_per_xcd = (nrt + kXcd - 1) / kXcd;
   const int64_t grid = bands_per_xcd * nct * kXcd;
+  // algorithmic flops: 2 n m c, or with W upper triangular 2 n sum_j min(m, j + 1)
+  double terms = (double)m * c;
+  if (w_upper) {
+    const double t = std::min(c, m);
+    terms = t * (t + 1) / 2 + (double)std::max(0, c - m) * m;
+  }
+  SpmmTimer::Scope scope(gemm_timer(),
+                         std::is_same<T, double>::value ? kUpdF64 : (fp32_cores ? kUpdF32Cores : kUpdF32),
+                         2.0 * n * terms, s);
   if (std::is_same<T, float>::value && fp32_cores)
     hipLaunchKernelGGL((k_update<float, true>), dim3((unsigned)grid), dim3(256), 0, s, n, (const float *)X.p, X.ld,
                        m, W, ldw, c, alpha, beta, (float *)Y.p, Y.ld, nct, nrt, w_upper ? 1 : 0);

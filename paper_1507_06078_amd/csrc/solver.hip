@@ -569,12 +569,18 @@ int Solver::solve() {
   ARR_HIP(hipSetDevice(o_.device));
   ensure_device();
   host_results_ = false;
-  SpmmTimer timer;
+  SpmmTimer timer, gtimer;
   struct Install {
-    SpmmTimer *prev;
-    explicit Install(SpmmTimer *t) : prev(spmm_timer()) { spmm_timer() = t; }
-    ~Install() { spmm_timer() = prev; }
-  } install(o_.timing ? &timer : nullptr);
+    SpmmTimer *prev, *gprev;
+    Install(SpmmTimer *t, SpmmTimer *g) : prev(spmm_timer()), gprev(gemm_timer()) {
+      spmm_timer() = t;
+      gemm_timer() = g;
+    }
+    ~Install() {
+      spmm_timer() = prev;
+      gemm_timer() = gprev;
+    }
+  } install(o_.timing ? &timer : nullptr, o_.timing ? &gtimer : nullptr);
   if (have_x0_)
     launch_copy<double>(n_, w_, B64_.Zb.as<double>(), B64_.ldz, x0_.as<double>(), w_, s_);
   else
@@ -630,6 +636,15 @@ int Solver::solve() {
     stats.spmm_cols_per_lane = 1 << (best % 5);
     stats.spmm_vec = (best % 10) >= 5 ? 4 : 1;
     stats.spmm_fp64 = best >= 10 ? 1 : 0;
+    gtimer.flush();
+    auto sum = [&](std::initializer_list<int> cls, int64_t &l, double &ms, double &fl) {
+      l = 0, ms = 0, fl = 0;
+      for (int c : cls) l += gtimer.launches[c], ms += gtimer.ms[c], fl += gtimer.bytes[c];
+    };
+    sum({kGramF64, kGramF32}, stats.gram64_launches, stats.gram64_ms, stats.gram64_flops);
+    sum({kGramF32Cores}, stats.gram32_launches, stats.gram32_ms, stats.gram32_flops);
+    sum({kUpdF64, kUpdF32}, stats.upd64_launches, stats.upd64_ms, stats.upd64_flops);
+    sum({kUpdF32Cores}, stats.upd32_launches, stats.upd32_ms, stats.upd32_flops);
   }
   stats.status = status;
   stats.a = which_ == ARR_SMALLEST_ALGEBRAIC ? -a_ : a_;

@@ -25,6 +25,7 @@
 //    waves of the same XCD (its L2), while all XCDs sweep the matrix together
 //    (small working set in the shared Infinity Cache).
 #include <algorithm>
+#include <exception>
 
 #include "common.h"
 
@@ -200,6 +201,34 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 SpmmTimer *&spmm_timer() {
   static thread_local SpmmTimer *t = nullptr;
   return t;
+}
+
+SpmmTimer *&gemm_timer() {
+  static thread_local SpmmTimer *t = nullptr;
+  return t;
+}
+
+SpmmTimer::Scope::Scope(SpmmTimer *t_, int cls, double work, hipStream_t s_) : t(t_), s(s_) {
+  if (!t) return;
+  p.a = t->get();
+  p.b = t->get();
+  p.cls = cls;
+  p.bytes = work;
+  ARR_HIP(hipEventRecord(p.a, s));
+}
+
+SpmmTimer::Scope::~Scope() {
+  if (!t) return;
+  // a launch that failed leaves the pair unrecorded: it is returned unused
+  if (hipEventRecord(p.b, s) == hipSuccess && !std::uncaught_exceptions()) {
+    try {
+      t->pending.push_back(p);
+      return;
+    } catch (...) {
+    }
+  }
+  t->pool.push_back(p.a);
+  t->pool.push_back(p.b);
 }
 
 hipEvent_t SpmmTimer::get() {

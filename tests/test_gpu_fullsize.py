@@ -1,0 +1,157 @@
+"""Parity at the full sizes of the workloads, in the launch configurations
+the solver uses there.
+
+* 3D Laplacian 100^3 + potential (n = 1e6, k = 200, block 240): whole solves,
+  FP64 and mixed, checked by properties that hold at any size: residuals
+  recomputed on the CPU in FP64, orthonormality, Weyl's bounds against the
+  closed-form Laplacian spectrum (0 <= V <= I), and FP64/mixed agreement.
+* Power-law graph (n = 2e6, rows up to ~2000 entries, block 600, FP32) and
+  the SBM normalized Laplacian (n = 4e6, block 1200, FP32 and FP64): one
+  filter degree on device-generated blocks, checked on sampled rows against
+  the definition evaluated in FP64 on the CPU; the block Gram (4e6 x 2400,
+  FP64) and block update on sampled entries.
+
+Device inputs come from torch's seeded generator; the CPU references use
+only the sampled rows read back from the device."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+from paper_1507_06078_amd import arr, workloads as W
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def lap3d():
+    return W.laplacian_3d(100, potential_seed=1)
+
+
+def _solve(A, precision):
+    o = arr.arr_options_default()
+    o.w = 240
+    o.precision = precision
+    h = arr.arr_create(A, A.n, 200, arr.SMALLEST, 1e-10, o)
+    st = arr.arr_solve(h)
+    ev, X, res = arr.arr_get_eigpairs(h, 200, A.n)
+    h.close()
+    return st, ev, X, res
+
+
+_fp64_evals = {}
+
+
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_lap3d_full_solve_properties(lap3d, precision):
+    A = lap3d
+    st, ev, X, res = _solve(A, precision)
+    assert st == arr.ARR_OK
+    S = A.to_scipy()
+    R = S @ X - X * ev[None, :]
+    r = np.linalg.norm(R, axis=0)
+    del R
+    assert np.all(r / np.maximum(1.0, np.abs(ev)) <= 1e-10 * 1.0001), r.max()
+    assert np.all(res <= 1e-10)
+    G = X.T @ X
+    assert np.abs(G - np.eye(200)).max() < 1e-9
+    L0 = W.laplacian_3d_eigenvalues(100)[:200]
+    assert np.all(ev >= L0 - 1e-10) and np.all(ev <= L0 + 1 + 1e-10)
+    assert np.all(np.diff(ev) >= -1e-12)
+    if precision == arr.FP64:
+        _fp64_evals["ev"] = ev
+    elif "ev" in _fp64_evals:
+        ref = _fp64_evals["ev"]
+        assert np.all(np.abs(ev - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref)))
+
+
+def _device_block(n, w, dtype, seed):
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    return torch.randn((n, w), generator=g, dtype=dtype, device="cuda")
+
+
+def _sampled_filter_check(A, Yd, Zd, Od, al, be, ga, rows, u):
+    rp, ci, va = A.rowptr, A.colind, A.val
+    if Yd.dtype == torch.float32:
+        va = va.astype(np.float32).astype(np.float64)
+    need = np.unique(np.concatenate([ci[rp[i]:rp[i + 1]] for i in rows] + [rows]))
+    pos = {int(j): t for t, j in enumerate(need)}
+    Yn = Yd[torch.as_tensor(need, device="cuda")].double().cpu().numpy()
+    ridx = torch.as_tensor(rows, device="cuda")
+    Zr = Zd[ridx].double().cpu().numpy()
+    got = Od[ridx].double().cpu().numpy()
+    for t, i in enumerate(rows):
+        cols, vals = ci[rp[i]:rp[i + 1]], va[rp[i]:rp[i + 1]]
+        G = Yn[[pos[int(j)] for j in cols]]
+        yi = Yn[pos[int(i)]]
+        ref = al * (vals @ G) + be * yi + ga * Zr[t]
+        bound = abs(al) * (np.abs(vals) @ np.abs(G)) + abs(be) * np.abs(yi) + abs(ga) * np.abs(Zr[t])
+        assert np.all(np.abs(got[t] - ref) <= (len(cols) + 4) * u * bound + 1e-30), (i, len(cols))
+
+
+def _filter_case(A, w, dtype, n_samples=256, seed=11):
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    Ad = arr.DeviceCSR(A, dtype=tdt)
+    Yd = _device_block(A.n, w, tdt, seed)
+    Zd = _device_block(A.n, w, tdt, seed + 1)
+    Od = torch.empty_like(Yd)
+    ss = torch.zeros(w, dtype=torch.float64, device="cuda")
+    al, be, ga = 0.4375, -1.125, 0.5  # exact in FP32
+    arr.arr_filter_step(Ad, Yd, Zd, Od, al, be, ga, colsumsq=ss)
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(A.n, n_samples, replace=False))
+    # always include the longest row and both ends
+    rows = np.unique(np.concatenate([rows, [0, A.n - 1, int(np.argmax(np.diff(A.rowptr)))]]))
+    _sampled_filter_check(A, Yd, Zd, Od, al, be, ga, rows, U32 if dtype == "f32" else U64)
+    # column norms of the whole output (FP64 sums of the stored values)
+    ref_ss = (Od.double() ** 2).sum(dim=0)
+    assert torch.allclose(ss, ref_ss, rtol=1e-10, atol=0)
+    del Yd, Zd, Od, Ad
+    torch.cuda.empty_cache()
+
+
+def test_powerlaw_2e6_filter_step_fp32_sampled():
+    A = W.powerlaw_random(2_000_000, seed=1)
+    _filter_case(A, 600, "f32")
+
+
+@pytest.fixture(scope="module")
+def sbm4m():
+    return W.sbm_normalized_laplacian(4_000_000, 64, seed=1)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sbm_4e6_filter_step_sampled(sbm4m, dtype):
+    _filter_case(sbm4m, 1200, dtype)
+
+
+def test_gram_and_update_4e6_x_2400_sampled():
+    n, m, c = 4_000_000, 2400, 1200
+    X = _device_block(n, m, torch.float64, 21)
+    G = torch.empty((m, m), dtype=torch.float64, device="cuda")
+    arr.arr_gram(X, X, G)
+    rng = np.random.default_rng(5)
+    pairs = [(int(i), int(j)) for i, j in rng.integers(0, m, size=(12, 2))] + [(0, 0), (m - 1, m - 1), (0, m - 1)]
+    Gh = G.cpu().numpy()
+    assert np.array_equal(Gh, Gh.T)
+    for i, j in pairs:
+        xi, xj = X[:, i].cpu().numpy(), X[:, j].cpu().numpy()
+        ref = float(xi @ xj)
+        bound = float(np.abs(xi) @ np.abs(xj))
+        assert abs(Gh[i, j] - ref) <= 2 * np.sqrt(n) * U64 * bound + 1e-300, (i, j)
+    # block update Y = X W (W m x c, FP64)
+    Wm = torch.randn((m, c), generator=torch.Generator(device="cuda").manual_seed(22), dtype=torch.float64,
+                     device="cuda")
+    del G
+    Y = torch.empty((n, c), dtype=torch.float64, device="cuda")
+    arr.arr_block_update(X, Wm, Y, alpha=1.0, beta=0.0)
+    rows = np.unique(np.concatenate([rng.choice(n, 64, replace=False), [0, n - 1]]))
+    ridx = torch.as_tensor(rows, device="cuda")
+    Xr, Yr, Wh = X[ridx].cpu().numpy(), Y[ridx].cpu().numpy(), Wm.cpu().numpy()
+    ref = Xr @ Wh
+    bound = np.abs(Xr) @ np.abs(Wh)
+    assert np.all(np.abs(Yr - ref) <= 2 * m * U64 * bound + 1e-300)
+    del X, Y, Wm
+    torch.cuda.empty_cache()
