@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("3D 7-point Laplacian 100^3 + U[0,1) diagonal potential (seed 1), n=1e6, nnz=6.94e6, "
             "k=200 smallest, block 240, tol 1e-10")
+WORKLOAD_POWERLAW = ("random symmetric, power-law row lengths (Pareto alpha 2.1, mean 16, cap 2048; seed 1), n=2e6, "
+                     "off-diagonal N(0,1), diagonal N(0,4), k=500 largest, block 600, tol 1e-10")
 
 
 def cpu_baseline(A, k, w, spmm_cols_per_solve, a, b):
@@ -172,7 +174,7 @@ def measured_traffic(kernel):
     return 1024.0 * (k["fetch_kib"] * rec["copy_fetch_factor"] + k["write_kib"] * rec["copy_write_factor"])
 
 
-def solve_run(A, k, w, tol, precision, args, label):
+def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     """Warmup + timed solves of one handle; returns the figures of the timed
     solves and the eigenvalues of the last one."""
     import torch
@@ -185,7 +187,7 @@ def solve_run(A, k, w, tol, precision, args, label):
     if args.mixed_switch is not None:
         o.mixed_switch = args.mixed_switch
     o.verbose = 1 if args.verbose else 0
-    h = arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o)
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, tol, o)
     print(f"[bench] {label}: handle ready (n={A.n}, nnz={A.nnz}); warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -274,6 +276,8 @@ def main():
     ap.add_argument("--mixed-switch", type=float, default=None)
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with three device copies of 2 GiB (reference kernel for counter scaling)")
+    ap.add_argument("--workload", choices=["lap3d100", "powerlaw2e6"], default="lap3d100",
+                    help="lap3d100: the headline workload; powerlaw2e6: the 2e6-row power-law graph")
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -299,10 +303,14 @@ def main():
                "serving": r}
         print(json.dumps(out), flush=True)
         return
-    A = W.laplacian_3d(100, potential_seed=1)
-    k, w, tol = 200, 240, 1e-10
+    if args.workload == "powerlaw2e6":
+        A = W.powerlaw_random(2_000_000, seed=1)
+        k, w, tol, which, workload = 500, 600, 1e-10, "LA", WORKLOAD_POWERLAW
+    else:
+        A = W.laplacian_3d(100, potential_seed=1)
+        k, w, tol, which, workload = 200, 240, 1e-10, "SA", WORKLOAD
     head_prec = "mixed" if args.precision == "mixed" else "fp64"
-    head = solve_run(A, k, w, tol, head_prec, args, head_prec)
+    head = solve_run(A, k, w, tol, head_prec, args, head_prec, which)
     out = {
         "metric": "converged eigenpairs/s at res<=1e-10",
         "value": head["value"],
@@ -316,7 +324,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "precision": head_prec},
+        "config": {"workload": workload, "precision": head_prec},
         "converged": head["converged"],
         "max_res": head["max_res"],
         "roofline": head["roofline"],
@@ -324,7 +332,7 @@ def main():
         "solve": head["solve"],
     }
     if args.precision == "both":
-        mix = solve_run(A, k, w, tol, "mixed", args, "mixed")
+        mix = solve_run(A, k, w, tol, "mixed", args, "mixed", which)
         rel = np.abs(mix["eigenvalues"] - head["eigenvalues"]) / np.abs(head["eigenvalues"])
         out["mixed"] = {
             "value": mix["value"], "ms_per_step": mix["ms_per_step"], "dtype": "f32+f64",
@@ -333,7 +341,7 @@ def main():
             "roofline": mix["roofline"], "gemm": mix["gemm"], "solve": mix["solve"],
         }
     out["accuracy_small_case"] = small_case_accuracy()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "lap3d100":
         # interval of the working operator (-A) as the solver estimated it
         a_w, b_w = -head["solve"]["a"], -head["solve"]["b"]
         out["cpu_baseline"] = cpu_baseline(A, k, w, int(head["solve"]["spmm_cols"]), a_w, b_w)

@@ -41,16 +41,22 @@ __device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
 }
 
 struct GramPlan {
-  int ntx, nty, ntiles, nsplit;
+  int tile, ntx, nty, ntiles, nsplit;
   int64_t chunk;
 };
 
 GramPlan gram_plan(int64_t n, int mx, int my, bool sym) {
   GramPlan p;
-  p.ntx = (mx + 63) / 64;
-  p.nty = (my + 63) / 64;
+  // 128 tiles (4x the work per row of a 64 tile) once both sides reach 128
+  p.tile = (mx >= 128 && my >= 128) ? 128 : 64;
+  p.ntx = (mx + p.tile - 1) / p.tile;
+  p.nty = (my + p.tile - 1) / p.tile;
   p.ntiles = sym ? p.ntx * (p.ntx + 1) / 2 : p.ntx * p.nty;
-  int64_t want = std::max<int64_t>(1, (2048 + p.ntiles - 1) / p.ntiles);
+  // Both tile kernels fit two workgroups per CU: 512 slots. Aim at four full
+  // rounds and round the split count down, so the last round is not a
+  // nearly empty tail.
+  const int64_t target = 4 * 512;
+  int64_t want = std::max<int64_t>(1, target / p.ntiles);
   // at least 256 rows per split so each wave streams a useful amount
   want = std::min<int64_t>(want, std::max<int64_t>(1, n / 256));
   p.nsplit = (int)want;
@@ -60,22 +66,29 @@ GramPlan gram_plan(int64_t n, int mx, int my, bool sym) {
   return p;
 }
 
-// Gram tile kernel. A workgroup owns a 64 x 64 output tile and a chunk of
-// rows; the rows stream through double-buffered LDS 32 at a time (each thread
-// moves 8 consecutive elements of X and of Y per step), and wave q accumulates
-// the 32 x 32 quadrant (q & 1, q >> 1) on the matrix cores, so no reduction
-// across waves is needed. Products run on the FP64 matrix cores (FP32 data are
-// widened exactly), except in the kMma32 variant: FP32 matrix cores over each
-// 32-row step, added into the FP64 accumulator after every step. That variant
-// is for well-conditioned products only (a Rayleigh quotient of an
-// orthonormal basis), where an FP32 rounding of each slice's sum is harmless.
-constexpr int kRS = 32;
-
-template <typename T, bool kMma32>
+// Gram tile kernel. A workgroup owns a TILE x TILE output tile (64 or 128)
+// and a chunk of rows; the rows stream through double-buffered LDS, KS at a
+// time (each thread moves 8 consecutive elements of X and of Y per stage), and
+// wave q accumulates the (TILE/2)-square quadrant (q & 1, q >> 1) on the
+// matrix cores as (TILE/32)^2 blocks of 16 x 16, so no reduction across waves
+// is needed. The 128 tiles halve the loads per flop; they serve products whose
+// sides are both at least 128. Products run on the FP64 matrix cores (FP32
+// data are widened exactly), except in the kMma32 variant: FP32 matrix cores
+// over each stage's KS rows, added into the FP64 accumulator after every
+// stage. That variant is for well-conditioned products only (a Rayleigh
+// quotient of an orthonormal basis), where an FP32 rounding of each slice's
+// sum is harmless.
+template <typename T, bool kMma32, int TILE>
 __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X, int64_t ldx, int mx,
                                               const T *__restrict__ Y, int64_t ldy, int my, int ntx, int nty,
                                               int ntiles, int sym, int64_t chunk, double *__restrict__ part) {
   static_assert(!kMma32 || std::is_same<T, float>::value, "FP32 matrix cores need FP32 data");
+  static_assert(TILE == 64 || TILE == 128, "tile is 64 or 128");
+  constexpr int KS = TILE == 64 ? 32 : 16;  // rows per stage
+  constexpr int FB = TILE / 32;             // 16 x 16 blocks per wave and dimension
+  constexpr int HALF = TILE / 2;
+  constexpr int PER = KS * TILE / 256;      // elements per thread and matrix per stage
+  static_assert(PER == 8, "8 elements per thread");
   const int tile = blockIdx.x % ntiles;
   const int split = blockIdx.x / ntiles;
   int tx, ty;
@@ -88,14 +101,13 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X
     tx = tile / nty;
     ty = tile % nty;
   }
-  const int cx = tx * 64, cy = ty * 64;
+  const int cx = tx * TILE, cy = ty * TILE;
   const int64_t r0 = (int64_t)split * chunk;
   const int64_t r1 = min(n, r0 + chunk);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
-  const int qx = (wv & 1) * 32, qy = (wv >> 1) * 32;
-  __shared__ T Xs[2][kRS][65], Ys[2][kRS][65];
-  constexpr int PER = kRS * 64 / 256;
-  const int lr = tid / (64 / PER), lc = (tid % (64 / PER)) * PER;
+  const int qx = (wv & 1) * HALF, qy = (wv >> 1) * HALF;
+  __shared__ T Xs[2][KS][TILE + 1], Ys[2][KS][TILE + 1];
+  const int lr = tid / (TILE / PER), lc = (tid % (TILE / PER)) * PER;
   T xv[PER], yv[PER];
   auto gload = [&](int64_t rb) {
     const int64_t row = rb + lr;
@@ -113,51 +125,59 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X
       Ys[b][lr][lc + q] = yv[q];
     }
   };
-  v4d acc[2][2];
+  v4d acc[FB][FB];
 #pragma unroll
-  for (int f = 0; f < 2; ++f)
+  for (int f = 0; f < FB; ++f)
 #pragma unroll
-    for (int g = 0; g < 2; ++g) acc[f][g] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < FB; ++g) acc[f][g] = v4d{0.0, 0.0, 0.0, 0.0};
   int buf = 0;
   if (r0 < r1) {
     gload(r0);
     lstore(0);
   }
   __syncthreads();
-  for (int64_t rb = r0; rb < r1; rb += kRS) {
-    const bool more = rb + kRS < r1;
-    if (more) gload(rb + kRS);
+  for (int64_t rb = r0; rb < r1; rb += KS) {
+    const bool more = rb + KS < r1;
+    if (more) gload(rb + KS);
     if constexpr (!kMma32) {
 #pragma unroll
-      for (int ks = 0; ks < kRS / 4; ++ks) {
-        const double a0 = (double)Xs[buf][4 * ks + lk][qx + li], a1 = (double)Xs[buf][4 * ks + lk][qx + 16 + li];
-        const double b0 = (double)Ys[buf][4 * ks + lk][qy + li], b1 = (double)Ys[buf][4 * ks + lk][qy + 16 + li];
-        acc[0][0] = mfma16(a0, b0, acc[0][0]);
-        acc[0][1] = mfma16(a0, b1, acc[0][1]);
-        acc[1][0] = mfma16(a1, b0, acc[1][0]);
-        acc[1][1] = mfma16(a1, b1, acc[1][1]);
+      for (int ks = 0; ks < KS / 4; ++ks) {
+        double a[FB], b[FB];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+          a[f] = (double)Xs[buf][4 * ks + lk][qx + 16 * f + li];
+          b[f] = (double)Ys[buf][4 * ks + lk][qy + 16 * f + li];
+        }
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+#pragma unroll
+          for (int g = 0; g < FB; ++g) acc[f][g] = mfma16(a[f], b[g], acc[f][g]);
       }
     } else {
-      v4f s[2][2];
+      v4f sl[FB][FB];
 #pragma unroll
-      for (int f = 0; f < 2; ++f)
+      for (int f = 0; f < FB; ++f)
 #pragma unroll
-        for (int g = 0; g < 2; ++g) s[f][g] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int g = 0; g < FB; ++g) sl[f][g] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < kRS / 4; ++ks) {
-        const float a0 = Xs[buf][4 * ks + lk][qx + li], a1 = Xs[buf][4 * ks + lk][qx + 16 + li];
-        const float b0 = Ys[buf][4 * ks + lk][qy + li], b1 = Ys[buf][4 * ks + lk][qy + 16 + li];
-        s[0][0] = mfma16f(a0, b0, s[0][0]);
-        s[0][1] = mfma16f(a0, b1, s[0][1]);
-        s[1][0] = mfma16f(a1, b0, s[1][0]);
-        s[1][1] = mfma16f(a1, b1, s[1][1]);
+      for (int ks = 0; ks < KS / 4; ++ks) {
+        float a[FB], b[FB];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+          a[f] = Xs[buf][4 * ks + lk][qx + 16 * f + li];
+          b[f] = Ys[buf][4 * ks + lk][qy + 16 * f + li];
+        }
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+#pragma unroll
+          for (int g = 0; g < FB; ++g) sl[f][g] = mfma16f(a[f], b[g], sl[f][g]);
       }
 #pragma unroll
-      for (int f = 0; f < 2; ++f)
+      for (int f = 0; f < FB; ++f)
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
+        for (int g = 0; g < FB; ++g)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[f][g][e] += (double)s[f][g][e];
+          for (int e = 0; e < 4; ++e) acc[f][g][e] += (double)sl[f][g][e];
     }
     if (more) lstore(buf ^ 1);
     __syncthreads();
@@ -165,9 +185,9 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X
   }
   double *out = part + (int64_t)split * mx * my;
 #pragma unroll
-  for (int f = 0; f < 2; ++f)
+  for (int f = 0; f < FB; ++f)
 #pragma unroll
-    for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < FB; ++g)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         // result layouts: FP64 MFMA row lk + 4e, FP32 MFMA row 4 lk + e
@@ -191,10 +211,17 @@ __global__ void k_gram_reduce(const double *__restrict__ part, int nsplit, int m
   G[idx] = s;
 }
 
-template <typename T, bool kMma32>
+// Block update tile kernel: a workgroup owns a TILE x TILE tile of Y (64, or
+// 128 for the FP32 matrix cores once Y has 128 columns: half the loads per
+// flop) and
+// walks k in steps of 16 through LDS with the next step prefetched into
+// registers; wave q accumulates the (TILE/2)-square quadrant (q & 1, q >> 1).
+template <typename T, bool kMma32, int TILE>
 __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__ X, int64_t ldx, int m,
                                                 const double *__restrict__ W, int64_t ldw, int c, double alpha,
                                                 double beta, T *Y, int64_t ldy, int nct, int64_t nrt, int w_upper) {
+  static_assert(TILE == 64 || TILE == 128, "tile is 64 or 128");
+  constexpr int FB = TILE / 32, HALF = TILE / 2, PER = TILE / 16;
   // tile order: XCD x gets workgroups b = x + 8 t; t walks the column tiles of
   // one row band before moving to the next band of that XCD.
   const int xcd = blockIdx.x % kXcd;
@@ -202,13 +229,12 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
   const int ct = (int)(t % nct);
   const int64_t rt = (t / nct) * kXcd + xcd;
   if (rt >= nrt) return;
-  const int64_t r0 = rt * 64;
-  const int c0 = ct * 64;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  // W upper triangular: rows k > c0 + 63 of this column tile are zero
-  const int kend = w_upper ? min(m, c0 + 64) : m;
+  const int64_t r0 = rt * TILE;
+  const int c0 = ct * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int qx = (wv & 1) * HALF, qy = (wv >> 1) * HALF;
+  // W upper triangular: rows k >= c0 + TILE of this column tile are zero
+  const int kend = w_upper ? min(m, c0 + TILE) : m;
 
   // FP64 matrix cores (FP32 data widened exactly, W kept in FP64), except in
   // the kMma32 variant for FP32 data times a well-conditioned W (an
@@ -216,20 +242,22 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
   static_assert(!kMma32 || std::is_same<T, float>::value, "FP32 matrix cores need FP32 data");
   typedef typename std::conditional<kMma32, float, double>::type S;
   typedef typename std::conditional<kMma32, v4f, v4d>::type acc_t;
-  __shared__ S Xs[64][17];
-  __shared__ S Ws[16][65];
+  __shared__ S Xs[TILE][17];
+  __shared__ S Ws[16][TILE + 1];
 
-  acc_t acc[4];
+  acc_t acc[FB][FB];
 #pragma unroll
-  for (int g = 0; g < 4; ++g) acc[g] = acc_t{0, 0, 0, 0};
+  for (int f = 0; f < FB; ++f)
+#pragma unroll
+    for (int g = 0; g < FB; ++g) acc[f][g] = acc_t{0, 0, 0, 0};
 
-  const int xr_ = threadIdx.x >> 2, xk = (threadIdx.x & 3) * 4;   // X tile: 64 rows x 16 k
-  const int wk_ = threadIdx.x >> 4, wc = (threadIdx.x & 15) * 4;  // W tile: 16 k x 64 cols
+  const int xr_ = tid / (16 / PER), xk = (tid % (16 / PER)) * PER;  // X tile: TILE rows x 16 k
+  const int wk_ = tid / 16, wc = (tid % 16) * PER;                  // W tile: 16 k x TILE cols
   const int64_t xrow = r0 + xr_;
-  S xv[4], wvv[4];
+  S xv[PER], wvv[PER];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PER; ++q) {
       const int kk = k0 + xk + q;
       xv[q] = (xrow < n && kk < kend) ? (S)X[xrow * ldx + kk] : S(0);
       const int kw = k0 + wk_, cc = c0 + wc + q;
@@ -239,7 +267,7 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
   if (kend > 0) load(0);
   for (int k0 = 0; k0 < kend; k0 += 16) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PER; ++q) {
       Xs[xr_][xk + q] = xv[q];
       Ws[wk_][wc + q] = wvv[q];
     }
@@ -247,39 +275,49 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
     if (k0 + 16 < kend) load(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      const S a = Xs[16 * wv + li][4 * ks + lk];
+      S a[FB], b[FB];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        if constexpr (kMma32)
-          acc[g] = mfma16f(a, Ws[4 * ks + lk][16 * g + li], acc[g]);
-        else
-          acc[g] = mfma16(a, Ws[4 * ks + lk][16 * g + li], acc[g]);
+      for (int f = 0; f < FB; ++f) {
+        a[f] = Xs[qx + 16 * f + li][4 * ks + lk];
+        b[f] = Ws[4 * ks + lk][qy + 16 * f + li];
       }
+#pragma unroll
+      for (int f = 0; f < FB; ++f)
+#pragma unroll
+        for (int g = 0; g < FB; ++g) {
+          if constexpr (kMma32)
+            acc[f][g] = mfma16f(a[f], b[g], acc[f][g]);
+          else
+            acc[f][g] = mfma16(a[f], b[g], acc[f][g]);
+        }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int col = c0 + 16 * g + li;
-    if (col >= c) continue;
+  for (int f = 0; f < FB; ++f)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t row = r0 + 16 * wv + (kMma32 ? 4 * lk + e : lk + 4 * e);
-      if (row >= n) continue;
-      T *yp = Y + row * ldy + col;
-      double v = alpha * (double)acc[g][e];
-      if (beta != 0.0) v += beta * (double)(*yp);
-      *yp = (T)v;
+    for (int g = 0; g < FB; ++g) {
+      const int col = c0 + qy + 16 * g + li;
+      if (col >= c) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + qx + 16 * f + (kMma32 ? 4 * lk + e : lk + 4 * e);
+        if (row >= n) continue;
+        T *yp = Y + row * ldy + col;
+        double v = alpha * (double)acc[f][g][e];
+        if (beta != 0.0) v += beta * (double)(*yp);
+        *yp = (T)v;
+      }
     }
-  }
 }
 
 }  // namespace
 
 size_t gram_work_bound(int64_t n, int m_max) {
-  // nsplit <= ceil(2048 / ntiles) and mx * my <= 4096 * tx * ty, so the partial
-  // tiles of any product with mx, my <= m_max fit in (4096 + t^2) 64 x 64
-  // tiles; nsplit is also at most max(1, n / 256).
+  // nsplit <= max(1, 2048 / ntiles), ntiles >= t'^2 / 2 for tiles of side T
+  // (t' = ceil(m / T)) and mx * my <= m_max^2 <= 4096 t^2 with t = ceil(m /
+  // 64), so the partial tiles fit in (4096 + t^2) 64 x 64 tiles; nsplit is
+  // also at most max(1, n / 256).
   const size_t t = (size_t)(m_max + 63) / 64;
   const size_t by_tiles = (4096 + t * t) * 4096;
   const size_t by_rows = (size_t)std::max<int64_t>(1, n / 256) * t * t * 4096;
@@ -306,17 +344,28 @@ void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *w
   }
   const GramPlan p = gram_plan(n, mx, my, sym);
   const dim3 grid(p.ntiles * p.nsplit);
+  const bool big = p.tile == 128;
   // algorithmic flops: 2 n mx my, or n m (m + 1) for the upper triangle
   const double flops = sym ? (double)n * mx * (mx + 1) : 2.0 * n * mx * my;
   SpmmTimer::Scope scope(gemm_timer(),
                          std::is_same<T, double>::value ? kGramF64 : (fp32_cores ? kGramF32Cores : kGramF32),
                          flops, s);
-  if (std::is_same<T, float>::value && fp32_cores)
-    hipLaunchKernelGGL((k_gram<float, true>), grid, dim3(256), 0, s, n, (const float *)X.p, X.ld, mx,
-                       (const float *)Y.p, Y.ld, my, p.ntx, p.nty, p.ntiles, sym ? 1 : 0, p.chunk, work);
-  else
-    hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(256), 0, s, n, X.p, X.ld, mx, Y.p, Y.ld, my, p.ntx, p.nty,
-                       p.ntiles, sym ? 1 : 0, p.chunk, work);
+  const int sy = sym ? 1 : 0;
+  if (std::is_same<T, float>::value && fp32_cores) {
+    const float *xf = (const float *)X.p, *yf = (const float *)Y.p;
+    if (big)
+      hipLaunchKernelGGL((k_gram<float, true, 128>), grid, dim3(256), 0, s, n, xf, X.ld, mx, yf, Y.ld, my, p.ntx,
+                         p.nty, p.ntiles, sy, p.chunk, work);
+    else
+      hipLaunchKernelGGL((k_gram<float, true, 64>), grid, dim3(256), 0, s, n, xf, X.ld, mx, yf, Y.ld, my, p.ntx,
+                         p.nty, p.ntiles, sy, p.chunk, work);
+  } else if (big) {
+    hipLaunchKernelGGL((k_gram<T, false, 128>), grid, dim3(256), 0, s, n, X.p, X.ld, mx, Y.p, Y.ld, my, p.ntx,
+                       p.nty, p.ntiles, sy, p.chunk, work);
+  } else {
+    hipLaunchKernelGGL((k_gram<T, false, 64>), grid, dim3(256), 0, s, n, X.p, X.ld, mx, Y.p, Y.ld, my, p.ntx,
+                       p.nty, p.ntiles, sy, p.chunk, work);
+  }
   ARR_HIP(hipGetLastError());
   const int64_t tot = (int64_t)mx * my;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, p.nsplit, mx,
@@ -329,10 +378,6 @@ void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int 
                    Blk<T> Y, hipStream_t s, bool w_upper, bool fp32_cores) {
   const int m = X.w;
   if (n == 0 || c == 0) return;
-  const int nct = (c + 63) / 64;
-  const int64_t nrt = (n + 63) / 64;
-  const int64_t bands_per_xcd = (nrt + kXcd - 1) / kXcd;
-  const int64_t grid = bands_per_xcd * nct * kXcd;
   // algorithmic flops: 2 n m c, or with W upper triangular 2 n sum_j min(m, j + 1)
   double terms = (double)m * c;
   if (w_upper) {
@@ -342,12 +387,28 @@ void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int 
   SpmmTimer::Scope scope(gemm_timer(),
                          std::is_same<T, double>::value ? kUpdF64 : (fp32_cores ? kUpdF32Cores : kUpdF32),
                          2.0 * n * terms, s);
-  if (std::is_same<T, float>::value && fp32_cores)
-    hipLaunchKernelGGL((k_update<float, true>), dim3((unsigned)grid), dim3(256), 0, s, n, (const float *)X.p, X.ld,
-                       m, W, ldw, c, alpha, beta, (float *)Y.p, Y.ld, nct, nrt, w_upper ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_update<T, false>), dim3((unsigned)grid), dim3(256), 0, s, n, X.p, X.ld, m, W, ldw, c,
-                       alpha, beta, Y.p, Y.ld, nct, nrt, w_upper ? 1 : 0);
+  // 128 tiles only for the FP32 matrix cores: with FP64 accumulators the
+  // 128 tile needs a whole SIMD per wave and ran at half the 64 tile's rate
+  const bool cores32 = std::is_same<T, float>::value && fp32_cores;
+  const int tile = (cores32 && c >= 128) ? 128 : 64;
+  const int nct = (c + tile - 1) / tile;
+  const int64_t nrt = (n + tile - 1) / tile;
+  const int64_t bands_per_xcd = (nrt + kXcd - 1) / kXcd;
+  const dim3 grid((unsigned)(bands_per_xcd * nct * kXcd));
+  const int wu = w_upper ? 1 : 0;
+  if (cores32) {
+    const float *xf = (const float *)X.p;
+    float *yf = (float *)Y.p;
+    if (tile == 128)
+      hipLaunchKernelGGL((k_update<float, true, 128>), grid, dim3(256), 0, s, n, xf, X.ld, m, W, ldw, c, alpha,
+                         beta, yf, Y.ld, nct, nrt, wu);
+    else
+      hipLaunchKernelGGL((k_update<float, true, 64>), grid, dim3(256), 0, s, n, xf, X.ld, m, W, ldw, c, alpha,
+                         beta, yf, Y.ld, nct, nrt, wu);
+  } else {
+    hipLaunchKernelGGL((k_update<T, false, 64>), grid, dim3(256), 0, s, n, X.p, X.ld, m, W, ldw, c, alpha, beta,
+                       Y.p, Y.ld, nct, nrt, wu);
+  }
   ARR_HIP(hipGetLastError());
 }
 

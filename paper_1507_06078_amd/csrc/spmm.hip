@@ -138,8 +138,15 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
         if (c < w) {
           vec o = alpha * acc[t];
           if (beta != T(0)) o += beta * w0[t];
-          if (zi) o += gamma * *(const vec *)(zi + c);
-          *(vec *)(oi + c) = o;
+          if constexpr (VEC == 1) {
+            // Z and Yout are touched once per launch: streaming hints keep
+            // them from displacing gathered Yin rows in L2
+            if (zi) o += gamma * __builtin_nontemporal_load(zi + c);
+            __builtin_nontemporal_store(o, oi + c);
+          } else {
+            if (zi) o += gamma * *(const vec *)(zi + c);
+            *(vec *)(oi + c) = o;
+          }
 #pragma unroll
           for (int v = 0; v < VEC; ++v) {
             const double ov = lane_elem<VEC>(o, v);

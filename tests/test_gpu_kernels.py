@@ -145,7 +145,8 @@ def test_poly_fp32_error_is_small():
     assert err < 1e-4, err
 
 
-@pytest.mark.parametrize("n,mx,my", [(5003, 1, 1), (5003, 17, 65), (777, 64, 64), (20011, 130, 200), (33, 5, 3)])
+@pytest.mark.parametrize("n,mx,my", [(5003, 1, 1), (5003, 17, 65), (777, 64, 64), (20011, 130, 200), (33, 5, 3),
+                                     (4099, 300, 300), (3001, 257, 128), (100, 128, 129)])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f32cores"])
 def test_gram(n, mx, my, dtype):
     rng = np.random.default_rng(n + mx)
