@@ -60,7 +60,8 @@ def cpu_baseline(A, k, w, spmm_cols_per_solve, a, b):
             "seconds_measured": dt}
 
 
-def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slots=8, budget=0, verbose=False):
+def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slots=8, budget=0, verbose=False,
+                  precision="mixed"):
     """Served workload: Poisson arrivals (exponential gaps, mean 1/rate); each
     request is a 2D or 3D (prob. 1/2) Laplacian plus a U[0,1) potential with n
     log-uniform in n_range (n = m^2 or m^3), k ~ U{10..200}, block
@@ -90,7 +91,7 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
         w = k + max(10, int(round(0.2 * k)))
         o = arr.arr_options_default()
         o.w = w
-        o.precision = arr.MIXED
+        o.precision = arr.MIXED if precision == "mixed" else arr.FP64
         o.seed = 2000 + i
         o.keep_vectors = 0
         handles.append(arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o))
@@ -131,6 +132,11 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
         if ok:
             _, _, r = arr.arr_get_eigpairs(h, ks[i], ns[i], vectors=False)
             ok = bool(r.max() <= tols[i])
+            if verbose and (status[i] != 0 or not ok):
+                st = arr.arr_get_stats(h)
+                print(f"[serve] request {i}: n {ns[i]} k {ks[i]} tol {tols[i]:g} status {status[i]} "
+                      f"maxres {r.max():.2e} outer {st['outer_iters']} fp32_outer {st['fp32_outer']}",
+                      file=sys.stderr, flush=True)
         res_ok.append(ok)
         h.close()
     tight = np.array([t <= 1e-10 for t in tols])
@@ -144,7 +150,8 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
         "requests_per_s": n_requests / makespan,
         "eigenpairs_per_s": float(k_arr[conv].sum() / makespan),
         "eigenpairs_per_s_tol1e-10": float(k_arr[conv & tight].sum() / makespan),
-        "n_median": float(np.median(ns)), "build_s": t_build,
+        "n_median": float(np.median(ns)), "build_s": t_build, "precision": precision,
+        "busy_s": float(np.sum(times[:, 2] - times[:, 1])),
     }
 
 
@@ -281,6 +288,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-compare", action="store_true",
+                    help="also run the same stream on the plain FP64 path, one request at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -294,6 +303,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serve:
         r = served_stream(n_requests=args.serve_requests, max_slots=args.serve_slots, verbose=args.verbose)
+        if args.serve_compare:
+            r64 = served_stream(n_requests=args.serve_requests, max_slots=1, verbose=args.verbose,
+                                precision="fp64")
+            r["fp64_one_at_a_time"] = r64
+            r["speedup_vs_fp64_one_at_a_time"] = r64["makespan_s"] / r["makespan_s"]
         out = {"metric": "served p50/p99 latency", "value": r["latency_p50_s"], "unit": "s", "n_gpus": 1,
                "steps": 1, "warmup": 0, "ms_per_step": r["makespan_s"] * 1e3, "higher_is_better": False,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",

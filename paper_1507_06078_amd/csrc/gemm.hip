@@ -40,6 +40,8 @@ __device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+constexpr int64_t kGramWorkCap = int64_t(1) << 24;  // doubles of split partials (128 MiB)
+
 struct GramPlan {
   int tile, ntx, nty, ntiles, nsplit;
   int64_t chunk;
@@ -53,12 +55,17 @@ GramPlan gram_plan(int64_t n, int mx, int my, bool sym) {
   p.nty = (my + p.tile - 1) / p.tile;
   p.ntiles = sym ? p.ntx * (p.ntx + 1) / 2 : p.ntx * p.nty;
   // Both tile kernels fit two workgroups per CU: 512 slots. Aim at four full
-  // rounds and round the split count down, so the last round is not a
-  // nearly empty tail.
+  // rounds and round the split count down to whole rounds, so the last round
+  // is not a nearly empty tail.
   const int64_t target = 4 * 512;
   int64_t want = std::max<int64_t>(1, target / p.ntiles);
+  // the partial tiles stay within kGramWorkCap doubles (or one product)
+  want = std::min<int64_t>(want, std::max<int64_t>(1, kGramWorkCap / ((int64_t)mx * my)));
   // at least 256 rows per split so each wave streams a useful amount
   want = std::min<int64_t>(want, std::max<int64_t>(1, n / 256));
+  // whole rounds of the 512 slots once there is more than one
+  const int64_t rounds = (int64_t)p.ntiles * want / 512;
+  if (rounds >= 1) want = std::max<int64_t>(1, rounds * 512 / p.ntiles);
   p.nsplit = (int)want;
   p.chunk = round_up((n + p.nsplit - 1) / p.nsplit, 16);
   if (p.chunk == 0) p.chunk = 16;
@@ -314,14 +321,12 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
 }  // namespace
 
 size_t gram_work_bound(int64_t n, int m_max) {
-  // nsplit <= max(1, 2048 / ntiles), ntiles >= t'^2 / 2 for tiles of side T
-  // (t' = ceil(m / T)) and mx * my <= m_max^2 <= 4096 t^2 with t = ceil(m /
-  // 64), so the partial tiles fit in (4096 + t^2) 64 x 64 tiles; nsplit is
-  // also at most max(1, n / 256).
-  const size_t t = (size_t)(m_max + 63) / 64;
-  const size_t by_tiles = (4096 + t * t) * 4096;
-  const size_t by_rows = (size_t)std::max<int64_t>(1, n / 256) * t * t * 4096;
-  return std::min(by_tiles, by_rows);
+  // nsplit * mx * my <= max(kGramWorkCap, mx * my) by the cap in gram_plan,
+  // and nsplit <= max(1, n / 256).
+  const size_t mm = (size_t)m_max * (size_t)m_max;
+  const size_t by_cap = std::max<size_t>((size_t)kGramWorkCap, mm);
+  const size_t by_rows = (size_t)std::max<int64_t>(1, n / 256) * mm;
+  return std::min(by_cap, by_rows);
 }
 
 size_t gram_work_doubles(int64_t n, int mx, int my) {

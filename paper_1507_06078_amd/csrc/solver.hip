@@ -501,7 +501,11 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       return status;
     }
     // ---- continuation (eq. contin) ----
-    if (maxres <= tol_t_) {
+    // Not in the FP32 stage: its residuals cannot reach the deflation
+    // threshold tol_t^2, so moving b up to mu_w there, with nothing locked,
+    // lets the filter amplify the leading directions until the block loses
+    // rank in the next sweep. b and tol_t move in the FP64 stage only.
+    if (!fp32_stage && maxres <= tol_t_) {
       tol_t_ = std::max(1e-2 * tol_t_, tol_);
       b_ = mu[w - 1];
     }

@@ -107,3 +107,26 @@ def test_served_without_vectors_keeps_values():
         arr.arr_get_eigpairs(h, 10, A.n, vectors=True)
     srv.close()
     h.close()
+
+
+def test_served_wide_block_stays_within_its_footprint():
+    """A request whose Gram products split many ways (n = 91125, block 240,
+    Krylov width up to 960): every pooled buffer stays inside the footprint
+    the server reserved, and the result equals the unserved solve."""
+    A = W.laplacian_3d(45, potential_seed=11)
+    k, w = 200, 240
+    o = arr.arr_options_default()
+    o.w = w
+    o.precision = arr.MIXED
+    h0 = arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-8, o)
+    st0 = arr.arr_solve(h0)
+    ev0, _, res0 = arr.arr_get_eigpairs(h0, k, A.n, vectors=False)
+    h0.close()
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-8, o)
+    srv = arr.Server(hbm_budget_bytes=arr.arr_footprint(h) + (1 << 20), max_slots=1)
+    st = srv.wait(srv.submit(h))
+    srv.close()
+    assert st == st0 == arr.ARR_OK
+    ev, _, res = arr.arr_get_eigpairs(h, k, A.n, vectors=False)
+    assert np.array_equal(ev, ev0) and np.array_equal(res, res0)
+    h.close()
