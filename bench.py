@@ -230,7 +230,17 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
         return {"achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak, "launches": n,
                 "avg_launch_us": ms * 1e3 / n, "algorithmic_flops_per_launch": fl / n}
 
+    roof32 = None
+    ms32, b32, l32 = tot("spmm32_ms"), tot("spmm32_bytes"), tot("spmm32_launches")
+    if precision == "mixed" and l32:
+        a32 = b32 / (ms32 * 1e-3) / 1e9
+        v32 = last["spmm32_vec"]
+        k32 = f"k_filter_spmm<float, {v32}, {max(1, last['spmm32_cols_per_lane'] // v32)}>"
+        roof32 = {"bound": "hbm", "kernel": k32, "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": a32 / HBM_PEAK_GBS, "traffic": measured_traffic(k32), "launches": l32,
+                  "avg_launch_us": ms32 * 1e3 / l32, "algorithmic_bytes_per_launch": b32 / l32}
     return {
+        "roofline_fp32_stage": roof32,
         "value": (k / sec) if ok else 0.0, "ms_per_step": sec * 1e3, "converged": ok,
         "max_res": float(res.max()), "eigenvalues": ev,
         "roofline": {
@@ -342,6 +352,7 @@ def main():
         "converged": head["converged"],
         "max_res": head["max_res"],
         "roofline": head["roofline"],
+        "roofline_fp32_stage": head["roofline_fp32_stage"],
         "gemm": head["gemm"],
         "solve": head["solve"],
     }
@@ -352,7 +363,8 @@ def main():
             "value": mix["value"], "ms_per_step": mix["ms_per_step"], "dtype": "f32+f64",
             "speedup_vs_fp64": head["ms_per_step"] / mix["ms_per_step"], "converged": mix["converged"],
             "max_res": mix["max_res"], "max_rel_eig_diff_vs_fp64_path": float(rel.max()),
-            "roofline": mix["roofline"], "gemm": mix["gemm"], "solve": mix["solve"],
+            "roofline": mix["roofline"], "roofline_fp32_stage": mix["roofline_fp32_stage"], "gemm": mix["gemm"],
+            "solve": mix["solve"],
         }
     out["accuracy_small_case"] = small_case_accuracy()
     if not args.no_cpu_baseline and args.workload == "lap3d100":

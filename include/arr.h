@@ -135,8 +135,12 @@ typedef struct {
    * upper triangular, as in Cholesky QR). "64" = FP64 matrix cores
    * (FP64 data, or FP32 data widened exactly); "32" = FP32 matrix cores. */
   int64_t gram64_launches, gram32_launches, upd64_launches, upd32_launches;
+  /* the most time-consuming FP32 SpMM variant alone (ARR_MIXED), as above */
   double gram64_ms, gram64_flops, gram32_ms, gram32_flops;
   double upd64_ms, upd64_flops, upd32_ms, upd32_flops;
+  int64_t spmm32_launches;
+  double spmm32_ms, spmm32_bytes;
+  int32_t spmm32_cols_per_lane, spmm32_vec;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

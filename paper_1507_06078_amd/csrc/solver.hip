@@ -640,6 +640,14 @@ int Solver::solve() {
     stats.spmm_cols_per_lane = 1 << (best % 5);
     stats.spmm_vec = (best % 10) >= 5 ? 4 : 1;
     stats.spmm_fp64 = best >= 10 ? 1 : 0;
+    int best32 = 0;
+    for (int c = 1; c < 10; ++c)
+      if (timer.ms[c] > timer.ms[best32]) best32 = c;
+    stats.spmm32_launches = timer.launches[best32];
+    stats.spmm32_ms = timer.ms[best32];
+    stats.spmm32_bytes = timer.bytes[best32];
+    stats.spmm32_cols_per_lane = 1 << (best32 % 5);
+    stats.spmm32_vec = best32 >= 5 ? 4 : 1;
     gtimer.flush();
     auto sum = [&](std::initializer_list<int> cls, int64_t &l, double &ms, double &fl) {
       l = 0, ms = 0, fl = 0;
