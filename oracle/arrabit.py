@@ -89,6 +89,30 @@ def shifted(A: sp.spmatrix, a: float) -> Callable[[np.ndarray], np.ndarray]:
 
 
 # --------------------------------------------------------------------------
+# Section 4 (A Gauss-Newton Algorithm) and the GN branch of Algorithm 8
+# --------------------------------------------------------------------------
+
+
+def gn_update(X: np.ndarray, rho_op: Callable[[np.ndarray], np.ndarray]) -> np.ndarray:
+    """One Gauss-Newton iteration with unit step for the least-squares fit of
+    X X^T to rho(A) (the GN algorithm of Sec. 4, as Algorithm 8 calls it):
+    Y = X (X^T X)^{-1}, Z = rho(A) Y, X+ = Z - X (Y^T Z - I) / 2.
+    ``rho_op`` applies rho(A) to a block."""
+    G = X.T @ X
+    Y = np.linalg.solve(G, X.T).T  # X G^{-1}; G is symmetric
+    Z = rho_op(Y)
+    C = Y.T @ Z
+    return Z - X @ (C - np.eye(C.shape[0])) / 2.0
+
+
+def gn_step(Aop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, a: float, b: float,
+            gam: np.ndarray) -> np.ndarray:
+    """The GN inner iteration of Algorithm 8: rho is Algorithm 7's poly on the
+    shifted operator over [a, b] with coefficients gam."""
+    return gn_update(X, lambda Y: poly(Aop, Y, a, b, gam))
+
+
+# --------------------------------------------------------------------------
 # Section 6: inner-loop quantities
 # --------------------------------------------------------------------------
 
@@ -241,6 +265,7 @@ class Options:
     lanczos_steps: int = 100
     stagnation: int = 3    # stop rule (ii)
     paper_faithful: bool = False  # stop rule (iii)
+    inner: str = "mpm"     # inner solver of Algorithm 8: "mpm" or "gn"
 
 
 @dataclasses.dataclass
@@ -264,7 +289,8 @@ def first_tolerance(tol: float, opts: Options) -> float:
 
 def arrabit_mpm(A: sp.spmatrix, k: int, tol: float, X0: np.ndarray, which: str = "LA",
                 opts: Options | None = None) -> Result:
-    """Algorithm 8 (ARRABIT, detailed version) with the MPM inner solver.
+    """Algorithm 8 (ARRABIT, detailed version) with the MPM inner solver, or
+    with the GN inner solver when ``opts.inner == "gn"``.
 
     Computes the k algebraically largest ('LA') or smallest ('SA') eigenpairs of
     symmetric A. Reading: 'SA' is solved as 'LA' of -A. ``X0`` (n x (k+q)) is
@@ -311,11 +337,15 @@ def arrabit_mpm(A: sp.spmatrix, k: int, tol: float, X0: np.ndarray, which: str =
         Qp = Qc if Qc.shape[1] else None
         for _i1 in range(opts.maxit1):
             for _i2 in range(opts.maxit2):
-                X = poly(opB, X, 0.0, b - a, coeffs(d))
+                if opts.inner == "gn":
+                    # GN branch: no normalization; X X^T tracks rho(A - aI)
+                    X = gn_step(opB, X, 0.0, b - a, coeffs(d))
+                else:
+                    X = poly(opB, X, 0.0, b - a, coeffs(d))
+                    X = normalize_columns(X)
                 stats["poly_calls"] += 1
                 stats["spmm_degrees"] += d
                 stats["block_spmm_cols"] += d * X.shape[1]
-                X = normalize_columns(X)
                 X = project_out(Qp, X)
             rcp = rc
             rc = rcond_gram(X)
