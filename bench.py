@@ -194,6 +194,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     if args.mixed_switch is not None:
         o.mixed_switch = args.mixed_switch
     o.verbose = 1 if args.verbose else 0
+    o.inner_solver = arr.INNER_GN if args.inner == "gn" else arr.INNER_MPM
     h = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, tol, o)
     print(f"[bench] {label}: handle ready (n={A.n}, nnz={A.nnz}); warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
@@ -293,6 +294,8 @@ def main():
     ap.add_argument("--mixed-switch", type=float, default=None)
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with three device copies of 2 GiB (reference kernel for counter scaling)")
+    ap.add_argument("--inner", choices=["mpm", "gn"], default="mpm",
+                    help="inner solver of Algorithm 8: multi-power (default) or Gauss-Newton")
     ap.add_argument("--workload", choices=["lap3d100", "powerlaw2e6"], default="lap3d100",
                     help="lap3d100: the headline workload; powerlaw2e6: the 2e6-row power-law graph")
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
@@ -348,7 +351,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": workload, "precision": head_prec},
+        "config": {"workload": workload, "precision": head_prec, "inner_solver": args.inner},
         "converged": head["converged"],
         "max_res": head["max_res"],
         "roofline": head["roofline"],

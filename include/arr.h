@@ -55,6 +55,12 @@ typedef enum { ARR_LARGEST_ALGEBRAIC = 0, ARR_SMALLEST_ALGEBRAIC = 1 } arr_which
  * FP64 Gram accumulation), then FP64 closing iterations down to tol. */
 typedef enum { ARR_FP64 = 0, ARR_MIXED = 1 } arr_precision_t;
 
+/* Inner solver of Algorithm 8 (the subspace update between ARR projections):
+ * ARR_INNER_MPM, the multi-power method (Sec. 3: filter, then normalize the
+ * columns); ARR_INNER_GN, the Gauss-Newton iteration of Sec. 4 with unit step
+ * (Y = X (X^T X)^{-1}, Z = rho(A) Y, X = Z - X (Y^T Z - I)/2). */
+typedef enum { ARR_INNER_MPM = 0, ARR_INNER_GN = 1 } arr_inner_t;
+
 /* Host CSR description (arr_create deep-copies it to the device). */
 typedef struct {
   int64_t n;             /* order of A                                   */
@@ -97,6 +103,7 @@ typedef struct {
   int32_t verbose;       /* 1: one line per outer iteration on stderr                      */
   int32_t timing;        /* 1: time filter SpMM launches with HIP events (stats)           */
   int32_t keep_vectors;  /* served requests: keep eigenvectors on the host (default 1)    */
+  int32_t inner_solver;  /* arr_inner_t, default ARR_INNER_MPM                              */
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -241,6 +248,16 @@ int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t 
  * Temporary device memory is allocated internally. Synchronous. */
 int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo,
              double hi, const double *gamma, int32_t d, void *stream);
+
+/* One Gauss-Newton inner iteration (Sec. 4 with unit step, the GN branch of
+ * Algorithm 8) with rho = poly(A - shift I, ., lo, hi, Gamma_d):
+ *   Y = X (X^T X)^{-1},  Z = rho(A) Y,  X <- Z - X (Y^T Z - I) / 2.
+ * X is a device block n x w (ld, A's dtype), overwritten; w >= 1. X^T X is
+ * formed with FP64 sums and inverted through its FP64 Cholesky factor;
+ * ARR_EBREAKDOWN if it is not numerically positive definite. Temporary
+ * device memory (4 n x w blocks) is allocated internally. Synchronous. */
+int arr_gn_step(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo,
+                double hi, const double *gamma, int32_t d, void *stream);
 
 /* Chebyshev-interpolant coefficients Gamma_d of Sec. 5 (eq. chebfun-f),
  * computed by the library: out[0..d] leading first. 1 <= d <= 32. */

@@ -329,6 +329,36 @@ int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shif
   });
 }
 
+int arr_gn_step(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo, double hi,
+                const double *gamma, int32_t d, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(A && X && gamma && d >= 1 && w >= 1 && ld >= w, "gn_step: bad arguments");
+    hipStream_t s = as_stream(stream);
+    std::vector<double> g(gamma, gamma + d + 1);
+    arr::Work wk;
+    const int64_t n = A->n;
+    ARR_REQUIRE(n > 0, "gn_step: empty matrix");
+    wk.ensure_cols(n, (int)w);
+    const int iw = (int)w;
+    auto run = [&](auto *Xp, auto tag) {
+      using T = decltype(tag);
+      arr::DevBuf tmp(sizeof(T) * n * 4 * w);
+      T *t = tmp.as<T>();
+      auto S = dev_split<T>(A);
+      auto blk = [&](int q) { return arr::Blk<T>{t + q * w, 4 * w, iw}; };
+      arr::gn_step<T>(S->M, arr::Blk<T>{Xp, ld, iw}, blk(0), blk(1), blk(2), blk(3), shift, lo, hi, g, wk, s);
+      ARR_HIP(hipStreamSynchronize(s));
+    };
+    if (A->dtype == 0)
+      run((double *)X, double{});
+    else {
+      ARR_REQUIRE(A->dtype == 1, "dtype must be 0 (FP64) or 1 (FP32)");
+      run((float *)X, float{});
+    }
+    return ARR_OK;
+  });
+}
+
 int arr_gram(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, const void *Y, int64_t ldy, int32_t my,
              double *G, void *stream) {
   return guarded(nullptr, [&]() {

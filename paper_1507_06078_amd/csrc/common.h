@@ -248,6 +248,8 @@ void rcond_device(int m, const double *G, double *work, int *info, double *rc, h
 // tiles strictly above the diagonal.
 void small_gemm(int m1, int m2, int kk, double alpha, const double *A, int64_t sai, int64_t sak, const double *B,
                 int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc, bool lower, hipStream_t s);
+// C <- (C - I) / 2 (m x m, ld m)
+void launch_half_minus_identity(int m, double *C, hipStream_t s);
 // max |diag| and Frobenius norm of a small matrix -> out[0], out[1]
 void launch_diag_max(int m, const double *A, int64_t lda, double *out, hipStream_t s);
 // Symmetrize: A = (A + A^T)/2

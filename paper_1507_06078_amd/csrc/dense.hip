@@ -314,6 +314,14 @@ __global__ __launch_bounds__(256) void k_rcond_final(int m, const double *G, con
   }
 }
 
+// C <- (C - I) / 2 for the m x m matrix C (ld m): the GN correction factor.
+__global__ __launch_bounds__(256) void k_half_minus_identity(int m, double *C) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int i = (int)(idx / m), j = (int)(idx % m);
+  C[idx] = 0.5 * (C[idx] - (i == j ? 1.0 : 0.0));
+}
+
 __global__ __launch_bounds__(256) void k_diag_max(int m, const double *A, int64_t lda, double *out) {
   __shared__ double s1[256], s2[256];
   double mx = 0.0, fro = 0.0;
@@ -608,6 +616,13 @@ void launch_tri_inv_t(int m, const double *L, int64_t ldl, double *Winv, int64_t
   const int64_t tot = (int64_t)m * m;
   hipLaunchKernelGGL(k_lower_to_upper_t, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, Li, (int64_t)m,
                      Winv, ldw);
+  ARR_HIP(hipGetLastError());
+}
+
+void launch_half_minus_identity(int m, double *C, hipStream_t s) {
+  if (m == 0) return;
+  const int64_t tot = (int64_t)m * m;
+  hipLaunchKernelGGL(k_half_minus_identity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, C);
   ARR_HIP(hipGetLastError());
 }
 

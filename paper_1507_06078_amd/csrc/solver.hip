@@ -92,6 +92,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
   ARR_REQUIRE(o.d0 >= 1 && o.d_max >= o.d0 && o.d_max <= 64, "need 1 <= d0 <= d_max <= 64");
   ARR_REQUIRE(o.maxit >= 1 && o.maxit1 >= 1 && o.maxit2 >= 1, "iteration limits must be >= 1");
   ARR_REQUIRE(o.precision == ARR_FP64 || o.precision == ARR_MIXED, "unknown precision");
+  ARR_REQUIRE(o.inner_solver == ARR_INNER_MPM || o.inner_solver == ARR_INNER_GN, "unknown inner solver");
   // validate CSR on the host
   const int64_t *rp = csr->rowptr;
   ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
@@ -388,8 +389,13 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     wk_.ensure_cols(n, wp_);
     for (int i1 = 0; i1 < o_.maxit1; ++i1) {
       for (int i2 = 0; i2 < o_.maxit2; ++i2) {
-        poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, wk_, true, s_);
-        normalize_from_partial<T>(n, X, wk_, s_);
+        if (o_.inner_solver == ARR_INNER_GN) {
+          // GN branch: no normalization; Y in Z's second segment, rho(A) Y in W
+          gn_step<T>(A, X, B.Z(wp_, wp_), B.W(0, wp_), Ya, Yb, a_, 0.0, b_ - a_, g, wk_, s_);
+        } else {
+          poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, wk_, true, s_);
+          normalize_from_partial<T>(n, X, wk_, s_);
+        }
         if (nc_) project_out<T>(n, Qc, X, wk_, s_);
         stats.poly_calls += 1;
         stats.spmm_degrees += d_;

@@ -37,6 +37,11 @@ template <typename T>
 void normalize(int64_t n, Blk<T> X, Work &wk, hipStream_t s);
 template <typename T>
 void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s);
+// One GN inner iteration (Sec. 4, GN branch of Algorithm 8); Y, Z, Ya, Yb are
+// n x X.w scratch blocks.
+template <typename T>
+void gn_step(const DevCSR<T> &A, Blk<T> X, Blk<T> Y, Blk<T> Z, Blk<T> Ya, Blk<T> Yb, double shift, double lo,
+             double hi, const std::vector<double> &g, Work &wk, hipStream_t s);
 template <typename T>
 double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s);
 // Orthonormal basis of R(Z) (and orthogonal to Q when Q.w > 0); Z and Zalt

@@ -126,6 +126,42 @@ double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s) {
   return h;
 }
 
+// One GN inner iteration of Algorithm 8 (Sec. 4, unit step) with rho =
+// Algorithm 7's poly on A - shift I over [lo, hi]:
+//   Y = X (X^T X)^{-1},  Z = rho(A) Y,  X <- Z - X (Y^T Z - I) / 2.
+// (X^T X)^{-1} = L^{-T} L^{-1} from the FP64 Cholesky factor of the Gram.
+// Y, Z, Ya, Yb are n x w scratch blocks (Ya, Yb: the poly's ping-pong pair).
+template <typename T>
+void gn_step(const DevCSR<T> &A, Blk<T> X, Blk<T> Y, Blk<T> Z, Blk<T> Ya, Blk<T> Yb, double shift, double lo,
+             double hi, const std::vector<double> &g, Work &wk, hipStream_t s) {
+  const int64_t n = A.n;
+  const int w = X.w;
+  if (w == 0) return;
+  wk.ensure_gram(n, w, w);
+  wk.ensure_small(w);
+  const size_t ww = (size_t)w * w;
+  double *G = wk.small.as<double>();
+  double *Wt = G + ww;         // L^{-T}
+  double *Gi = Wt + ww;        // (X^T X)^{-1}, later (Y^T Z - I) / 2
+  double *scratch = Gi + ww;   // 2 w^2 for the triangular inverse
+  const Blk<const T> Xc{X.p, X.ld, w};
+  launch_gram<T>(n, Xc, Xc, G, wk.gramw.as<double>(), true, s);
+  launch_cholesky(w, G, w, 0.0, wk.info.as<int>(), s);
+  int info = 0;
+  ARR_HIP(hipMemcpyAsync(&info, wk.info.as<int>(), sizeof(int), hipMemcpyDeviceToHost, s));
+  ARR_HIP(hipStreamSynchronize(s));
+  if (info) throw Error(-5, "GN step: X^T X is not numerically positive definite");
+  launch_tri_inv_t(w, G, w, Wt, w, scratch, s);
+  small_gemm(w, w, w, 1.0, Wt, w, 1, Wt, 1, w, 0.0, Gi, w, false, s);  // L^{-T} L^{-1}
+  launch_update<T>(n, Xc, Gi, w, w, 1.0, 0.0, Y, s);                    // Y = X G^{-1}
+  launch_copy<T>(n, w, Z.p, Z.ld, Y.p, Y.ld, s);
+  poly_apply<T>(A, Z, Ya, Yb, shift, lo, hi, g, wk, false, s);          // Z = rho(A) Y
+  launch_gram<T>(n, Blk<const T>{Y.p, Y.ld, w}, Blk<const T>{Z.p, Z.ld, w}, Gi, wk.gramw.as<double>(), false, s);
+  launch_half_minus_identity(w, Gi, s);                                 // (Y^T Z - I) / 2
+  launch_update<T>(n, Xc, Gi, w, w, -1.0, 1.0, Z, s);                   // Z - X (Y^T Z - I) / 2
+  launch_copy<T>(n, w, X.p, X.ld, Z.p, Z.ld, s);
+}
+
 // One Cholesky-QR pass: G = Z^T Z (+ shift I), G = L L^T, Zout = Z L^-T.
 // Returns the (1-based) failing pivot column or 0.
 template <typename T>
@@ -220,6 +256,8 @@ std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, c
   template void normalize_from_partial<T>(int64_t, Blk<T>, Work &, hipStream_t);                                 \
   template void normalize<T>(int64_t, Blk<T>, Work &, hipStream_t);                                              \
   template void project_out<T>(int64_t, Blk<const T>, Blk<T>, Work &, hipStream_t);                             \
+  template void gn_step<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, Blk<T>, Blk<T>, double, double, double,    \
+                           const std::vector<double> &, Work &, hipStream_t);                                    \
   template double rcond_gram<T>(int64_t, Blk<const T>, Work &, hipStream_t);                                     \
   template Blk<T> orthonormalize<T>(int64_t, Blk<T>, Blk<T>, Blk<const T>, Work &, hipStream_t, int *);          \
   template void rayleigh_ritz<T>(const DevCSR<T> &, int64_t, Blk<const T>, Blk<T>, Work &, std::vector<double> &, \

@@ -131,6 +131,47 @@ def test_poly_matches_oracle_fp64(d):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("d", [3, 8, 15])
+def test_gn_step_matches_oracle_fp64(d):
+    """The GN inner iteration of Algorithm 8 (Sec. 4) against the oracle."""
+    A = W.laplacian_3d(12, potential_seed=1)
+    S = -A.to_scipy()
+    lam = np.linalg.eigvalsh(S.toarray())
+    a, b = lam[0] - 0.01, lam[-40]
+    X = W.gaussian_block(A.n, 37, seed=5)
+    g = O.interpolant_coefficients(d)
+    ref = O.gn_step(O.shifted(S, a), X, 0.0, b - a, g)
+    Xd = dev(X)
+    arr.arr_gn_step(arr.DeviceCSR(A.negated()), Xd, a, 0.0, b - a, arr.arr_filter_coefficients(d))
+    got = Xd.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_gn_step_fp32_and_repeated_steps_track_oracle():
+    """FP32 blocks against the oracle; and 40 GN steps in FP64 follow the
+    oracle's trajectory to the same X X^T (GN contracts towards the rank-w
+    part of rho(A), so the two agree to rounding)."""
+    A = W.laplacian_2d_potential(20, potential_seed=3)
+    S = -A.to_scipy()
+    lam = np.linalg.eigvalsh(S.toarray())
+    a, b = lam[0] - 0.01, lam[-30]
+    g = O.interpolant_coefficients(5)
+    X = W.gaussian_block(A.n, 12, seed=6)
+    ref = O.gn_step(O.shifted(S, a), X, 0.0, b - a, g)
+    Xf = dev(X, torch.float32)
+    arr.arr_gn_step(arr.DeviceCSR(A.negated(), dtype=torch.float32), Xf, a, 0.0, b - a, arr.arr_filter_coefficients(5))
+    assert np.abs(Xf.double().cpu().numpy() - ref).max() <= 1e-4 * np.abs(ref).max()
+    Xd = dev(X)
+    Ad = arr.DeviceCSR(A.negated())
+    Xo = X.copy()
+    for _ in range(40):
+        arr.arr_gn_step(Ad, Xd, a, 0.0, b - a, arr.arr_filter_coefficients(5))
+        Xo = O.gn_step(O.shifted(S, a), Xo, 0.0, b - a, g)
+    Xg = Xd.cpu().numpy()
+    Pg, Po = Xg @ Xg.T, Xo @ Xo.T
+    assert np.abs(Pg - Po).max() <= 1e-8 * np.abs(Po).max()
+
+
 def test_poly_fp32_error_is_small():
     A = W.laplacian_3d(12, potential_seed=1).negated()
     S = A.to_scipy()

@@ -69,6 +69,33 @@ def test_c1_laplacian_matches_oracle_and_closed_form(precision):
     assert_same_subspaces(ev, X, ref.evecs)
 
 
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_c1_gn_inner_solver_matches_oracle_and_closed_form(precision):
+    """ARRABIT-GN (the GN branch of Algorithm 8)."""
+    A, k, which, w, tol = W.workload("lap2d_40")
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    status, ev, X, res, st = solve(A, k, which, tol, w=w, precision=precision, X0=X0, inner_solver=arr.INNER_GN)
+    assert status == arr.ARR_OK, st
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    ref = O.arrabit_mpm(A.to_scipy(), k, 1e-12, X0, which, O.Options(inner="gn"))
+    assert np.all(np.abs(ev - exact) <= 1e-10 * np.maximum(1, np.abs(exact)))
+    assert np.all(np.abs(ev - ref.evals) <= 1e-10 * np.maximum(1, np.abs(ref.evals)))
+    check_pairs(A, ev, X, tol)
+    assert_same_subspaces(ev, X, ref.evecs)
+
+
+@pytest.mark.parametrize("which", ["LA", "SA"])
+def test_gn_random_symmetric_vs_dense(which):
+    n, k, w = 300, 8, 12
+    A = W.random_symmetric(n, seed=31, density=0.1)
+    lam = np.linalg.eigvalsh(A.to_scipy().toarray())
+    exact = lam[::-1][:k] if which == "LA" else lam[:k]
+    status, ev, X, res, st = solve(A, k, which, 1e-10, w=w, inner_solver=arr.INNER_GN)
+    assert status == arr.ARR_OK, st
+    assert np.abs(ev - exact).max() <= 1e-10 * np.abs(lam).max()
+    check_pairs(A, ev, X, 1e-10)
+
+
 def test_c1_device_gaussian_start():
     A, k, which, w, tol = W.workload("lap2d_40")
     status, ev, X, res, st = solve(A, k, which, tol, w=w)
