@@ -61,6 +61,14 @@ typedef enum { ARR_FP64 = 0, ARR_MIXED = 1 } arr_precision_t;
  * (Y = X (X^T X)^{-1}, Z = rho(A) Y, X = Z - X (Y^T Z - I)/2). */
 typedef enum { ARR_INNER_MPM = 0, ARR_INNER_GN = 1 } arr_inner_t;
 
+/* How the filter psi_d (Sec. 5) is applied. ARR_POLY_PRODUCT: as the product
+ * lead * prod (A' - r_i I) over psi_d's d real roots (all in [-1, 1)), Leja
+ * ordered, with A' the shifted and scaled operator of Algorithm 7: one
+ * gathered read and one write of the block per degree. ARR_POLY_HORNER:
+ * Algorithm 7's Horner recurrence on the monomial coefficients Gamma_d, which
+ * also reads X every degree. The two are the same polynomial. */
+typedef enum { ARR_POLY_PRODUCT = 0, ARR_POLY_HORNER = 1 } arr_poly_form_t;
+
 /* Host CSR description (arr_create deep-copies it to the device). */
 typedef struct {
   int64_t n;             /* order of A                                   */
@@ -104,6 +112,7 @@ typedef struct {
   int32_t timing;        /* 1: time filter SpMM launches with HIP events (stats)           */
   int32_t keep_vectors;  /* served requests: keep eigenvectors on the host (default 1)    */
   int32_t inner_solver;  /* arr_inner_t, default ARR_INNER_MPM                              */
+  int32_t poly_form;     /* arr_poly_form_t, default ARR_POLY_PRODUCT                       */
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -248,6 +257,19 @@ int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t 
  * Temporary device memory is allocated internally. Synchronous. */
 int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo,
              double hi, const double *gamma, int32_t d, void *stream);
+
+/* Real roots of psi_d (Sec. 5), in the Leja order the product form applies
+ * them, and its leading monomial coefficient: psi_d(t) = lead * prod (t -
+ * roots[i]). roots: host, d doubles. 1 <= d <= 64. */
+int arr_filter_roots(int32_t d, double *roots, double *lead);
+
+/* Apply the library's filter psi_d of Sec. 5 as Algorithm 8 does:
+ * X <- psi_d(c0 I + c1 (A - shift I)) X with c0 = (lo + hi)/(lo - hi),
+ * c1 = 2/(hi - lo), in the given arr_poly_form_t. X is a device block n x w
+ * (ld, A's dtype), overwritten. Temporary device memory is allocated
+ * internally. Synchronous. */
+int arr_filter(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo, double hi,
+               int32_t d, int32_t form, void *stream);
 
 /* One Gauss-Newton inner iteration (Sec. 4 with unit step, the GN branch of
  * Algorithm 8) with rho = poly(A - shift I, ., lo, hi, Gamma_d):

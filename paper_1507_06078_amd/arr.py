@@ -29,6 +29,8 @@ FP64 = 0
 MIXED = 1
 INNER_MPM = 0
 INNER_GN = 1
+POLY_PRODUCT = 0
+POLY_HORNER = 1
 
 
 class ArrError(RuntimeError):
@@ -55,7 +57,8 @@ class arr_options_t(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int32), ("device", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("mixed_switch", ctypes.c_double), ("verbose", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("keep_vectors", ctypes.c_int32),
-                ("inner_solver", ctypes.c_int32)]
+                ("inner_solver", ctypes.c_int32),
+                ("poly_form", ctypes.c_int32)]
 
 
 class arr_server_opts_t(ctypes.Structure):
@@ -85,7 +88,8 @@ class arr_stats_t(ctypes.Structure):
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
            "arr_get_eigpairs", "arr_get_stats", "arr_last_error", "arr_last_global_error", "arr_destroy",
-           "arr_filter_step", "arr_poly", "arr_gn_step", "arr_filter_coefficients", "arr_gram", "arr_block_update",
+           "arr_filter_step", "arr_poly", "arr_filter", "arr_filter_roots", "arr_gn_step",
+           "arr_filter_coefficients", "arr_gram", "arr_block_update",
            "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
            "arr_server_create", "arr_footprint", "arr_submit", "arr_poll", "arr_wait", "arr_request_times",
            "arr_server_destroy"]
@@ -121,6 +125,8 @@ def lib() -> ctypes.CDLL:
     L.arr_filter_step.argtypes = [P(arr_dev_csr_t), i64, vp, i64, vp, i64, vp, i64, f64, f64, f64, vp, vp]
     L.arr_poly.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, vp, i32, vp]
     L.arr_gn_step.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, vp, i32, vp]
+    L.arr_filter.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, i32, i32, vp]
+    L.arr_filter_roots.argtypes = [i32, vp, vp]
     L.arr_filter_coefficients.argtypes = [i32, vp]
     L.arr_gram.argtypes = [i32, i64, vp, i64, i32, vp, i64, i32, vp, vp]
     L.arr_block_update.argtypes = [i32, i64, i32, i32, f64, vp, i64, vp, i64, f64, vp, i64, vp]
@@ -329,6 +335,19 @@ def arr_poly(A: DeviceCSR, X, shift: float, lo: float, hi: float, gamma: np.ndar
     g = np.ascontiguousarray(gamma, dtype=np.float64)
     _check(lib().arr_poly(ctypes.byref(A.desc), int(X.shape[1]), _ptr(X), _ld(X), float(shift), float(lo),
                           float(hi), g.ctypes.data, len(g) - 1, _stream()))
+
+
+def arr_filter_roots(d: int):
+    """Roots of psi_d (Leja order) and its leading coefficient."""
+    r = np.zeros(d)
+    lead = ctypes.c_double()
+    _check(lib().arr_filter_roots(int(d), r.ctypes.data, ctypes.addressof(lead)))
+    return r, lead.value
+
+
+def arr_filter(A: DeviceCSR, X, shift: float, lo: float, hi: float, d: int, form: int = POLY_PRODUCT):
+    _check(lib().arr_filter(ctypes.byref(A.desc), int(X.shape[1]), _ptr(X), _ld(X), float(shift), float(lo),
+                            float(hi), int(d), int(form), _stream()))
 
 
 def arr_gn_step(A: DeviceCSR, X, shift: float, lo: float, hi: float, gamma: np.ndarray):

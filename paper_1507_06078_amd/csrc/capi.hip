@@ -313,18 +313,59 @@ int arr_poly(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shif
       arr::DevBuf tmp(sizeof(double) * n * 2 * std::max<int64_t>(1, w));
       double *t = tmp.as<double>();
       auto S = dev_split<double>(A);
-      arr::poly_apply<double>(S->M, arr::Blk<double>{(double *)X, ld, (int)w},
+      arr::poly_apply_horner<double>(S->M, arr::Blk<double>{(double *)X, ld, (int)w},
                               arr::Blk<double>{t, 2 * w, (int)w}, arr::Blk<double>{t + w, 2 * w, (int)w}, shift, lo,
                               hi, g, wk, false, s);
     } else {
       arr::DevBuf tmp(sizeof(float) * n * 2 * std::max<int64_t>(1, w));
       float *t = tmp.as<float>();
       auto S = dev_split<float>(A);
-      arr::poly_apply<float>(S->M, arr::Blk<float>{(float *)X, ld, (int)w},
+      arr::poly_apply_horner<float>(S->M, arr::Blk<float>{(float *)X, ld, (int)w},
                              arr::Blk<float>{t, 2 * w, (int)w}, arr::Blk<float>{t + w, 2 * w, (int)w}, shift, lo, hi,
                              g, wk, false, s);
     }
     ARR_HIP(hipStreamSynchronize(s));
+    return ARR_OK;
+  });
+}
+
+int arr_filter_roots(int32_t d, double *roots, double *lead) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(roots && lead && d >= 1 && d <= 64, "filter_roots: bad arguments");
+    const arr::FilterPoly fp = arr::filter_poly(d);
+    std::copy(fp.roots.begin(), fp.roots.end(), roots);
+    *lead = fp.lead;
+    return ARR_OK;
+  });
+}
+
+int arr_filter(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo, double hi,
+               int32_t d, int32_t form, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(A && X && d >= 1 && d <= 64 && w >= 0 && ld >= w, "filter: bad arguments");
+    ARR_REQUIRE(form == ARR_POLY_PRODUCT || form == ARR_POLY_HORNER, "filter: unknown form");
+    hipStream_t s = as_stream(stream);
+    const arr::FilterPoly fp = arr::filter_poly(d);
+    arr::Work wk;
+    const int64_t n = A->n;
+    ARR_REQUIRE(n > 0, "filter: empty matrix");
+    wk.ensure_cols(n, (int)w);
+    const int iw = (int)w;
+    auto run = [&](auto *Xp, auto tag) {
+      using T = decltype(tag);
+      arr::DevBuf tmp(sizeof(T) * n * 2 * std::max<int64_t>(1, w));
+      T *t = tmp.as<T>();
+      auto S = dev_split<T>(A);
+      arr::poly_apply<T>(S->M, arr::Blk<T>{Xp, ld, iw}, arr::Blk<T>{t, 2 * w, iw}, arr::Blk<T>{t + w, 2 * w, iw},
+                         shift, lo, hi, fp, form, wk, false, s);
+      ARR_HIP(hipStreamSynchronize(s));
+    };
+    if (A->dtype == 0)
+      run((double *)X, double{});
+    else {
+      ARR_REQUIRE(A->dtype == 1, "dtype must be 0 (FP64) or 1 (FP32)");
+      run((float *)X, float{});
+    }
     return ARR_OK;
   });
 }
@@ -346,7 +387,10 @@ int arr_gn_step(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double s
       T *t = tmp.as<T>();
       auto S = dev_split<T>(A);
       auto blk = [&](int q) { return arr::Blk<T>{t + q * w, 4 * w, iw}; };
-      arr::gn_step<T>(S->M, arr::Blk<T>{Xp, ld, iw}, blk(0), blk(1), blk(2), blk(3), shift, lo, hi, g, wk, s);
+      arr::FilterPoly fp;
+      fp.gamma = g;  // the caller's coefficients, applied by Algorithm 7's recurrence
+      arr::gn_step<T>(S->M, arr::Blk<T>{Xp, ld, iw}, blk(0), blk(1), blk(2), blk(3), shift, lo, hi, fp,
+                      arr::kPolyHorner, wk, s);
       ARR_HIP(hipStreamSynchronize(s));
     };
     if (A->dtype == 0)

@@ -274,6 +274,17 @@ struct Jacobi {
 
 // Chebyshev-interpolant coefficients Gamma_d (leading first), Sec. 5.
 std::vector<double> filter_coefficients(int d);
+// psi_d in both forms: monomial coefficients (leading first) for Algorithm 7's
+// Horner recurrence, and lead * prod (t - roots[i]) with the real roots in
+// Leja order for the product form.
+struct FilterPoly {
+  std::vector<double> gamma, roots;
+  double lead = 0.0;
+};
+FilterPoly filter_poly(int d);
+// Form of the filter application: the product of d linear factors (2 block
+// passes per degree) or Algorithm 7's Horner recurrence (3 block passes).
+enum PolyForm { kPolyProduct = 0, kPolyHorner = 1 };
 // The same interpolant in the Chebyshev basis: psi_d = sum_k c[k] T_k.
 std::vector<double> filter_chebyshev_coefficients(int d);
 

@@ -89,7 +89,7 @@ class Solver {
   std::vector<double> h_val_, h_band_, h_x0_, h_vecs_;
   int64_t nnz_ = 0;  // entries of the whole matrix
   size_t device_plan(bool allocate);
-  std::map<int, std::vector<double>> coef_;
+  std::map<int, FilterPoly> coef_;
 
   // iteration state (Algorithm 8)
   int nc_ = 0, wp_ = 0, d_ = 3, p_ = 1, j_ = 0;
@@ -99,7 +99,7 @@ class Solver {
   int since_best_ = 0;
   std::vector<double> out_vals_, out_res_;
 
-  const std::vector<double> &coeffs(int d);
+  const FilterPoly &coeffs(int d);
   void setup_interval();
   template <typename T>
   int outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage);

@@ -93,6 +93,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
   ARR_REQUIRE(o.maxit >= 1 && o.maxit1 >= 1 && o.maxit2 >= 1, "iteration limits must be >= 1");
   ARR_REQUIRE(o.precision == ARR_FP64 || o.precision == ARR_MIXED, "unknown precision");
   ARR_REQUIRE(o.inner_solver == ARR_INNER_MPM || o.inner_solver == ARR_INNER_GN, "unknown inner solver");
+  ARR_REQUIRE(o.poly_form == ARR_POLY_PRODUCT || o.poly_form == ARR_POLY_HORNER, "unknown polynomial form");
   // validate CSR on the host
   const int64_t *rp = csr->rowptr;
   ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
@@ -225,9 +226,9 @@ double Solver::now() const {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
 }
 
-const std::vector<double> &Solver::coeffs(int d) {
+const FilterPoly &Solver::coeffs(int d) {
   auto it = coef_.find(d);
-  if (it == coef_.end()) it = coef_.emplace(d, filter_coefficients(d)).first;
+  if (it == coef_.end()) it = coef_.emplace(d, filter_poly(d)).first;
   return it->second;
 }
 
@@ -312,7 +313,7 @@ int Solver::degree_update(double mu_k, double mu_w) {
     return v;
   };
   for (int d = 3; d <= o_.d_max; ++d) {
-    const std::vector<double> &g = coeffs(d);
+    const std::vector<double> &g = coeffs(d).gamma;
     const double num = std::fabs(rho(g, mu_w)), den = std::fabs(rho(g, mu_k));
     if (den > 0.0 && num / den < 0.9) return d;
   }
@@ -384,16 +385,16 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     Blk<T> X = B.Z(0, wp_);
     Blk<T> Ya = B.U(0, wp_), Yb = B.U(wp_, wp_);
     const Blk<const T> Qc{B.Qb.template as<T>(), B.ldq, nc_};
-    const std::vector<double> &g = coeffs(d_);
+    const FilterPoly &g = coeffs(d_);
     double rc = std::numeric_limits<double>::infinity();
     wk_.ensure_cols(n, wp_);
     for (int i1 = 0; i1 < o_.maxit1; ++i1) {
       for (int i2 = 0; i2 < o_.maxit2; ++i2) {
         if (o_.inner_solver == ARR_INNER_GN) {
           // GN branch: no normalization; Y in Z's second segment, rho(A) Y in W
-          gn_step<T>(A, X, B.Z(wp_, wp_), B.W(0, wp_), Ya, Yb, a_, 0.0, b_ - a_, g, wk_, s_);
+          gn_step<T>(A, X, B.Z(wp_, wp_), B.W(0, wp_), Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, s_);
         } else {
-          poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, wk_, true, s_);
+          poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, true, s_);
           normalize_from_partial<T>(n, X, wk_, s_);
         }
         if (nc_) project_out<T>(n, Qc, X, wk_, s_);

@@ -28,9 +28,14 @@ struct Work {
   void ensure_small(int m);
 };
 
+// Algorithm 7 with the caller's monomial coefficients g (leading first).
+template <typename T>
+void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
+                       const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s);
+// psi_d in the chosen PolyForm.
 template <typename T>
 void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
-                const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s);
+                const FilterPoly &fp, int form, Work &wk, bool want_norms, hipStream_t s);
 template <typename T>
 void normalize_from_partial(int64_t n, Blk<T> X, Work &wk, hipStream_t s);
 template <typename T>
@@ -41,7 +46,7 @@ void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s);
 // n x X.w scratch blocks.
 template <typename T>
 void gn_step(const DevCSR<T> &A, Blk<T> X, Blk<T> Y, Blk<T> Z, Blk<T> Ya, Blk<T> Yb, double shift, double lo,
-             double hi, const std::vector<double> &g, Work &wk, hipStream_t s);
+             double hi, const FilterPoly &fp, int form, Work &wk, hipStream_t s);
 template <typename T>
 double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s);
 // Orthonormal basis of R(Z) (and orthogonal to Q when Q.w > 0); Z and Zalt

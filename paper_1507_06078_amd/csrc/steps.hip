@@ -1,8 +1,10 @@
 // Building blocks of the ARRABIT iteration on the device, shared by the
 // solver driver and the step-level C entry points:
-//  * poly_apply   -- Algorithm 7 on the shifted operator (Horner form), one
-//                    fused SpMM launch per degree, the column norms of the last
-//                    degree accumulated in its epilogue;
+//  * poly_apply   -- Algorithm 7's polynomial on the shifted operator, one
+//                    fused SpMM launch per degree (Horner recurrence, or the
+//                    product of linear factors over psi_d's real roots), the
+//                    column norms of the last degree accumulated in its
+//                    epilogue;
 //  * normalize    -- x_i = x_i / ||x_i|| (multi-power method, Sec. 3);
 //  * project_out  -- X - Qc (Qc^T X) (Sec. 6, deflation);
 //  * rcond_gram   -- rcond(X^T X) (eq. inn-stop);
@@ -59,7 +61,7 @@ void Work::ensure_small(int m) {
 }
 
 template <typename T>
-void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
+void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
                 const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s) {
   const int d = (int)g.size() - 1;
   ARR_REQUIRE(d >= 1, "poly: degree must be >= 1");
@@ -85,6 +87,45 @@ void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift
   }
   // last degree writes X in place (Z = X is read row-locally before the store)
   wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, Xc, X, al, be, g[d], partial, s);
+}
+
+// The same polynomial as a product of linear factors over its real roots
+// (Leja order): Y <- (c1 A + (c0 - c1 shift - r_i) I) Y, the leading
+// coefficient folded into the first factor. One gathered read and one write
+// per degree; the last degree writes X and (optionally) its column norms.
+template <typename T>
+void poly_apply_product(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
+                        const std::vector<double> &roots, double lead, Work &wk, bool want_norms, hipStream_t s) {
+  const int d = (int)roots.size();
+  ARR_REQUIRE(d >= 1, "poly: degree must be >= 1");
+  ARR_REQUIRE(hi != lo, "poly: empty interval");
+  const int w = X.w;
+  double *partial = want_norms ? wk.partial.as<double>() : nullptr;
+  const double c0 = (lo + hi) / (lo - hi), c1 = 2.0 / (hi - lo);
+  const Blk<const T> none{nullptr, 0, 0};
+  auto beta = [&](int i) { return c0 - c1 * shift - roots[i]; };
+  if (d == 1) {
+    wk.groups = launch_filter_spmm<T>(A, Blk<const T>{X.p, X.ld, w}, none, Ya, lead * c1, lead * beta(0), 0.0,
+                                      partial, s);
+    launch_copy<T>(A.n, w, X.p, X.ld, Ya.p, Ya.ld, s);
+    return;
+  }
+  launch_filter_spmm<T>(A, Blk<const T>{X.p, X.ld, w}, none, Ya, lead * c1, lead * beta(0), 0.0, nullptr, s);
+  Blk<T> cur = Ya, nxt = Yb;
+  for (int i = 1; i < d - 1; ++i) {
+    launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, none, nxt, c1, beta(i), 0.0, nullptr, s);
+    std::swap(cur, nxt);
+  }
+  wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, none, X, c1, beta(d - 1), 0.0, partial, s);
+}
+
+template <typename T>
+void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
+                const FilterPoly &fp, int form, Work &wk, bool want_norms, hipStream_t s) {
+  if (form == kPolyHorner)
+    poly_apply_horner<T>(A, X, Ya, Yb, shift, lo, hi, fp.gamma, wk, want_norms, s);
+  else
+    poly_apply_product<T>(A, X, Ya, Yb, shift, lo, hi, fp.roots, fp.lead, wk, want_norms, s);
 }
 
 template <typename T>
@@ -133,7 +174,7 @@ double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s) {
 // Y, Z, Ya, Yb are n x w scratch blocks (Ya, Yb: the poly's ping-pong pair).
 template <typename T>
 void gn_step(const DevCSR<T> &A, Blk<T> X, Blk<T> Y, Blk<T> Z, Blk<T> Ya, Blk<T> Yb, double shift, double lo,
-             double hi, const std::vector<double> &g, Work &wk, hipStream_t s) {
+             double hi, const FilterPoly &fp, int form, Work &wk, hipStream_t s) {
   const int64_t n = A.n;
   const int w = X.w;
   if (w == 0) return;
@@ -155,37 +196,46 @@ void gn_step(const DevCSR<T> &A, Blk<T> X, Blk<T> Y, Blk<T> Z, Blk<T> Ya, Blk<T>
   small_gemm(w, w, w, 1.0, Wt, w, 1, Wt, 1, w, 0.0, Gi, w, false, s);  // L^{-T} L^{-1}
   launch_update<T>(n, Xc, Gi, w, w, 1.0, 0.0, Y, s);                    // Y = X G^{-1}
   launch_copy<T>(n, w, Z.p, Z.ld, Y.p, Y.ld, s);
-  poly_apply<T>(A, Z, Ya, Yb, shift, lo, hi, g, wk, false, s);          // Z = rho(A) Y
+  poly_apply<T>(A, Z, Ya, Yb, shift, lo, hi, fp, form, wk, false, s);   // Z = rho(A) Y
   launch_gram<T>(n, Blk<const T>{Y.p, Y.ld, w}, Blk<const T>{Z.p, Z.ld, w}, Gi, wk.gramw.as<double>(), false, s);
   launch_half_minus_identity(w, Gi, s);                                 // (Y^T Z - I) / 2
   launch_update<T>(n, Xc, Gi, w, w, -1.0, 1.0, Z, s);                   // Z - X (Y^T Z - I) / 2
   launch_copy<T>(n, w, X.p, X.ld, Z.p, Z.ld, s);
 }
 
-// One Cholesky-QR pass: G = Z^T Z (+ shift I), G = L L^T, Zout = Z L^-T.
-// Returns the (1-based) failing pivot column or 0.
+// One Cholesky-QR pass: G = Z^T Z, G = L L^T, Zout = Z L^-T. If G is not
+// numerically positive definite and allow_shift is set, the same Gram (kept
+// aside, not recomputed) is factored again with the diagonal shift
+// shift_rel * |G|_F of shifted Cholesky QR, and *shifted is set. Returns the
+// (1-based) failing pivot column or 0.
 template <typename T>
-static int cholqr_pass(int64_t n, Blk<const T> Z, Blk<T> Zout, double shift_rel, Work &wk, hipStream_t s,
-                       double *gnorm_out) {
+static int cholqr_pass(int64_t n, Blk<const T> Z, Blk<T> Zout, double shift_rel, bool allow_shift, Work &wk,
+                       hipStream_t s, int *shifted) {
   const int m = Z.w;
+  const size_t mm = (size_t)m * m;
   double *G = wk.small.as<double>();
-  double *Wt = G + (size_t)m * m;
-  double *nrm = Wt + (size_t)m * m;  // 2 doubles
-  double *scratch = nrm + 64;        // 2 m^2 doubles
+  double *Wt = G + mm;
+  double *nrm = Wt + mm;           // 2 doubles
+  double *scratch = nrm + 64;      // 2 m^2 doubles
+  double *Gsave = scratch + 2 * mm;
+  *shifted = 0;
   launch_gram<T>(n, Z, Z, G, wk.gramw.as<double>(), true, s);
-  double shift = 0.0;
-  if (shift_rel > 0.0) {
+  if (allow_shift) launch_copy<double>(m, m, Gsave, m, G, m, s);
+  launch_cholesky(m, G, m, 0.0, wk.info.as<int>(), s);
+  int info = 0;
+  ARR_HIP(hipMemcpyAsync(&info, wk.info.as<int>(), sizeof(int), hipMemcpyDeviceToHost, s));
+  ARR_HIP(hipStreamSynchronize(s));
+  if (info && allow_shift) {
+    launch_copy<double>(m, m, G, m, Gsave, m, s);
     launch_diag_max(m, G, m, nrm, s);
     double hn[2];
     ARR_HIP(hipMemcpyAsync(hn, nrm, sizeof(hn), hipMemcpyDeviceToHost, s));
     ARR_HIP(hipStreamSynchronize(s));
-    shift = shift_rel * hn[1];
-    if (gnorm_out) *gnorm_out = hn[1];
+    launch_cholesky(m, G, m, shift_rel * hn[1], wk.info.as<int>(), s);
+    ARR_HIP(hipMemcpyAsync(&info, wk.info.as<int>(), sizeof(int), hipMemcpyDeviceToHost, s));
+    ARR_HIP(hipStreamSynchronize(s));
+    *shifted = 1;
   }
-  launch_cholesky(m, G, m, shift, wk.info.as<int>(), s);
-  int info = 0;
-  ARR_HIP(hipMemcpyAsync(&info, wk.info.as<int>(), sizeof(int), hipMemcpyDeviceToHost, s));
-  ARR_HIP(hipStreamSynchronize(s));
   if (info) return info;
   launch_tri_inv_t(m, G, m, Wt, m, scratch, s);
   launch_update<T>(n, Z, Wt, m, m, 1.0, 0.0, Zout, s, true);
@@ -206,14 +256,10 @@ Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk
   // up to 2 plain passes after any shifted ones; at most 6 in all
   while (done_plain < 2 && total < 6) {
     if (Q.w) project_out<T>(n, Q, cur, wk, s);
-    int info = cholqr_pass<T>(n, Blk<const T>{cur.p, cur.ld, m}, nxt, 0.0, wk, s, nullptr);
-    if (info) {
-      info = cholqr_pass<T>(n, Blk<const T>{cur.p, cur.ld, m}, nxt, shift_rel, wk, s, nullptr);
-      if (info) throw Error(-5, "Cholesky QR broke down even with a diagonal shift");
-      done_plain = 0;
-    } else {
-      ++done_plain;
-    }
+    int shifted = 0;
+    const int info = cholqr_pass<T>(n, Blk<const T>{cur.p, cur.ld, m}, nxt, shift_rel, true, wk, s, &shifted);
+    if (info) throw Error(-5, "Cholesky QR broke down even with a diagonal shift");
+    done_plain = shifted ? 0 : done_plain + 1;
     std::swap(cur, nxt);
     ++total;
   }
@@ -251,13 +297,15 @@ std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, c
 }
 
 #define ARR_INST(T)                                                                                              \
+  template void poly_apply_horner<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, double, double, double,          \
+                                     const std::vector<double> &, Work &, bool, hipStream_t);                    \
   template void poly_apply<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, double, double, double,                 \
-                              const std::vector<double> &, Work &, bool, hipStream_t);                           \
+                              const FilterPoly &, int, Work &, bool, hipStream_t);                               \
   template void normalize_from_partial<T>(int64_t, Blk<T>, Work &, hipStream_t);                                 \
   template void normalize<T>(int64_t, Blk<T>, Work &, hipStream_t);                                              \
   template void project_out<T>(int64_t, Blk<const T>, Blk<T>, Work &, hipStream_t);                             \
   template void gn_step<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, Blk<T>, Blk<T>, double, double, double,    \
-                           const std::vector<double> &, Work &, hipStream_t);                                    \
+                           const FilterPoly &, int, Work &, hipStream_t);                                        \
   template double rcond_gram<T>(int64_t, Blk<const T>, Work &, hipStream_t);                                     \
   template Blk<T> orthonormalize<T>(int64_t, Blk<T>, Blk<T>, Blk<const T>, Work &, hipStream_t, int *);          \
   template void rayleigh_ritz<T>(const DevCSR<T> &, int64_t, Blk<const T>, Blk<T>, Work &, std::vector<double> &, \

@@ -48,6 +48,28 @@ def test_library_coefficients_match_oracle(d):
     np.testing.assert_allclose(g_lib, g_or, rtol=1e-9, atol=1e-9 * np.abs(g_or).max())
 
 
+@pytest.mark.parametrize("d,rtol", [(1, 1e-12), (2, 1e-12), (3, 1e-12), (5, 1e-11), (8, 1e-10), (12, 1e-10),
+                                    (15, 1e-10), (24, 1e-7)])
+def test_library_filter_roots_reproduce_the_interpolant(d, rtol):
+    """The product form lead * prod (t - r_i) is the oracle's psi_d: d real
+    roots in [-1, 1), the nonpositive interpolation nodes among them exactly,
+    and the values agree on [-1.05, 2.2] (where the filter is used). The
+    tolerance follows the oracle's monomial coefficients, whose Vandermonde
+    solve loses accuracy as d grows (about 1e-9 at d = 24)."""
+    roots, lead = arr.arr_filter_roots(d)
+    assert roots.shape == (d,) and np.all(np.isfinite(roots))
+    assert np.all(roots >= -1.0) and np.all(roots < 1.0)
+    assert len(np.unique(roots)) == d
+    nodes = O.interpolation_nodes(d)
+    for t in nodes[nodes <= 0]:
+        assert np.any(roots == t) or np.any(np.abs(roots - t) <= 1e-15)
+    g = O.interpolant_coefficients(d) if d > 1 else np.array([0.5, 0.5])
+    t = np.linspace(-1.05, 2.2, 2001)
+    prod = lead * np.prod(t[:, None] - roots[None, :], axis=1)
+    ref = O.psi(t, g)
+    assert np.all(np.abs(prod - ref) <= rtol * np.maximum(1.0, np.abs(ref)))
+
+
 def _bad(csr_mut, **kw):
     A = W.laplacian_2d(8)
     rowptr, colind, val = A.rowptr.copy(), A.colind.copy(), A.val.copy()

@@ -131,6 +131,45 @@ def test_poly_matches_oracle_fp64(d):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 8, 15])
+@pytest.mark.parametrize("form", ["product", "horner"])
+def test_filter_forms_match_oracle_fp64(d, form):
+    """psi_d applied as the product over its roots, or by Algorithm 7's
+    recurrence, against the oracle's Algorithm 7."""
+    A = W.laplacian_3d(12, potential_seed=1)
+    S = -A.to_scipy()
+    lam = np.linalg.eigvalsh(S.toarray())
+    a, b = lam[0] - 0.01, lam[-40]
+    X = W.gaussian_block(A.n, 37, seed=4)
+    g = O.interpolant_coefficients(d) if d > 1 else np.array([0.5, 0.5])
+    ref = O.poly(O.shifted(S, a), X, 0.0, b - a, g)
+    Xd = dev(X)
+    arr.arr_filter(arr.DeviceCSR(A.negated()), Xd, a, 0.0, b - a, d,
+                   arr.POLY_PRODUCT if form == "product" else arr.POLY_HORNER)
+    got = Xd.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_filter_product_fp32_more_accurate_than_horner():
+    """In FP32 the product form keeps psi_15's accuracy (no cancellation of
+    large monomial terms); Algorithm 7's monomial recurrence loses about
+    three digits more (the FP32 reading of Algorithm 7)."""
+    A = W.laplacian_3d(12, potential_seed=1).negated()
+    S = A.to_scipy()
+    lam = np.linalg.eigvalsh(S.toarray())
+    a, b = lam[0] - 0.01, lam[-40]
+    X = W.gaussian_block(A.n, 16, seed=4)
+    g = O.interpolant_coefficients(15)
+    ref = O.poly(O.shifted(S, a), X, 0.0, b - a, g)
+    errs = {}
+    for form in (arr.POLY_PRODUCT, arr.POLY_HORNER):
+        Xd = dev(X, torch.float32)
+        arr.arr_filter(arr.DeviceCSR(A, dtype=torch.float32), Xd, a, 0.0, b - a, 15, form)
+        errs[form] = np.abs(Xd.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert errs[arr.POLY_PRODUCT] < 1e-5, errs
+    assert errs[arr.POLY_PRODUCT] < errs[arr.POLY_HORNER], errs
+
+
 @pytest.mark.parametrize("d", [3, 8, 15])
 def test_gn_step_matches_oracle_fp64(d):
     """The GN inner iteration of Algorithm 8 (Sec. 4) against the oracle."""
