@@ -157,6 +157,7 @@ typedef struct {
   int64_t spmm32_launches;
   double spmm32_ms, spmm32_bytes;
   int32_t spmm32_cols_per_lane, spmm32_vec;
+  double fp32_maxres;    /* ARR_MIXED: maxres of the last FP32-stage iteration (eq. resi) */
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

@@ -83,7 +83,8 @@ class arr_stats_t(ctypes.Structure):
                 ("upd64_ms", ctypes.c_double), ("upd64_flops", ctypes.c_double),
                 ("upd32_ms", ctypes.c_double), ("upd32_flops", ctypes.c_double),
                 ("spmm32_launches", ctypes.c_int64), ("spmm32_ms", ctypes.c_double), ("spmm32_bytes", ctypes.c_double),
-                ("spmm32_cols_per_lane", ctypes.c_int32), ("spmm32_vec", ctypes.c_int32)]
+                ("spmm32_cols_per_lane", ctypes.c_int32), ("spmm32_vec", ctypes.c_int32),
+                ("fp32_maxres", ctypes.c_double)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",

@@ -471,7 +471,10 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     if (!(maxres == maxres)) maxres = std::numeric_limits<double>::infinity();
     stats.maxres = maxres;
     stats.t_arr += now() - t;
-    if (fp32_stage) stats.fp32_outer += 1;
+    if (fp32_stage) {
+      stats.fp32_outer += 1;
+      stats.fp32_maxres = maxres;  // the raw FP32-stage figure, before the FP64 closing iterations
+    }
     if (o_.verbose) {
       std::fprintf(stderr,
                    "[arr] outer %d %s maxres %.3e tol_t %.1e d %d p %d locked %d width %d m %d jacobi_sweeps %d "
