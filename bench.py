@@ -181,6 +181,13 @@ def measured_traffic(kernel):
     return 1024.0 * (k["fetch_kib"] * rec["copy_fetch_factor"] + k["write_kib"] * rec["copy_write_factor"])
 
 
+def spmm_kernel_name(dtype, vec, cols_per_lane, flags):
+    """The SpMM kernel instance the solver timed: k_filter_spmm<T, VEC, NT,
+    overflow rows, Z operand, column sums>, as rocprofv3 names it."""
+    b = lambda bit: "true" if flags & bit else "false"
+    return f"k_filter_spmm<{dtype}, {vec}, {max(1, cols_per_lane // vec)}, {b(2)}, {b(1)}, {b(4)}>"
+
+
 def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     """Warmup + timed solves of one handle; returns the figures of the timed
     solves and the eigenvalues of the last one."""
@@ -224,9 +231,8 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     spmm_ms, spmm_bytes, launches = tot("spmm_ms"), tot("spmm_bytes"), tot("spmm_launches")
     last = stats[-1]
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9 if spmm_ms > 0 else None
-    vec = last["spmm_vec"]
-    kernel = (f"k_filter_spmm<{'double' if last['spmm_fp64'] else 'float'}, {vec}, "
-              f"{max(1, last['spmm_cols_per_lane'] // vec)}>")
+    kernel = spmm_kernel_name("double" if last["spmm_fp64"] else "float", last["spmm_vec"],
+                              last["spmm_cols_per_lane"], last["spmm_flags"])
     traffic = measured_traffic(kernel)
 
     def gemm(prefix, peak):
@@ -241,8 +247,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     ms32, b32, l32 = tot("spmm32_ms"), tot("spmm32_bytes"), tot("spmm32_launches")
     if precision == "mixed" and l32:
         a32 = b32 / (ms32 * 1e-3) / 1e9
-        v32 = last["spmm32_vec"]
-        k32 = f"k_filter_spmm<float, {v32}, {max(1, last['spmm32_cols_per_lane'] // v32)}>"
+        k32 = spmm_kernel_name("float", last["spmm32_vec"], last["spmm32_cols_per_lane"], last["spmm32_flags"])
         roof32 = {"bound": "hbm", "kernel": k32, "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": a32 / HBM_PEAK_GBS, "traffic": measured_traffic(k32), "launches": l32,
                   "avg_launch_us": ms32 * 1e3 / l32, "algorithmic_bytes_per_launch": b32 / l32}

@@ -151,13 +151,17 @@ typedef struct {
    * upper triangular, as in Cholesky QR). "64" = FP64 matrix cores
    * (FP64 data, or FP32 data widened exactly); "32" = FP32 matrix cores. */
   int64_t gram64_launches, gram32_launches, upd64_launches, upd32_launches;
-  /* the most time-consuming FP32 SpMM variant alone (ARR_MIXED), as above */
   double gram64_ms, gram64_flops, gram32_ms, gram32_flops;
   double upd64_ms, upd64_flops, upd32_ms, upd32_flops;
+  /* the most time-consuming FP32 SpMM variant alone (ARR_MIXED), as above */
   int64_t spmm32_launches;
   double spmm32_ms, spmm32_bytes;
   int32_t spmm32_cols_per_lane, spmm32_vec;
   double fp32_maxres;    /* ARR_MIXED: maxres of the last FP32-stage iteration (eq. resi) */
+  /* flags of the SpMM variants above: 1 = recurrence block Z present,
+   * 2 = matrix has rows with more than four entries off the central band,
+   * 4 = column sums of squares computed */
+  int32_t spmm_flags, spmm32_flags;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

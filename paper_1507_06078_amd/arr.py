@@ -84,7 +84,7 @@ class arr_stats_t(ctypes.Structure):
                 ("upd32_ms", ctypes.c_double), ("upd32_flops", ctypes.c_double),
                 ("spmm32_launches", ctypes.c_int64), ("spmm32_ms", ctypes.c_double), ("spmm32_bytes", ctypes.c_double),
                 ("spmm32_cols_per_lane", ctypes.c_int32), ("spmm32_vec", ctypes.c_int32),
-                ("fp32_maxres", ctypes.c_double)]
+                ("fp32_maxres", ctypes.c_double), ("spmm_flags", ctypes.c_int32), ("spmm32_flags", ctypes.c_int32)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",

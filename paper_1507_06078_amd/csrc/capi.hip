@@ -38,12 +38,12 @@ int guarded(std::string *err, F &&f) {
   }
 }
 
-// The caller's device CSR in the split form of the SpMM kernels: downloaded,
+// The caller's device CSR in the row form of the SpMM kernels: downloaded,
 // checked (row pointers, column range and order), split on the host and
 // uploaded into buffers this object owns.
 template <typename T>
 struct SplitDev {
-  arr::DevBuf rp, col, val, band;
+  arr::DevBuf coef, fcol, orp, ocol, oval;
   arr::DevCSR<T> M;
 };
 
@@ -68,25 +68,31 @@ std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
       ARR_REQUIRE(q == rp[i] || ci[q - 1] < ci[q], "column indices must be strictly increasing within a row");
     }
   }
-  std::vector<double> v(vt.begin(), vt.end()), fval, band;
-  std::vector<int64_t> frp;
-  std::vector<int32_t> fcol;
-  arr::split_band(n, rp.data(), ci.data(), v.data(), frp, fcol, fval, band);
-  std::vector<T> fv(fval.begin(), fval.end()), bv(band.begin(), band.end());
+  std::vector<double> v(vt.begin(), vt.end());
+  arr::RowSplit sp;
+  arr::split_rows(n, rp.data(), ci.data(), v.data(), sp);
+  std::vector<T> cv(sp.coef.begin(), sp.coef.end()), ov(sp.oval.begin(), sp.oval.end());
   auto d = std::make_unique<SplitDev<T>>();
-  const int64_t nf = (int64_t)fcol.size();
-  d->rp.alloc(sizeof(int64_t) * (n + 1));
-  d->col.alloc(sizeof(int32_t) * std::max<int64_t>(1, nf));
-  d->val.alloc(sizeof(T) * std::max<int64_t>(1, nf));
-  d->band.alloc(sizeof(T) * 3 * n);
-  ARR_HIP(hipMemcpy(d->rp.p, frp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
-  if (nf) {
-    ARR_HIP(hipMemcpy(d->col.p, fcol.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice));
-    ARR_HIP(hipMemcpy(d->val.p, fv.data(), sizeof(T) * nf, hipMemcpyHostToDevice));
+  const int64_t no = (int64_t)sp.ocol.size();
+  d->coef.alloc(sizeof(T) * 8 * n);
+  d->fcol.alloc(sizeof(int32_t) * 4 * n);
+  ARR_HIP(hipMemcpy(d->coef.p, cv.data(), sizeof(T) * 8 * n, hipMemcpyHostToDevice));
+  ARR_HIP(hipMemcpy(d->fcol.p, sp.fcol.data(), sizeof(int32_t) * 4 * n, hipMemcpyHostToDevice));
+  if (no) {
+    d->orp.alloc(sizeof(int64_t) * (n + 1));
+    d->ocol.alloc(sizeof(int32_t) * no);
+    d->oval.alloc(sizeof(T) * no);
+    ARR_HIP(hipMemcpy(d->orp.p, sp.orp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    ARR_HIP(hipMemcpy(d->ocol.p, sp.ocol.data(), sizeof(int32_t) * no, hipMemcpyHostToDevice));
+    ARR_HIP(hipMemcpy(d->oval.p, ov.data(), sizeof(T) * no, hipMemcpyHostToDevice));
   }
-  ARR_HIP(hipMemcpy(d->band.p, bv.data(), sizeof(T) * 3 * n, hipMemcpyHostToDevice));
-  d->M = arr::DevCSR<T>{n, nnz, (const int64_t *)d->rp.p, (const int32_t *)d->col.p, (const T *)d->val.p,
-                        (const T *)d->band.p};
+  d->M = arr::DevCSR<T>{n,
+                        nnz,
+                        (const T *)d->coef.p,
+                        (const int32_t *)d->fcol.p,
+                        no ? (const int64_t *)d->orp.p : nullptr,
+                        no ? (const int32_t *)d->ocol.p : nullptr,
+                        no ? (const T *)d->oval.p : nullptr};
   return d;
 }
 

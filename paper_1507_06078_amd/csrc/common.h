@@ -32,24 +32,35 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::arr::Error(-1, std::string(msg));      \
   } while (0)
 
-// Device matrix in the split form the SpMM kernels read: band [3n] holds the
-// three central diagonals (band[i] = A[i][i-1], band[n+i] = A[i][i],
-// band[2n+i] = A[i][i+1]; zero where the entry is absent) and a CSR (rowptr
-// int64 [n+1], col int32, values in T) holds the remaining entries. nnz
-// counts every entry of the matrix.
+// Device matrix in the row form the SpMM kernels read. Per row i: coef[8i ..
+// 8i+7] = {A[i][i-1], A[i][i], A[i][i+1], f0, f1, f2, f3, 0} (zero where an
+// entry is absent) and fcol[4i .. 4i+3] the columns of the first four other
+// ("far") entries f0..f3 (unused slots: column i, value 0). Far entries past
+// the fourth are an overflow CSR (orp int64 [n+1], ocol int32, oval in T);
+// orp is null when no row has more than four. nnz counts every entry of the
+// matrix.
 template <typename T>
 struct DevCSR {
   int64_t n = 0, nnz = 0;
-  const int64_t *rowptr = nullptr;
-  const int32_t *col = nullptr;
-  const T *val = nullptr;
-  const T *band = nullptr;
+  const T *coef = nullptr;
+  const int32_t *fcol = nullptr;
+  const int64_t *orp = nullptr;
+  const int32_t *ocol = nullptr;
+  const T *oval = nullptr;
 };
 
-// Host split of a CSR with strictly increasing columns per row into the band
-// [3n] and the CSR of the other entries (frp [n+1], fcol, fval).
-void split_band(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, std::vector<int64_t> &frp,
-                std::vector<int32_t> &fcol, std::vector<double> &fval, std::vector<double> &band);
+// Host form of the same split (FP64 values); orp is left empty when no row
+// has more than four far entries.
+struct RowSplit {
+  std::vector<double> coef;
+  std::vector<int32_t> fcol;
+  std::vector<int64_t> orp;
+  std::vector<int32_t> ocol;
+  std::vector<double> oval;
+};
+
+// Host split of a CSR with strictly increasing columns per row.
+void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out);
 
 // A row-major view of columns [0, w) of a device block with leading
 // dimension ld.
@@ -152,7 +163,7 @@ struct SpmmTimer {
   struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
-  static constexpr int kClasses = 20;
+  static constexpr int kClasses = 160;
   int64_t launches[kClasses] = {};
   double ms[kClasses] = {}, bytes[kClasses] = {};
   hipEvent_t get();

@@ -73,7 +73,7 @@ class Solver {
   double tol_;
   arr_options_t o_;
   hipStream_t s_ = nullptr;
-  DevBuf rowptr_, col_, val64_, val32_, band64_, band32_;  // split matrix (band + far CSR)
+  DevBuf coef64_, coef32_, fcol_, orp_, ocol_, oval64_, oval32_;  // matrix in the row form of the SpMM
   DevCSR<double> A64_;
   DevCSR<float> A32_;
   Blocks<double> B64_;
@@ -84,9 +84,8 @@ class Solver {
   bool have_x0_ = false, device_ready_ = false, host_results_ = false;
   int64_t ldz_ = 0, ldq_ = 0;
   int lanczos_L_ = 0;
-  std::vector<int64_t> h_rowptr_;  // far CSR of the working operator
-  std::vector<int32_t> h_col_;
-  std::vector<double> h_val_, h_band_, h_x0_, h_vecs_;
+  RowSplit h_split_;  // the working operator in the row form of the SpMM
+  std::vector<double> h_x0_, h_vecs_;
   int64_t nnz_ = 0;  // entries of the whole matrix
   size_t device_plan(bool allocate);
   std::map<int, FilterPoly> coef_;

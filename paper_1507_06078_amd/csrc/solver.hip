@@ -116,11 +116,11 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
     }
   }
   // working operator (A, or -A for the smallest end) in the split form
-  split_band(n, rp, csr->colind, csr->val, h_rowptr_, h_col_, h_val_, h_band_);
+  split_rows(n, rp, csr->colind, csr->val, h_split_);
   nnz_ = csr->nnz;
   if (which == ARR_SMALLEST_ALGEBRAIC) {
-    for (double &x : h_val_) x = -x;
-    for (double &x : h_band_) x = -x;
+    for (double &x : h_split_.coef) x = -x;
+    for (double &x : h_split_.oval) x = -x;
   }
   ldz_ = round_up((int64_t)std::max(o.p_max + 1, 2) * w_, 8);
   ldq_ = round_up(w_, 8);
@@ -130,20 +130,23 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
 // Every device buffer of a solve, in one place: with allocate = false the
 // padded byte count is returned (the footprint a server reserves).
 size_t Solver::device_plan(bool allocate) {
-  const int64_t n = n_, nnz = (int64_t)h_col_.size();  // far entries
+  const int64_t n = n_, no = (int64_t)h_split_.ocol.size();  // overflow entries
   const bool mixed = o_.precision == ARR_MIXED;
   size_t total = 0;
   auto take = [&](DevBuf &b, size_t bytes) {
     total += (bytes + 255) / 256 * 256;
     if (allocate) b.alloc(bytes);
   };
-  take(rowptr_, sizeof(int64_t) * (n + 1));
-  take(col_, sizeof(int32_t) * std::max<int64_t>(1, nnz));
-  take(val64_, sizeof(double) * std::max<int64_t>(1, nnz));
-  take(band64_, sizeof(double) * 3 * n);
+  take(coef64_, sizeof(double) * 8 * n);
+  take(fcol_, sizeof(int32_t) * 4 * n);
+  if (no) {
+    take(orp_, sizeof(int64_t) * (n + 1));
+    take(ocol_, sizeof(int32_t) * no);
+    take(oval64_, sizeof(double) * no);
+  }
   if (mixed) {
-    take(val32_, sizeof(float) * std::max<int64_t>(1, nnz));
-    take(band32_, sizeof(float) * 3 * n);
+    take(coef32_, sizeof(float) * 8 * n);
+    if (no) take(oval32_, sizeof(float) * no);
   }
   for (DevBuf *b : {&B64_.Zb, &B64_.Ub, &B64_.Wb}) take(*b, sizeof(double) * n * ldz_);
   for (DevBuf *b : {&B64_.Qb, &B64_.Q2b}) take(*b, sizeof(double) * n * ldq_);
@@ -170,24 +173,26 @@ void Solver::ensure_device() {
   ARR_HIP(hipSetDevice(o_.device));
   if (!s_) ARR_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
   device_plan(true);
-  const int64_t n = n_, nnz = (int64_t)h_col_.size();
-  ARR_HIP(hipMemcpyAsync(rowptr_.p, h_rowptr_.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s_));
-  if (nnz) {
-    ARR_HIP(hipMemcpyAsync(col_.p, h_col_.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s_));
-    ARR_HIP(hipMemcpyAsync(val64_.p, h_val_.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, s_));
-    if (o_.precision == ARR_MIXED)
-      launch_convert<float, double>(nnz, 1, val32_.as<float>(), 1, val64_.as<double>(), 1, s_);
+  const int64_t n = n_, no = (int64_t)h_split_.ocol.size();
+  const bool mixed = o_.precision == ARR_MIXED;
+  ARR_HIP(hipMemcpyAsync(coef64_.p, h_split_.coef.data(), sizeof(double) * 8 * n, hipMemcpyHostToDevice, s_));
+  ARR_HIP(hipMemcpyAsync(fcol_.p, h_split_.fcol.data(), sizeof(int32_t) * 4 * n, hipMemcpyHostToDevice, s_));
+  if (mixed) launch_convert<float, double>(8 * n, 1, coef32_.as<float>(), 1, coef64_.as<double>(), 1, s_);
+  if (no) {
+    ARR_HIP(hipMemcpyAsync(orp_.p, h_split_.orp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s_));
+    ARR_HIP(hipMemcpyAsync(ocol_.p, h_split_.ocol.data(), sizeof(int32_t) * no, hipMemcpyHostToDevice, s_));
+    ARR_HIP(hipMemcpyAsync(oval64_.p, h_split_.oval.data(), sizeof(double) * no, hipMemcpyHostToDevice, s_));
+    if (mixed) launch_convert<float, double>(no, 1, oval32_.as<float>(), 1, oval64_.as<double>(), 1, s_);
   }
-  ARR_HIP(hipMemcpyAsync(band64_.p, h_band_.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, s_));
-  if (o_.precision == ARR_MIXED)
-    launch_convert<float, double>(3 * n, 1, band32_.as<float>(), 1, band64_.as<double>(), 1, s_);
   if (have_x0_)
     ARR_HIP(hipMemcpyAsync(x0_.p, h_x0_.data(), sizeof(double) * n * w_, hipMemcpyHostToDevice, s_));
-  A64_ = DevCSR<double>{n, nnz_, rowptr_.as<int64_t>(), col_.as<int32_t>(), val64_.as<double>(),
-                        band64_.as<double>()};
-  if (o_.precision == ARR_MIXED)
-    A32_ = DevCSR<float>{n, nnz_, rowptr_.as<int64_t>(), col_.as<int32_t>(), val32_.as<float>(),
-                         band32_.as<float>()};
+  const int64_t *orp = no ? orp_.as<int64_t>() : nullptr;
+  const int32_t *ocol = no ? ocol_.as<int32_t>() : nullptr;
+  A64_ = DevCSR<double>{n, nnz_, coef64_.as<double>(), fcol_.as<int32_t>(), orp, ocol,
+                        no ? oval64_.as<double>() : nullptr};
+  if (mixed)
+    A32_ = DevCSR<float>{n, nnz_, coef32_.as<float>(), fcol_.as<int32_t>(), orp, ocol,
+                         no ? oval32_.as<float>() : nullptr};
   B64_.ldz = ldz_;
   B64_.ldq = ldq_;
   B32_.ldz = ldz_;
@@ -198,7 +203,7 @@ void Solver::ensure_device() {
 
 void Solver::release_device() {
   if (s_) ARR_HIP(hipStreamSynchronize(s_));
-  for (DevBuf *b : {&rowptr_, &col_, &val64_, &val32_, &band64_, &band32_, &B64_.Zb, &B64_.Ub, &B64_.Wb, &B64_.Qb, &B64_.Q2b, &B32_.Zb,
+  for (DevBuf *b : {&coef64_, &coef32_, &fcol_, &orp_, &ocol_, &oval64_, &oval32_, &B64_.Zb, &B64_.Ub, &B64_.Wb, &B64_.Qb, &B64_.Q2b, &B32_.Zb,
                     &B32_.Ub, &B32_.Wb, &B32_.Qb, &B32_.Q2b, &mu_, &desc_, &outv_, &x0_, &lz_V_, &lz_w_, &lz_h_,
                     &lz_part_, &wk_.partial, &wk_.colv, &wk_.gramw, &wk_.small, &wk_.proj, &wk_.info, &wk_.jac.bufA,
                     &wk_.jac.bufB, &wk_.jac.bufV, &wk_.jac.bufOff, &wk_.jac.bufEval})
@@ -647,17 +652,20 @@ int Solver::solve() {
     stats.spmm_launches = timer.launches[best];
     stats.spmm_ms = timer.ms[best];
     stats.spmm_bytes = timer.bytes[best];
+    // class = slots + 5 vec4 + 10 fp64 + 20 Z + 40 overflow + 80 sums
     stats.spmm_cols_per_lane = 1 << (best % 5);
     stats.spmm_vec = (best % 10) >= 5 ? 4 : 1;
-    stats.spmm_fp64 = best >= 10 ? 1 : 0;
+    stats.spmm_fp64 = (best % 20) >= 10 ? 1 : 0;
+    stats.spmm_flags = (best / 20) & 7;
     int best32 = 0;
-    for (int c = 1; c < 10; ++c)
-      if (timer.ms[c] > timer.ms[best32]) best32 = c;
+    for (int c = 1; c < SpmmTimer::kClasses; ++c)
+      if ((c % 20) < 10 && timer.ms[c] > timer.ms[best32]) best32 = c;
     stats.spmm32_launches = timer.launches[best32];
     stats.spmm32_ms = timer.ms[best32];
     stats.spmm32_bytes = timer.bytes[best32];
     stats.spmm32_cols_per_lane = 1 << (best32 % 5);
-    stats.spmm32_vec = best32 >= 5 ? 4 : 1;
+    stats.spmm32_vec = (best32 % 10) >= 5 ? 4 : 1;
+    stats.spmm32_flags = (best32 / 20) & 7;
     gtimer.flush();
     auto sum = [&](std::initializer_list<int> cls, int64_t &l, double &ms, double &fl) {
       l = 0, ms = 0, fl = 0;

@@ -1,28 +1,36 @@
 // Fused filter SpMM for gfx950: one degree of the polynomial accelerator
-// (the loop body of Algorithm 7, and the plain products A*X of the Krylov
-// augmentation [X, AX, ..., A^p X] of eq. S:ARR):
+// (the loop body of Algorithm 7, a factor of the product form of psi_d, and
+// the plain products A*X of the Krylov augmentation [X, AX, ..., A^p X] of
+// eq. S:ARR):
 //
-//   Yout = alpha * A * Yin + beta * Yin + gamma * Z
+//   Yout = alpha * A * Yin + beta * Yin + gamma * Z      (Z optional)
 //
 // Design (about 1.5 flop per byte; bound by the memory system):
-//  * matrix format: the three central diagonals (band: dl, dd, du) are split
-//    off the CSR at set-up; the CSR keeps the remaining ("far") entries. A
-//    wave visits a run of kRun consecutive rows and keeps Yin rows i-1, i,
-//    i+1 in a register window, so the band and the beta*Yin term cost one
-//    new Yin row per output row instead of four gathered ones;
-//  * one 64-lane wavefront per row; the far (col, val) entries are
-//    wave-uniform (scalar cache); lane l owns columns l, l+64, ... of the
-//    row-major blocks (FP32 blocks with 16-byte aligned rows: 4 consecutive
-//    columns per lane, one 16-byte load), so every gathered Yin row is read
-//    as full, contiguous segments;
+//  * matrix format (built on the host at set-up): one record of 8 values per
+//    row {A[i][i-1], A[i][i], A[i][i+1], f0, f1, f2, f3, 0} with the columns
+//    of the first four other ("far") entries in a table of 4 per row (unused
+//    slots: column i, value 0); far entries past the fourth go to an overflow
+//    CSR. A row's coefficients are one 64-byte scalar load;
+//  * a wave visits a run of kRun consecutive rows and keeps Yin rows i-1, i,
+//    i+1 in a register window, so the band and the beta*Yin term cost one new
+//    Yin row per output row;
+//  * inside a run the loads are software pipelined: columns two rows ahead,
+//    the far gathers and the next window row one row ahead, so about twenty
+//    loads per wave are in flight while a row is combined. Full runs take a
+//    straight-line path with unconditional loads (the wait counts stay
+//    exact); the first and last runs take a guarded row-at-a-time path;
+//  * rows are read and written through buffer resources sized to the block
+//    width: lanes past it read zeros and their stores are dropped, so no lane
+//    predicate splits the code; lane l owns columns l, l+64, ... (FP32 blocks
+//    with 16-byte aligned rows: 4 consecutive columns per lane, one 16-byte
+//    load), so every gathered row is read as full contiguous segments;
 //  * the recurrence (beta*Yin + gamma*Z) is applied in the epilogue, so a
 //    degree makes exactly one pass over Yin (gathered), Z and Yout;
 //  * optional epilogue: per-workgroup column sums of squares of Yout in FP64,
 //    reduced later in a fixed order (deterministic column norms for the
 //    multi-power normalization);
 //  * XCD-aware order: workgroup b runs on XCD b % 8; runs are dealt to the
-//    XCDs in chunks of kRunChunk so stencil neighbours are mostly gathered by
-//    waves of the same XCD (its L2), while all XCDs sweep the matrix together
+//    XCDs in chunks of kRunChunk so that all XCDs sweep the matrix together
 //    (small working set in the shared Infinity Cache).
 #include <algorithm>
 #include <exception>
@@ -36,9 +44,10 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kXcd = 8;
-constexpr int64_t kRun = 8;       // consecutive rows per wave visit
-constexpr int64_t kRunChunk = 8;  // runs per XCD chunk
+constexpr int64_t kRun = 32;      // consecutive rows per wave visit
+constexpr int64_t kRunChunk = 4;  // runs per XCD chunk (128 rows)
 constexpr int kMaxGroups = 1024;  // 4 waves per SIMD on 256 CUs
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit elements
 
 template <typename T, int V>
 struct VecT {
@@ -57,29 +66,83 @@ __device__ __forceinline__ double lane_elem(const X &x, int v) {
     return (double)x[v];
 }
 
+// Buffer loads and stores of one lane's slot (out-of-range offsets read 0 and
+// drop the store). Output rows are written once per launch: the streaming
+// hint keeps them from displacing gathered rows in L2.
+template <typename T, int VEC>
+struct BufIO;
+template <>
+struct BufIO<double, 1> {
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(double v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          off, 0, 2);
+  }
+};
+template <>
+struct BufIO<float, 1> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+  }
+};
+template <>
+struct BufIO<float, 4> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(v4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(v4 v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
+                                           off, 0, 2);
+  }
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, kRsrcWord3);
+}
+
 // Run assigned to the k-th slot of XCD x.
 __device__ __forceinline__ int64_t xcd_run(int64_t k, int x) {
   return (x + kXcd * (k / kRunChunk)) * kRunChunk + (k % kRunChunk);
 }
 
-template <typename T, int VEC, int NT>
+template <typename T>
+struct RowCoef {
+  T v[8];
+};
+struct RowCols {
+  int32_t v[4];
+};
+
+template <typename T, int VEC, int NT, bool OVF, bool HASZ, bool SUMS>
 __global__ __launch_bounds__(kThreads) void k_filter_spmm(
-    int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-    const T *__restrict__ val, const T *__restrict__ band, int w, const T *__restrict__ Yin, int64_t ldy,
+    int64_t n, const T *__restrict__ coef, const int32_t *__restrict__ fcol, const int64_t *__restrict__ orp,
+    const int32_t *__restrict__ ocol, const T *__restrict__ oval, int w, const T *__restrict__ Yin, int64_t ldy,
     const T *Z, int64_t ldz, T *Yout, int64_t ldo, T alpha, T beta, T gamma, double *__restrict__ partial,
     int wtot, int c0) {
   typedef typename VecT<T, VEC>::type vec;
+  typedef BufIO<T, VEC> IO;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = blockIdx.x % kXcd;
   const int64_t wave_in_xcd = (int64_t)(blockIdx.x / kXcd) * kWaves + wv;
   const int64_t waves_per_xcd = (int64_t)(gridDim.x / kXcd) * kWaves;
   const int64_t nruns = (n + kRun - 1) / kRun;
-  const T *dl = band, *dd = band + n, *du = band + 2 * n;
-  auto ld = [&](const T *row, int t) -> vec {
-    const int c = VEC * lane + 64 * VEC * t;
-    return c < w ? *(const vec *)(row + c) : vec(0);
+  const int rowbytes = w * (int)sizeof(T);
+  int off[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) off[t] = (VEC * lane + 64 * VEC * t) * (int)sizeof(T);
+  auto ldrow = [&](const T *base, int64_t ld, int64_t j, vec *dst) {
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(base + j * ld, rowbytes);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) dst[t] = IO::ld(r, off[t]);
   };
+  auto gather = [&](int64_t j, vec *dst) { ldrow(Yin, ldy, j, dst); };
 
   double ss[NT][VEC];
 #pragma unroll
@@ -87,83 +150,168 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
 #pragma unroll
     for (int v = 0; v < VEC; ++v) ss[t][v] = 0.0;
 
-  for (int64_t k = wave_in_xcd;; k += waves_per_xcd) {
-    const int64_t r = xcd_run(k, x);
-    if (r >= nruns) break;
-    const int64_t i0 = r * kRun, iend = min(n, i0 + kRun);
-    vec wm[NT], w0[NT], wp[NT];
+  // beta*Yin + gamma*Z and the store of row i; column sums of squares
+  auto finish_row = [&](int64_t i, const vec *acc, const vec *yi, const vec *zi) {
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(Yout + i * ldo, rowbytes);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      wm[t] = i0 > 0 ? ld(Yin + (i0 - 1) * ldy, t) : vec(0);
-      w0[t] = ld(Yin + i0 * ldy, t);
-      wp[t] = i0 + 1 < n ? ld(Yin + (i0 + 1) * ldy, t) : vec(0);
+      vec o = alpha * acc[t];
+      if (beta != T(0)) o += beta * yi[t];
+      if constexpr (HASZ) o += gamma * zi[t];
+      IO::st(o, r, off[t]);
+      if constexpr (SUMS) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double ov = lane_elem<VEC>(o, v);
+          ss[t][v] = fma(ov, ov, ss[t][v]);
+        }
+      }
     }
-    for (int64_t i = i0; i < iend; ++i) {
-      // next window row, in flight while this row is gathered
-      vec nx[NT];
-      const bool more = i + 1 < iend && i + 2 < n;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) nx[t] = more ? ld(Yin + (i + 2) * ldy, t) : vec(0);
-      const T al = dl[i], ad = dd[i], au = du[i];
-      vec acc[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = al * wm[t] + ad * w0[t] + au * wp[t];
-      const int64_t b = rowptr[i], e = rowptr[i + 1];
+  };
+  // far entries past the fourth, four gathers at a time
+  auto overflow = [&](int64_t i, vec *acc) {
+    if constexpr (OVF) {
+      const int64_t b = orp[i], e = orp[i + 1];
       int64_t p = b;
       for (; p + 4 <= e; p += 4) {
-        const int64_t j0 = col[p], j1 = col[p + 1], j2 = col[p + 2], j3 = col[p + 3];
-        const T a0 = val[p], a1 = val[p + 1], a2 = val[p + 2], a3 = val[p + 3];
+        const T a0 = oval[p], a1 = oval[p + 1], a2 = oval[p + 2], a3 = oval[p + 3];
         vec v0[NT], v1[NT], v2[NT], v3[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          v0[t] = ld(Yin + j0 * ldy, t);
-          v1[t] = ld(Yin + j1 * ldy, t);
-          v2[t] = ld(Yin + j2 * ldy, t);
-          v3[t] = ld(Yin + j3 * ldy, t);
-        }
+        gather(ocol[p], v0);
+        gather(ocol[p + 1], v1);
+        gather(ocol[p + 2], v2);
+        gather(ocol[p + 3], v3);
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] += a0 * v0[t] + a1 * v1[t] + a2 * v2[t] + a3 * v3[t];
       }
       for (; p < e; ++p) {
-        const int64_t j0 = col[p];
-        const T a0 = val[p];
+        const T a0 = oval[p];
+        vec v0[NT];
+        gather(ocol[p], v0);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] += a0 * ld(Yin + j0 * ldy, t);
+        for (int t = 0; t < NT; ++t) acc[t] += a0 * v0[t];
       }
-      const T *zi = Z ? Z + i * ldz : nullptr;
-      T *oi = Yout + i * ldo;
+    }
+  };
+
+  for (int64_t k = wave_in_xcd;; k += waves_per_xcd) {
+    const int64_t r = xcd_run(k, x);
+    if (r >= nruns) break;
+    const int64_t i0 = r * kRun;
+    if constexpr (OVF) {
+      // rows with more than four far entries: one row at a time with the
+      // register window, far entries four gathers at a time
+      const int64_t iend = min(n, i0 + kRun);
+      vec wm[NT], w0[NT], wp[NT], zero[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int c = VEC * lane + 64 * VEC * t;
-        if (c < w) {
-          vec o = alpha * acc[t];
-          if (beta != T(0)) o += beta * w0[t];
-          if constexpr (VEC == 1) {
-            // Z and Yout are touched once per launch: streaming hints keep
-            // them from displacing gathered Yin rows in L2
-            if (zi) o += gamma * __builtin_nontemporal_load(zi + c);
-            __builtin_nontemporal_store(o, oi + c);
-          } else {
-            if (zi) o += gamma * *(const vec *)(zi + c);
-            *(vec *)(oi + c) = o;
-          }
+      for (int t = 0; t < NT; ++t) zero[t] = vec(0);
+      if (i0 > 0) gather(i0 - 1, wm); else for (int t = 0; t < NT; ++t) wm[t] = zero[t];
+      gather(i0, w0);
+      if (i0 + 1 < n) gather(i0 + 1, wp); else for (int t = 0; t < NT; ++t) wp[t] = zero[t];
+      for (int64_t i = i0; i < iend; ++i) {
+        vec nx[NT], zi[NT], g[4][NT];
+        if (i + 1 < iend && i + 2 < n) gather(i + 2, nx); else for (int t = 0; t < NT; ++t) nx[t] = zero[t];
+        const RowCoef<T> kk = *(const RowCoef<T> *)(coef + 8 * i);
+        const RowCols ci = *(const RowCols *)(fcol + 4 * i);
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) {
-            const double ov = lane_elem<VEC>(o, v);
-            ss[t][v] = fma(ov, ov, ss[t][v]);
-          }
+        for (int e = 0; e < 4; ++e) gather(ci.v[e], g[e]);
+        vec acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[t] = kk.v[0] * wm[t] + kk.v[1] * w0[t] + kk.v[2] * wp[t] + kk.v[3] * g[0][t] + kk.v[4] * g[1][t] +
+                   kk.v[5] * g[2][t] + kk.v[6] * g[3][t];
+        overflow(i, acc);
+        if constexpr (HASZ) ldrow(Z, ldz, i, zi);
+        finish_row(i, acc, w0, zi);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          wm[t] = w0[t];
+          w0[t] = wp[t];
+          wp[t] = nx[t];
         }
       }
+    } else if (i0 >= 1 && i0 + kRun + 1 <= n) {
+      // full run: rows i0-1 .. i0+kRun exist; straight-line code
+      vec wm[NT], w0[NT], wp[NT], g[4][NT], z[NT];
+      gather(i0 - 1, wm);
+      gather(i0, w0);
+      gather(i0 + 1, wp);
+      RowCols c0 = *(const RowCols *)(fcol + 4 * i0);
+      RowCoef<T> k0 = *(const RowCoef<T> *)(coef + 8 * i0);
+      RowCols c1 = *(const RowCols *)(fcol + 4 * (i0 + 1));
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        wm[t] = w0[t];
-        w0[t] = wp[t];
-        wp[t] = nx[t];
+      for (int e = 0; e < 4; ++e) gather(c0.v[e], g[e]);
+      if constexpr (HASZ) ldrow(Z, ldz, i0, z);
+#pragma unroll
+      for (int q = 0; q < kRun; ++q) {
+        const int64_t i = i0 + q;
+        vec nx[NT], gn[4][NT], zn[NT];
+        RowCols c2 = c1;
+        RowCoef<T> k1 = k0;
+        if (q < kRun - 1) gather(i + 2, nx);
+        if (q < kRun - 1) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) gather(c1.v[e], gn[e]);
+          if constexpr (HASZ) ldrow(Z, ldz, i + 1, zn);
+          k1 = *(const RowCoef<T> *)(coef + 8 * (i + 1));
+        }
+        if (q < kRun - 2) c2 = *(const RowCols *)(fcol + 4 * (i + 2));
+        vec acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[t] = k0.v[0] * wm[t] + k0.v[1] * w0[t] + k0.v[2] * wp[t] + k0.v[3] * g[0][t] + k0.v[4] * g[1][t] +
+                   k0.v[5] * g[2][t] + k0.v[6] * g[3][t];
+        finish_row(i, acc, w0, z);
+        // keep the scheduler from hoisting later rows' loads into this one
+        // (register pressure); the loads already issued stay in flight
+        __builtin_amdgcn_sched_barrier(0);
+        if (q < kRun - 1) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            wm[t] = w0[t];
+            w0[t] = wp[t];
+            wp[t] = nx[t];
+            if constexpr (HASZ) z[t] = zn[t];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) g[e][t] = gn[e][t];
+          }
+          k0 = k1;
+          c1 = c2;
+        }
+      }
+    } else {
+      // first run and the runs at the end: guarded, one row at a time
+      const int64_t iend = min(n, i0 + kRun);
+      for (int64_t i = i0; i < iend; ++i) {
+        const RowCoef<T> kk = *(const RowCoef<T> *)(coef + 8 * i);
+        const RowCols ci = *(const RowCols *)(fcol + 4 * i);
+        vec acc[NT], yi[NT], v[NT], zi[NT];
+        gather(i, yi);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = kk.v[1] * yi[t];
+        if (i > 0) {
+          gather(i - 1, v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] += kk.v[0] * v[t];
+        }
+        if (i + 1 < n) {
+          gather(i + 1, v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] += kk.v[2] * v[t];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          gather(ci.v[e], v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] += kk.v[3 + e] * v[t];
+        }
+        overflow(i, acc);
+        if constexpr (HASZ) ldrow(Z, ldz, i, zi);
+        finish_row(i, acc, yi, zi);
       }
     }
   }
 
-  if (partial) {
+  if constexpr (SUMS) {
     __shared__ double red[kWaves][64 * VEC * NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -180,25 +328,51 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col, const T *__restrict__ val,
-                                              const T *__restrict__ band, const T *__restrict__ x,
+__global__ __launch_bounds__(256) void k_spmv(int64_t n, const T *__restrict__ coef, const int32_t *__restrict__ fcol,
+                                              const int64_t *__restrict__ orp, const int32_t *__restrict__ ocol,
+                                              const T *__restrict__ oval, const T *__restrict__ x,
                                               T *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  T s = band[n + i] * x[i];
-  if (i > 0) s = fma(band[i], x[i - 1], s);
-  if (i + 1 < n) s = fma(band[2 * n + i], x[i + 1], s);
-  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) s = fma(val[p], x[col[p]], s);
+  const T *k = coef + 8 * i;
+  T s = k[1] * x[i];
+  if (i > 0) s = fma(k[0], x[i - 1], s);
+  if (i + 1 < n) s = fma(k[2], x[i + 1], s);
+  for (int e = 0; e < 4; ++e) s = fma(k[3 + e], x[fcol[4 * i + e]], s);
+  if (orp)
+    for (int64_t p = orp[i]; p < orp[i + 1]; ++p) s = fma(oval[p], x[ocol[p]], s);
   y[i] = s;
+}
+
+template <typename T, int VEC, int NT, bool OVF, bool HASZ, bool SUMS>
+void launch_variant(const DevCSR<T> &A, Blk<const T> Yin, const T *zp, int64_t ldz, Blk<T> Yout, int w, int c0,
+                    T alpha, T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+  hipLaunchKernelGGL((k_filter_spmm<T, VEC, NT, OVF, HASZ, SUMS>), dim3(groups), dim3(kThreads), 0, s, A.n, A.coef,
+                     A.fcol, A.orp, A.ocol, A.oval, w, Yin.p + c0, Yin.ld, zp, ldz, Yout.p + c0, Yout.ld, alpha, beta,
+                     gamma, partial, wtot, c0);
 }
 
 template <typename T, int VEC, int NT>
 void launch_nt(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w, int c0, T alpha,
                T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
-  hipLaunchKernelGGL((k_filter_spmm<T, VEC, NT>), dim3(groups), dim3(kThreads), 0, s, A.n, A.rowptr, A.col,
-                     A.val, A.band, w, Yin.p + c0, Yin.ld, Z.p ? Z.p + c0 : nullptr, Z.ld, Yout.p + c0, Yout.ld,
-                     alpha, beta, gamma, partial, wtot, c0);
+  const T *zp = Z.p ? Z.p + c0 : nullptr;
+  const int sel = (A.orp ? 4 : 0) + (zp ? 2 : 0) + (partial ? 1 : 0);
+#define ARR_SPMM_CASE(k, O, H, S)                                                                        \
+  case k:                                                                                               \
+    launch_variant<T, VEC, NT, O, H, S>(A, Yin, zp, Z.ld, Yout, w, c0, alpha, beta, gamma, partial, wtot, \
+                                        groups, s);                                                     \
+    break;
+  switch (sel) {
+    ARR_SPMM_CASE(0, false, false, false)
+    ARR_SPMM_CASE(1, false, false, true)
+    ARR_SPMM_CASE(2, false, true, false)
+    ARR_SPMM_CASE(3, false, true, true)
+    ARR_SPMM_CASE(4, true, false, false)
+    ARR_SPMM_CASE(5, true, false, true)
+    ARR_SPMM_CASE(6, true, true, false)
+    ARR_SPMM_CASE(7, true, true, true)
+  }
+#undef ARR_SPMM_CASE
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -281,31 +455,35 @@ int spmm_groups(int64_t n) {
   return (int)g;
 }
 
-void split_band(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, std::vector<int64_t> &frp,
-                std::vector<int32_t> &fcol, std::vector<double> &fval, std::vector<double> &band) {
-  frp.assign(n + 1, 0);
-  fcol.clear();
-  fval.clear();
-  band.assign(3 * n, 0.0);
-  const int64_t nnz = rowptr[n];
-  fcol.reserve(nnz);
-  fval.reserve(nnz);
+void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out) {
+  out.coef.assign(8 * n, 0.0);
+  out.fcol.assign(4 * n, 0);
+  out.orp.assign(n + 1, 0);
+  out.ocol.clear();
+  out.oval.clear();
   for (int64_t i = 0; i < n; ++i) {
+    int slot = 0;
+    for (int e = 0; e < 4; ++e) out.fcol[4 * i + e] = (int32_t)i;  // padding: column i, value 0
     for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
       const int64_t j = col[q];
       if (j == i - 1)
-        band[i] = val[q];
+        out.coef[8 * i] = val[q];
       else if (j == i)
-        band[n + i] = val[q];
+        out.coef[8 * i + 1] = val[q];
       else if (j == i + 1)
-        band[2 * n + i] = val[q];
-      else {
-        fcol.push_back((int32_t)j);
-        fval.push_back(val[q]);
+        out.coef[8 * i + 2] = val[q];
+      else if (slot < 4) {
+        out.fcol[4 * i + slot] = (int32_t)j;
+        out.coef[8 * i + 3 + slot] = val[q];
+        ++slot;
+      } else {
+        out.ocol.push_back((int32_t)j);
+        out.oval.push_back(val[q]);
       }
     }
-    frp[i + 1] = (int64_t)fcol.size();
+    out.orp[i + 1] = (int64_t)out.ocol.size();
   }
+  if (out.ocol.empty()) out.orp.clear();
 }
 
 template <typename T>
@@ -314,20 +492,24 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   const int w = Yout.w;
   ARR_REQUIRE(Yin.w >= w && (!Z.p || Z.w >= w), "filter_spmm: block widths differ");
   ARR_REQUIRE(Yin.p != Yout.p, "filter_spmm: Yout must not alias Yin");
-  ARR_REQUIRE(A.n == 0 || A.band, "filter_spmm: matrix band missing");
+  ARR_REQUIRE(A.n == 0 || (A.coef && A.fcol), "filter_spmm: matrix rows missing");
+  ARR_REQUIRE(!A.orp || (A.ocol && A.oval), "filter_spmm: overflow entries missing");
   const int groups = spmm_groups(A.n);
   if (A.n == 0 || w == 0) return groups;
   SpmmTimer *timer = spmm_timer();
   // FP32 with 16-byte aligned rows: 4 consecutive columns per lane
   const bool vec4 = sizeof(T) == 4 && Yin.ld % 4 == 0 && Yout.ld % 4 == 0 && (!Z.p || Z.ld % 4 == 0) &&
                     aligned16(Yin.p) && aligned16(Yout.p) && (!Z.p || aligned16(Z.p)) && w % 4 == 0;
-  // Column chunks of at most 1024 (16 slots per lane).
-  for (int c0 = 0; c0 < w; c0 += 1024) {
-    const int wc = std::min(1024, w - c0);
+  // Column chunks: at most 4 slots per lane for FP64 (256 columns), 2 with
+  // 16-byte FP32 loads (512 columns), 1 for FP32 rows that are not 16-byte
+  // aligned (64 columns)
+  const int chunk = vec4 ? 512 : sizeof(T) == 8 ? 256 : 64;
+  for (int c0 = 0; c0 < w; c0 += chunk) {
+    const int wc = std::min(chunk, w - c0);
     const T al = (T)alpha, be = (T)beta, ga = (T)gamma;
     const int slots = vec4 ? 4 * ((wc + 255) / 256) : (wc + 63) / 64;  // columns per lane
     const int cls = (slots <= 1 ? 0 : slots <= 2 ? 1 : slots <= 4 ? 2 : slots <= 8 ? 3 : 4) + (vec4 ? 5 : 0) +
-                    (sizeof(T) == 8 ? 10 : 0);
+                    (sizeof(T) == 8 ? 10 : 0) + (Z.p ? 20 : 0) + (A.orp ? 40 : 0) + (partial ? 80 : 0);
     SpmmTimer::Pending pend{};
     if (timer) {
       pend.a = timer->get();
@@ -339,29 +521,20 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
                    (double)sizeof(T) * A.n * wc * (2.0 + (Z.p ? 1.0 : 0.0));
       ARR_HIP(hipEventRecord(pend.a, s));
     }
-    bool done = false;
-    if constexpr (sizeof(T) == 4) {
-      if (vec4) {
+    if (vec4) {
+      if constexpr (sizeof(T) == 4) {
         if (wc <= 256)
           launch_nt<T, 4, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
-        else if (wc <= 512)
-          launch_nt<T, 4, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
         else
-          launch_nt<T, 4, 4>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
-        done = true;
+          launch_nt<T, 4, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
       }
-    }
-    if (done) {
     } else if (wc <= 64) {
       launch_nt<T, 1, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
-    } else if (wc <= 128) {
-      launch_nt<T, 1, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
-    } else if (wc <= 256) {
-      launch_nt<T, 1, 4>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
-    } else if (wc <= 512) {
-      launch_nt<T, 1, 8>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
-    } else {
-      launch_nt<T, 1, 16>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+    } else if constexpr (sizeof(T) == 8) {
+      if (wc <= 128)
+        launch_nt<T, 1, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+      else
+        launch_nt<T, 1, 4>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
     }
     if (timer) {
       ARR_HIP(hipEventRecord(pend.b, s));
@@ -376,8 +549,8 @@ template <typename T>
 void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s) {
   if (A.n == 0) return;
   const int64_t blocks = (A.n + 255) / 256;
-  hipLaunchKernelGGL((k_spmv<T>), dim3((unsigned)blocks), dim3(256), 0, s, A.n, A.rowptr, A.col, A.val, A.band, x,
-                     y);
+  hipLaunchKernelGGL((k_spmv<T>), dim3((unsigned)blocks), dim3(256), 0, s, A.n, A.coef, A.fcol, A.orp, A.ocol,
+                     A.oval, x, y);
   ARR_HIP(hipGetLastError());
 }
 

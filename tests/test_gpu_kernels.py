@@ -38,8 +38,24 @@ def tridiagonal(n=1001, seed=5):
     return W.from_scipy(S, "tridiagonal")
 
 
+def lap2d_holes(m=41, seed=4):
+    """2D 5-point Laplacian (two entries off the band per row, so no row
+    overflows the four far slots) with 50 rows and columns removed: empty
+    rows inside full runs of the pipelined path. n = 1681 is not a multiple
+    of the run length."""
+    rng = np.random.default_rng(seed)
+    S = W.laplacian_2d(m).to_scipy()
+    keep = np.ones(m * m)
+    keep[rng.choice(m * m, 50, replace=False)] = 0.0
+    D = sp.diags(keep)
+    S = sp.csr_matrix(D @ S @ D)
+    S.eliminate_zeros()
+    return W.from_scipy(S, "lap2d_holes")
+
+
 MATS = {
     "lap3d_12V": lambda: W.laplacian_3d(12, potential_seed=1),
+    "lap2d_holes": lap2d_holes,
     "powerlaw_4000": lambda: W.powerlaw_random(4000, seed=7, cap=300),
     "empty_rows": with_empty_rows,
     "tridiagonal": tridiagonal,
@@ -96,22 +112,38 @@ def test_filter_step_fp32(mat, w, ld):
     np.testing.assert_allclose(ss.cpu().numpy(), (got[:, :w] ** 2).sum(axis=0), rtol=1e-12)
 
 
+NO_Z_MATS = {"powerlaw_3000": lambda: W.powerlaw_random(3000, seed=9, cap=500), **MATS}
+
+
+@pytest.mark.parametrize("mat", list(NO_Z_MATS))
 @pytest.mark.parametrize("w", [1, 33, 240])
-def test_filter_step_fp32_and_no_z(w):
-    A = W.powerlaw_random(3000, seed=9, cap=500)
-    S = A.to_scipy()
-    Ad = arr.DeviceCSR(A, dtype=torch.float32)
-    rng = np.random.default_rng(1)
-    Yin = rng.standard_normal((A.n, w)).astype(np.float32)
-    Yd = dev(Yin, torch.float32)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("sums", [False, True])
+def test_filter_step_no_z(mat, w, dtype, sums):
+    """Y = alpha A X + beta X with no Z operand (the product form's factors),
+    with and without the column sums: every kernel variant on matrices with
+    and without rows past four far entries."""
+    A = NO_Z_MATS[mat]()
+    tdt, u = (torch.float32, 6e-8) if dtype == "f32" else (torch.float64, 1.2e-16)
+    Ad = arr.DeviceCSR(A, dtype=tdt)
+    vals = A.val.astype(np.float32).astype(np.float64) if dtype == "f32" else A.val
+    Sx = sp.csr_matrix((vals, A.colind, A.rowptr), shape=(A.n, A.n))
+    rng = np.random.default_rng(1 + w)
+    Yin = rng.standard_normal((A.n, w))
+    if dtype == "f32":
+        Yin = Yin.astype(np.float32).astype(np.float64)
+    Yd = dev(Yin, tdt)
     Od = torch.zeros_like(Yd)
-    arr.arr_filter_step(Ad, Yd, None, Od, 2.0, 0.25, 0.0)
+    ss = torch.zeros(w, dtype=torch.float64, device="cuda") if sums else None
+    arr.arr_filter_step(Ad, Yd, None, Od, 2.0, 0.25, 0.0, colsumsq=ss)
     torch.cuda.synchronize()
-    S32 = sp.csr_matrix((A.val.astype(np.float32).astype(np.float64), A.colind, A.rowptr), shape=S.shape)
-    Y64 = Yin.astype(np.float64)
-    ref = 2.0 * (S32 @ Y64) + 0.25 * Y64
-    bound = 2.0 * (abs(S32) @ np.abs(Y64)) + 0.25 * np.abs(Y64)
-    assert np.all(np.abs(Od.cpu().numpy() - ref) <= 600 * 6e-8 * bound + 1e-30)
+    got = Od.double().cpu().numpy()
+    ref = 2.0 * (Sx @ Yin) + 0.25 * Yin
+    bound = 2.0 * (abs(Sx) @ np.abs(Yin)) + 0.25 * np.abs(Yin)
+    kmax = int(np.diff(A.rowptr).max()) + 4
+    assert np.all(np.abs(got - ref) <= kmax * u * bound + 1e-30)
+    if sums:
+        np.testing.assert_allclose(ss.cpu().numpy(), (got ** 2).sum(axis=0), rtol=1e-12)
 
 
 @pytest.mark.parametrize("d", [3, 8, 15])
