@@ -83,6 +83,42 @@ def poly(Aop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, a: float, b: fl
     return Y
 
 
+def chebyshev_T(x, d: int):
+    """T_d(x) by the three-term recursion of eq. cheby-poly: T_0 = 1, T_1 = x,
+    T_{j+1} = 2 x T_j - T_{j-1}."""
+    x = np.asarray(x, dtype=np.float64)
+    t_prev, t = np.ones_like(x), x
+    if d == 0:
+        return t_prev
+    for _ in range(1, d):
+        t_prev, t = t, 2.0 * x * t - t_prev
+    return t
+
+
+def rho_chebyshev(t, a: float, b: float, d: int):
+    """The classic Chebyshev filter: T_d((2t - a - b)/(b - a)), [a,b] mapped
+    onto [-1,1] as in eq. rhod, with T_d of eq. cheby-poly in place of psi_d
+    (the alternative compared in Table comp-cheby)."""
+    return chebyshev_T((2.0 * np.asarray(t, dtype=np.float64) - a - b) / (b - a), d)
+
+
+def chebyshev_poly(Aop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, a: float, b: float,
+                   d: int) -> np.ndarray:
+    """Y = T_d(t(A)) X with t(A) = (2A - (a+b)I)/(b-a), by the block form of eq.
+    cheby-poly: Y_0 = X, Y_1 = t(A) X, Y_{j+1} = 2 t(A) Y_j - Y_{j-1}."""
+    assert d >= 1
+    c0 = (a + b) / (a - b)
+    c1 = 2.0 / (b - a)
+
+    def t(Y):
+        return c1 * Aop(Y) + c0 * Y
+
+    Y_prev, Y = X, t(X)
+    for _ in range(1, d):
+        Y_prev, Y = Y, 2.0 * t(Y) - Y_prev
+    return Y
+
+
 def shifted(A: sp.spmatrix, a: float) -> Callable[[np.ndarray], np.ndarray]:
     """The operator Y -> (A - aI) Y used by the inner solvers (Sec. 6, inner loop)."""
     return lambda Y: A @ Y - a * Y
@@ -238,14 +274,17 @@ def relative_residuals(A: sp.spmatrix, X: np.ndarray, mu: np.ndarray) -> np.ndar
 
 
 def degree_update(mu_k: float, mu_w: float, a: float, b: float, d_max: int,
-                  coeffs: Callable[[int], np.ndarray]) -> int:
+                  coeffs: Callable[[int], np.ndarray] | None = None,
+                  rho_d: Callable[[float, int], float] | None = None) -> int:
     """d = min(d_hat, d_max), d_hat = min{d >= 3 : rho_d(mu*_{k+q})/rho_d(mu*_k) < 0.9}
     (eq. hat-d, eq. degree). Reading: the ratio is taken in absolute value and
-    d = d_max when no d in [3, d_max] satisfies it."""
+    d = d_max when no d in [3, d_max] satisfies it. rho_d is eq. rhod with
+    psi_d (from ``coeffs``) unless ``rho_d(t, d)`` is given (Chebyshev mode)."""
+    if rho_d is None:
+        rho_d = lambda t, dd: rho(t, a, b, coeffs(dd))
     for d in range(3, d_max + 1):
-        g = coeffs(d)
-        num = abs(float(rho(mu_w, a, b, g)))
-        den = abs(float(rho(mu_k, a, b, g)))
+        num = abs(float(rho_d(mu_w, d)))
+        den = abs(float(rho_d(mu_k, d)))
         if den > 0.0 and num / den < 0.9:
             return d
     return d_max
@@ -266,6 +305,7 @@ class Options:
     stagnation: int = 3    # stop rule (ii)
     paper_faithful: bool = False  # stop rule (iii)
     inner: str = "mpm"     # inner solver of Algorithm 8: "mpm" or "gn"
+    poly: str = "interp"   # filter: "interp" (psi_d, Sec. 5) or "chebyshev" (T_d, eq. cheby-poly)
 
 
 @dataclasses.dataclass
@@ -297,6 +337,7 @@ def arrabit_mpm(A: sp.spmatrix, k: int, tol: float, X0: np.ndarray, which: str =
     the i.i.d. Gaussian starting block; its first column also starts Lanczos.
     """
     opts = opts or Options()
+    assert opts.poly in ("interp", "chebyshev") and opts.inner in ("mpm", "gn")
     A = sp.csr_matrix(A, dtype=np.float64)
     B = -A if which == "SA" else A
     n = B.shape[0]
@@ -333,16 +374,22 @@ def arrabit_mpm(A: sp.spmatrix, k: int, tol: float, X0: np.ndarray, which: str =
     for j in range(1, opts.maxit + 1):
         stats["outer"] = j
         opB = shifted(B, a)
+
+        def filt(Y, dd):
+            """rho_d(A - aI) Y over [0, b - a]: Algorithm 7's psi_d, or T_d."""
+            if opts.poly == "chebyshev":
+                return chebyshev_poly(opB, Y, 0.0, b - a, dd)
+            return poly(opB, Y, 0.0, b - a, coeffs(dd))
+
         rc = math.inf
         Qp = Qc if Qc.shape[1] else None
         for _i1 in range(opts.maxit1):
             for _i2 in range(opts.maxit2):
                 if opts.inner == "gn":
                     # GN branch: no normalization; X X^T tracks rho(A - aI)
-                    X = gn_step(opB, X, 0.0, b - a, coeffs(d))
+                    X = gn_update(X, lambda Y: filt(Y, d))
                 else:
-                    X = poly(opB, X, 0.0, b - a, coeffs(d))
-                    X = normalize_columns(X)
+                    X = normalize_columns(filt(X, d))
                 stats["poly_calls"] += 1
                 stats["spmm_degrees"] += d
                 stats["block_spmm_cols"] += d * X.shape[1]
@@ -398,7 +445,11 @@ def arrabit_mpm(A: sp.spmatrix, k: int, tol: float, X0: np.ndarray, which: str =
                 p = min(p + 1, opts.p_max)
         maxresp = maxres
         # degree (eq. hat-d, eq. degree) from the best iterate so far
-        d = degree_update(best_mu[0], best_mu[1], a, b, opts.d_max, coeffs)
+        if opts.poly == "chebyshev":
+            d = degree_update(best_mu[0], best_mu[1], a, b, opts.d_max,
+                              rho_d=lambda t, dd: rho_chebyshev(t, a, b, dd))
+        else:
+            d = degree_update(best_mu[0], best_mu[1], a, b, opts.d_max, coeffs)
         if X.shape[1] == 0:  # every pair locked; nothing left to iterate
             break
 
