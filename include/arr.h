@@ -66,8 +66,12 @@ typedef enum { ARR_INNER_MPM = 0, ARR_INNER_GN = 1 } arr_inner_t;
  * ordered, with A' the shifted and scaled operator of Algorithm 7: one
  * gathered read and one write of the block per degree. ARR_POLY_HORNER:
  * Algorithm 7's Horner recurrence on the monomial coefficients Gamma_d, which
- * also reads X every degree. The two are the same polynomial. */
-typedef enum { ARR_POLY_PRODUCT = 0, ARR_POLY_HORNER = 1 } arr_poly_form_t;
+ * also reads X every degree. The two are the same polynomial.
+ * ARR_POLY_CHEBYSHEV: the classic Chebyshev polynomial T_d of eq. cheby-poly
+ * on the same mapped operator instead of psi_d (the alternative of Table
+ * comp-cheby), by its three-term recursion (reads Y_{j-1} every degree); the
+ * degree rule eq. hat-d is then evaluated on T_d. */
+typedef enum { ARR_POLY_PRODUCT = 0, ARR_POLY_HORNER = 1, ARR_POLY_CHEBYSHEV = 2 } arr_poly_form_t;
 
 /* Host CSR description (arr_create deep-copies it to the device). */
 typedef struct {
@@ -270,7 +274,8 @@ int arr_filter_roots(int32_t d, double *roots, double *lead);
 
 /* Apply the library's filter psi_d of Sec. 5 as Algorithm 8 does:
  * X <- psi_d(c0 I + c1 (A - shift I)) X with c0 = (lo + hi)/(lo - hi),
- * c1 = 2/(hi - lo), in the given arr_poly_form_t. X is a device block n x w
+ * c1 = 2/(hi - lo), in the given arr_poly_form_t (ARR_POLY_CHEBYSHEV: T_d of
+ * eq. cheby-poly in place of psi_d). X is a device block n x w
  * (ld, A's dtype), overwritten. Temporary device memory is allocated
  * internally. Synchronous. */
 int arr_filter(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo, double hi,

@@ -31,6 +31,7 @@ INNER_MPM = 0
 INNER_GN = 1
 POLY_PRODUCT = 0
 POLY_HORNER = 1
+POLY_CHEBYSHEV = 2
 
 
 class ArrError(RuntimeError):

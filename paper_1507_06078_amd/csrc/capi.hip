@@ -349,7 +349,8 @@ int arr_filter(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double sh
                int32_t d, int32_t form, void *stream) {
   return guarded(nullptr, [&]() {
     ARR_REQUIRE(A && X && d >= 1 && d <= 64 && w >= 0 && ld >= w, "filter: bad arguments");
-    ARR_REQUIRE(form == ARR_POLY_PRODUCT || form == ARR_POLY_HORNER, "filter: unknown form");
+    ARR_REQUIRE(form == ARR_POLY_PRODUCT || form == ARR_POLY_HORNER || form == ARR_POLY_CHEBYSHEV,
+                "filter: unknown form");
     hipStream_t s = as_stream(stream);
     const arr::FilterPoly fp = arr::filter_poly(d);
     arr::Work wk;

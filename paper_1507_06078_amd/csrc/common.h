@@ -294,8 +294,9 @@ struct FilterPoly {
 };
 FilterPoly filter_poly(int d);
 // Form of the filter application: the product of d linear factors (2 block
-// passes per degree) or Algorithm 7's Horner recurrence (3 block passes).
-enum PolyForm { kPolyProduct = 0, kPolyHorner = 1 };
+// passes per degree) or Algorithm 7's Horner recurrence (3 block passes); or
+// the classic Chebyshev polynomial T_d (eq. cheby-poly) in place of psi_d.
+enum PolyForm { kPolyProduct = 0, kPolyHorner = 1, kPolyChebyshev = 2 };
 // The same interpolant in the Chebyshev basis: psi_d = sum_k c[k] T_k.
 std::vector<double> filter_chebyshev_coefficients(int d);
 

@@ -93,7 +93,8 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
   ARR_REQUIRE(o.maxit >= 1 && o.maxit1 >= 1 && o.maxit2 >= 1, "iteration limits must be >= 1");
   ARR_REQUIRE(o.precision == ARR_FP64 || o.precision == ARR_MIXED, "unknown precision");
   ARR_REQUIRE(o.inner_solver == ARR_INNER_MPM || o.inner_solver == ARR_INNER_GN, "unknown inner solver");
-  ARR_REQUIRE(o.poly_form == ARR_POLY_PRODUCT || o.poly_form == ARR_POLY_HORNER, "unknown polynomial form");
+  ARR_REQUIRE(o.poly_form == ARR_POLY_PRODUCT || o.poly_form == ARR_POLY_HORNER || o.poly_form == ARR_POLY_CHEBYSHEV,
+              "unknown polynomial form");
   // validate CSR on the host
   const int64_t *rp = csr->rowptr;
   ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
@@ -310,16 +311,25 @@ void Solver::setup_interval() {
 }
 
 int Solver::degree_update(double mu_k, double mu_w) {
-  // eq. hat-d / eq. degree with rho_d(t) = psi_d((2t - a - b)/(b - a))
-  auto rho = [&](const std::vector<double> &g, double t) {
+  // eq. hat-d / eq. degree with rho_d(t) = psi_d((2t - a - b)/(b - a)), or
+  // T_d of eq. cheby-poly at the same point in the Chebyshev mode
+  auto rho = [&](int d, double t) {
     const double x = (2.0 * t - a_ - b_) / (b_ - a_);
+    if (o_.poly_form == ARR_POLY_CHEBYSHEV) {
+      double tp = 1.0, tc = x;
+      for (int j = 1; j < d; ++j) {
+        const double tn = 2.0 * x * tc - tp;
+        tp = tc;
+        tc = tn;
+      }
+      return tc;
+    }
     double v = 0.0;
-    for (double c : g) v = v * x + c;
+    for (double c : coeffs(d).gamma) v = v * x + c;
     return v;
   };
   for (int d = 3; d <= o_.d_max; ++d) {
-    const std::vector<double> &g = coeffs(d).gamma;
-    const double num = std::fabs(rho(g, mu_w)), den = std::fabs(rho(g, mu_k));
+    const double num = std::fabs(rho(d, mu_w)), den = std::fabs(rho(d, mu_k));
     if (den > 0.0 && num / den < 0.9) return d;
   }
   return o_.d_max;

@@ -119,11 +119,38 @@ void poly_apply_product(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doub
   wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, none, X, c1, beta(d - 1), 0.0, partial, s);
 }
 
+// The classic Chebyshev filter (eq. cheby-poly) in place of psi_d:
+// X <- T_d(t) X with t = c0 I + c1 (A - shift I), by Y_1 = t X and
+// Y_{j+1} = 2 t Y_j - Y_{j-1}: one fused SpMM per degree whose recurrence
+// operand is Y_{j-1}. Y_j lives in buffer j mod 3 of (X, Ya, Yb); when d is
+// not a multiple of 3 the result is copied into X.
+template <typename T>
+void poly_apply_chebyshev(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
+                          int d, Work &wk, bool want_norms, hipStream_t s) {
+  ARR_REQUIRE(d >= 1, "poly: degree must be >= 1");
+  ARR_REQUIRE(hi != lo, "poly: empty interval");
+  const int w = X.w;
+  double *partial = want_norms ? wk.partial.as<double>() : nullptr;
+  const double c0 = (lo + hi) / (lo - hi), c1 = 2.0 / (hi - lo);
+  const double b1 = c0 - c1 * shift;  // t = c1 A + b1 I
+  const Blk<T> buf[3] = {Blk<T>{X.p, X.ld, w}, Blk<T>{Ya.p, Ya.ld, w}, Blk<T>{Yb.p, Yb.ld, w}};
+  auto in = [&](int j) { return Blk<const T>{buf[j % 3].p, buf[j % 3].ld, w}; };
+  const Blk<const T> none{nullptr, 0, 0};
+  int groups = launch_filter_spmm<T>(A, in(0), none, buf[1], c1, b1, 0.0, d == 1 ? partial : nullptr, s);
+  for (int j = 1; j < d; ++j)
+    groups = launch_filter_spmm<T>(A, in(j), in(j - 1), buf[(j + 1) % 3], 2.0 * c1, 2.0 * b1, -1.0,
+                                   j == d - 1 ? partial : nullptr, s);
+  if (d % 3 != 0) launch_copy<T>(A.n, w, X.p, X.ld, buf[d % 3].p, buf[d % 3].ld, s);
+  if (want_norms) wk.groups = groups;
+}
+
 template <typename T>
 void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
                 const FilterPoly &fp, int form, Work &wk, bool want_norms, hipStream_t s) {
   if (form == kPolyHorner)
     poly_apply_horner<T>(A, X, Ya, Yb, shift, lo, hi, fp.gamma, wk, want_norms, s);
+  else if (form == kPolyChebyshev)
+    poly_apply_chebyshev<T>(A, X, Ya, Yb, shift, lo, hi, (int)fp.gamma.size() - 1, wk, want_norms, s);
   else
     poly_apply_product<T>(A, X, Ya, Yb, shift, lo, hi, fp.roots, fp.lead, wk, want_norms, s);
 }

@@ -182,6 +182,24 @@ def test_filter_forms_match_oracle_fp64(d, form):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 8, 15])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_chebyshev_filter_matches_oracle(d, dtype):
+    """The classic Chebyshev filter T_d (eq. cheby-poly) on the mapped operator,
+    against the oracle's recursion; d mod 3 covers every buffer rotation."""
+    A = W.laplacian_3d(12, potential_seed=1)
+    S = -A.to_scipy()
+    lam = np.linalg.eigvalsh(S.toarray())
+    a, b = lam[0] - 0.01, lam[-40]
+    X = W.gaussian_block(A.n, 37, seed=4)
+    ref = O.chebyshev_poly(O.shifted(S, a), X, 0.0, b - a, d)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    Xd = dev(X, tdt)
+    arr.arr_filter(arr.DeviceCSR(A.negated(), dtype=tdt), Xd, a, 0.0, b - a, d, arr.POLY_CHEBYSHEV)
+    err = np.abs(Xd.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err <= (1e-12 if dtype == "f64" else 2e-6 * d), err
+
+
 def test_filter_product_fp32_more_accurate_than_horner():
     """In FP32 the product form keeps psi_15's accuracy (no cancellation of
     large monomial terms); Algorithm 7's monomial recurrence loses about

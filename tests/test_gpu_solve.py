@@ -84,6 +84,25 @@ def test_c1_gn_inner_solver_matches_oracle_and_closed_form(precision):
     assert_same_subspaces(ev, X, ref.evecs)
 
 
+@pytest.mark.parametrize("precision,inner", [(arr.FP64, arr.INNER_MPM), (arr.MIXED, arr.INNER_MPM),
+                                             (arr.FP64, arr.INNER_GN)])
+def test_c1_chebyshev_mode_matches_oracle_and_closed_form(precision, inner):
+    """Algorithm 8 with the classic Chebyshev filter T_d in place of psi_d
+    (Table comp-cheby's alternative), MPM and GN inner solvers."""
+    A, k, which, w, tol = W.workload("lap2d_40")
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    status, ev, X, res, st = solve(A, k, which, tol, w=w, precision=precision, X0=X0, inner_solver=inner,
+                                   poly_form=arr.POLY_CHEBYSHEV)
+    assert status == arr.ARR_OK, st
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    ref = O.arrabit_mpm(A.to_scipy(), k, 1e-12, X0, which,
+                        O.Options(poly="chebyshev", inner="gn" if inner == arr.INNER_GN else "mpm"))
+    assert np.all(np.abs(ev - exact) <= 1e-10 * np.maximum(1, np.abs(exact)))
+    assert np.all(np.abs(ev - ref.evals) <= 1e-10 * np.maximum(1, np.abs(ref.evals)))
+    check_pairs(A, ev, X, tol)
+    assert_same_subspaces(ev, X, ref.evecs)
+
+
 @pytest.mark.parametrize("which", ["LA", "SA"])
 def test_gn_random_symmetric_vs_dense(which):
     n, k, w = 300, 8, 12
