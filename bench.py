@@ -322,7 +322,7 @@ def main():
                     help="also run the same stream on the plain FP64 path, one request at a time")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the row-sharded multi-GPU design is documented but not built)", file=sys.stderr)
         sys.exit(2)
 
