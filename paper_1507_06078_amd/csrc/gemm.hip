@@ -113,23 +113,29 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T *__restrict__ X
   const int64_t r1 = min(n, r0 + chunk);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int qx = (wv & 1) * HALF, qy = (wv >> 1) * HALF;
-  __shared__ T Xs[2][KS][TILE + 1], Ys[2][KS][TILE + 1];
-  const int lr = tid / (TILE / PER), lc = (tid % (TILE / PER)) * PER;
+  // thread t stages column
+  // t % TILE of rows t / TILE + q * (256 / TILE): coalesced loads, and
+  // consecutive lanes write consecutive LDS words
+  constexpr int PAD = 1;
+  __shared__ T Xs[2][KS][TILE + PAD], Ys[2][KS][TILE + PAD];
+  constexpr int RSTEP = 256 / TILE;
+  const int lc = tid % TILE, lr0 = tid / TILE;
   T xv[PER], yv[PER];
   auto gload = [&](int64_t rb) {
-    const int64_t row = rb + lr;
-    const bool rok = row < r1;
+    const bool cxok = cx + lc < mx, cyok = cy + lc < my;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      xv[q] = (rok && cx + lc + q < mx) ? X[row * ldx + cx + lc + q] : T(0);
-      yv[q] = (rok && cy + lc + q < my) ? Y[row * ldy + cy + lc + q] : T(0);
+      const int64_t row = rb + lr0 + q * RSTEP;
+      const bool rok = row < r1;
+      xv[q] = (rok && cxok) ? X[row * ldx + cx + lc] : T(0);
+      yv[q] = (rok && cyok) ? Y[row * ldy + cy + lc] : T(0);
     }
   };
   auto lstore = [&](int b) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      Xs[b][lr][lc + q] = xv[q];
-      Ys[b][lr][lc + q] = yv[q];
+      Xs[b][lr0 + q * RSTEP][lc] = xv[q];
+      Ys[b][lr0 + q * RSTEP][lc] = yv[q];
     }
   };
   v4d acc[FB][FB];
