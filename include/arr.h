@@ -174,10 +174,13 @@ typedef struct arr_solver *arr_handle_t;
 void arr_options_default(arr_options_t *o);
 
 /* Problem setup: the k extreme eigenpairs of A with residual tolerance tol
- * (eq. out-stop, eq. resi). Copies the CSR to the device, validates it
- * (bounds, 0 < k <= w, (p_max+1) w < n as required by Algorithm 8, tol > 0) and
- * allocates every device block of the solve (about (p_max+3) n w values plus
- * the CSR). The caller keeps ownership of csr's arrays and may free them on
+ * (eq. out-stop, eq. resi). Validates on the host (row pointers, column
+ * bounds and order, finite values, symmetry, 0 < k <= w, (p_max+1) w < n as
+ * required by Algorithm 8, tol > 0) and keeps a host copy of the matrix in
+ * the SpMM's row form. Device memory (about (p_max+3) n w values plus the
+ * matrix; arr_footprint gives the exact size) is allocated and the matrix
+ * uploaded by the first arr_solve, or on admission when the handle is
+ * served. The caller keeps ownership of csr's arrays and may free them on
  * return. n must equal csr->n. On success *out is a new handle that the
  * caller releases with arr_destroy. */
 int arr_create(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,
