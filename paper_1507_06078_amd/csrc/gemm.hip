@@ -226,15 +226,16 @@ __global__ void k_gram_reduce(const double *__restrict__ part, int nsplit, int m
 
 // Block update tile kernel: a workgroup owns a TILE x TILE tile of Y (64, or
 // 128 for the FP32 matrix cores once Y has 128 columns: half the loads per
-// flop) and
-// walks k in steps of 16 through LDS with the next step prefetched into
-// registers; wave q accumulates the (TILE/2)-square quadrant (q & 1, q >> 1).
+// flop) and walks k in steps of 16 through two LDS buffers: the next step is
+// loaded into registers while the current one is multiplied, then stored into
+// the other buffer (one barrier per step); wave q accumulates the
+// (TILE/2)-square quadrant (q & 1, q >> 1).
 template <typename T, bool kMma32, int TILE>
 __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__ X, int64_t ldx, int m,
                                                 const double *__restrict__ W, int64_t ldw, int c, double alpha,
                                                 double beta, T *Y, int64_t ldy, int nct, int64_t nrt, int w_upper) {
   static_assert(TILE == 64 || TILE == 128, "tile is 64 or 128");
-  constexpr int FB = TILE / 32, HALF = TILE / 2, PER = TILE / 16;
+  constexpr int FB = TILE / 32, HALF = TILE / 2;
   // tile order: XCD x gets workgroups b = x + 8 t; t walks the column tiles of
   // one row band before moving to the next band of that XCD.
   const int xcd = blockIdx.x % kXcd;
@@ -255,8 +256,11 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
   static_assert(!kMma32 || std::is_same<T, float>::value, "FP32 matrix cores need FP32 data");
   typedef typename std::conditional<kMma32, float, double>::type S;
   typedef typename std::conditional<kMma32, v4f, v4d>::type acc_t;
-  __shared__ S Xs[TILE][17];
-  __shared__ S Ws[16][TILE + 1];
+  constexpr int KS = 16;                 // k per stage
+  constexpr int PX = TILE * KS / 256;      // X elements per thread and stage
+  constexpr int PW = KS * TILE / 256;      // W elements per thread and stage
+  __shared__ S Xs[2][TILE][KS + 1];
+  __shared__ S Ws[2][KS][TILE + 1];
 
   acc_t acc[FB][FB];
 #pragma unroll
@@ -264,35 +268,44 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
 #pragma unroll
     for (int g = 0; g < FB; ++g) acc[f][g] = acc_t{0, 0, 0, 0};
 
-  const int xr_ = tid / (16 / PER), xk = (tid % (16 / PER)) * PER;  // X tile: TILE rows x 16 k
-  const int wk_ = tid / 16, wc = (tid % 16) * PER;                  // W tile: 16 k x TILE cols
+  const int xr_ = tid / (KS / PX), xk = (tid % (KS / PX)) * PX;      // X tile: TILE rows x KS k
+  const int wk_ = tid / (TILE / PW), wc = (tid % (TILE / PW)) * PW;  // W tile: KS k x TILE cols
   const int64_t xrow = r0 + xr_;
-  S xv[PER], wvv[PER];
+  S xv[PX], wvv[PW];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
+    for (int q = 0; q < PX; ++q) {
       const int kk = k0 + xk + q;
       xv[q] = (xrow < n && kk < kend) ? (S)X[xrow * ldx + kk] : S(0);
+    }
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
       const int kw = k0 + wk_, cc = c0 + wc + q;
       wvv[q] = (kw < kend && cc < c) ? (S)W[(int64_t)kw * ldw + cc] : S(0);
     }
   };
-  if (kend > 0) load(0);
-  for (int k0 = 0; k0 < kend; k0 += 16) {
+  auto stash = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      Xs[xr_][xk + q] = xv[q];
-      Ws[wk_][wc + q] = wvv[q];
-    }
-    __syncthreads();
-    if (k0 + 16 < kend) load(k0 + 16);
+    for (int q = 0; q < PX; ++q) Xs[b][xr_][xk + q] = xv[q];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int q = 0; q < PW; ++q) Ws[b][wk_][wc + q] = wvv[q];
+  };
+  int buf = 0;
+  if (kend > 0) {
+    load(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < kend; k0 += KS) {
+    const bool more = k0 + KS < kend;
+    if (more) load(k0 + KS);
+#pragma unroll
+    for (int ks = 0; ks < KS / 4; ++ks) {
       S a[FB], b[FB];
 #pragma unroll
       for (int f = 0; f < FB; ++f) {
-        a[f] = Xs[qx + 16 * f + li][4 * ks + lk];
-        b[f] = Ws[4 * ks + lk][qy + 16 * f + li];
+        a[f] = Xs[buf][qx + 16 * f + li][4 * ks + lk];
+        b[f] = Ws[buf][4 * ks + lk][qy + 16 * f + li];
       }
 #pragma unroll
       for (int f = 0; f < FB; ++f)
@@ -304,7 +317,9 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
             acc[f][g] = mfma16(a[f], b[g], acc[f][g]);
         }
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int f = 0; f < FB; ++f)
