@@ -122,3 +122,38 @@ def test_footprint_is_host_arithmetic():
     assert arr.arr_footprint(h2) >= fp + 4 * n * (3 * ldz + 2 * ldq)
     h.close()
     h2.close()
+
+
+def test_step_entry_points_reject_bad_arguments_on_host():
+    """The filter, roots and GN entry points validate their scalar arguments
+    before touching device memory (fake, never dereferenced pointers here)."""
+    L = arr.lib()
+    fake = ctypes.c_void_p(0x1000)
+    A = arr.arr_dev_csr_t(n=100, nnz=300, rowptr=fake, colind=fake, val=fake, dtype=0)
+    bad = [
+        lambda: L.arr_filter(ctypes.byref(A), 8, fake, 8, 0.0, 0.0, 1.0, 3, 3, None),   # unknown form
+        lambda: L.arr_filter(ctypes.byref(A), 8, fake, 8, 0.0, 0.0, 1.0, 0, 0, None),   # d = 0
+        lambda: L.arr_filter(ctypes.byref(A), 8, fake, 8, 0.0, 0.0, 1.0, 65, 0, None),  # d > 64
+        lambda: L.arr_filter(ctypes.byref(A), 8, fake, 4, 0.0, 0.0, 1.0, 3, 2, None),   # ld < w
+        lambda: L.arr_filter(ctypes.byref(A), 8, None, 8, 0.0, 0.0, 1.0, 3, 2, None),   # X NULL
+        lambda: L.arr_gn_step(ctypes.byref(A), 8, fake, 8, 0.0, 0.0, 1.0, None, 3, None),  # gamma NULL
+        lambda: L.arr_gn_step(ctypes.byref(A), 0, fake, 8, 0.0, 0.0, 1.0, fake, 3, None),  # w = 0
+    ]
+    for call in bad:
+        assert call() == arr.ARR_EINVAL
+    r = np.zeros(70)
+    lead = ctypes.c_double()
+    assert L.arr_filter_roots(0, r.ctypes.data, ctypes.addressof(lead)) == arr.ARR_EINVAL
+    assert L.arr_filter_roots(65, r.ctypes.data, ctypes.addressof(lead)) == arr.ARR_EINVAL
+    assert L.arr_filter_roots(3, None, ctypes.addressof(lead)) == arr.ARR_EINVAL
+
+
+def test_options_reject_unknown_filter_form_and_inner_solver():
+    A = W.laplacian_2d(8)
+    for field, value in (("poly_form", 3), ("inner_solver", 2)):
+        o = arr.arr_options_default()
+        o.w = 6
+        setattr(o, field, value)
+        with pytest.raises(arr.ArrError) as e:
+            arr.arr_create(A, A.n, 4, arr.SMALLEST, 1e-8, o)
+        assert e.value.code == arr.ARR_EINVAL
