@@ -112,6 +112,50 @@ def test_filter_step_fp32(mat, w, ld):
     np.testing.assert_allclose(ss.cpu().numpy(), (got[:, :w] ** 2).sum(axis=0), rtol=1e-12)
 
 
+def _small_matrix(kind, n):
+    if kind == "band5":  # tridiagonal plus the diagonals at +-5: two far entries a row, no overflow
+        rng = np.random.default_rng(n)
+        diags, offs = [rng.standard_normal(n) + 4.0], [0]
+        for k in (1, 5):
+            if k < n:
+                v = rng.standard_normal(n - k)
+                diags += [v, v]
+                offs += [k, -k]
+        return W.from_scipy(sp.diags(diags, offs, shape=(n, n), format="csr"), "band5")
+    return W.random_symmetric(n, seed=n, density=0.08 if kind == "sparse" else 0.5)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 33, 34, 35, 66, 97])
+@pytest.mark.parametrize("kind", ["band5", "sparse", "dense"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_filter_step_small_n(n, kind, dtype):
+    """Matrices shorter than one or two 32-row runs: the guarded row path, a
+    single full run, and full runs next to ragged ones; without overflow rows
+    (band5) and with them (random sparse and dense rows)."""
+    A = _small_matrix(kind, n)
+    tdt, u = (torch.float32, 6e-8) if dtype == "f32" else (torch.float64, 1.2e-16)
+    vals = A.val.astype(np.float32).astype(np.float64) if dtype == "f32" else A.val
+    Sx = sp.csr_matrix((vals, A.colind, A.rowptr), shape=(A.n, A.n))
+    Ad = arr.DeviceCSR(A, dtype=tdt)
+    for w in (1, 5, 65):
+        rng = np.random.default_rng(w)
+        Yin = rng.standard_normal((n, w))
+        Z = rng.standard_normal((n, w))
+        if dtype == "f32":
+            Yin = Yin.astype(np.float32).astype(np.float64)
+            Z = Z.astype(np.float32).astype(np.float64)
+        Yd, Zd = dev(Yin, tdt), dev(Z, tdt)
+        Od = torch.zeros_like(Yd)
+        ss = torch.zeros(w, dtype=torch.float64, device="cuda")
+        arr.arr_filter_step(Ad, Yd, Zd, Od, 0.5, -0.25, 2.0, colsumsq=ss)
+        got = Od.double().cpu().numpy()
+        ref = 0.5 * (Sx @ Yin) - 0.25 * Yin + 2.0 * Z
+        bound = 0.5 * (abs(Sx) @ np.abs(Yin)) + 0.25 * np.abs(Yin) + 2.0 * np.abs(Z)
+        kmax = int(np.diff(A.rowptr).max()) + 4
+        assert np.all(np.abs(got - ref) <= kmax * u * bound + 1e-30), (n, w)
+        np.testing.assert_allclose(ss.cpu().numpy(), (got ** 2).sum(axis=0), rtol=1e-12)
+
+
 NO_Z_MATS = {"powerlaw_3000": lambda: W.powerlaw_random(3000, seed=9, cap=500), **MATS}
 
 
