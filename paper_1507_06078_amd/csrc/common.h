@@ -206,10 +206,12 @@ size_t gram_work_bound(int64_t n, int m_max);
 // Y = beta*Y + alpha * X * W with W FP64 (m x c, ldw) on the device; w_upper:
 // W is upper triangular (its zero blocks are skipped). Y must not alias X.
 // fp32_cores (FP32 data only): W rounded to FP32 and FP32 matrix cores, for a
-// well-conditioned W such as an orthogonal rotation.
+// well-conditioned W such as an orthogonal rotation. colss (device, c values,
+// may be null): column j of the result is divided by sqrt(colss[j]).
 template <typename T>
 void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int c, double alpha,
-                   double beta, Blk<T> Y, hipStream_t s, bool w_upper = false, bool fp32_cores = false);
+                   double beta, Blk<T> Y, hipStream_t s, bool w_upper = false, bool fp32_cores = false,
+                   const double *colss = nullptr);
 
 // ---- launchers (misc.hip) ----------------------------------------------------
 

@@ -233,7 +233,8 @@ __global__ void k_gram_reduce(const double *__restrict__ part, int nsplit, int m
 template <typename T, bool kMma32, int TILE>
 __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__ X, int64_t ldx, int m,
                                                 const double *__restrict__ W, int64_t ldw, int c, double alpha,
-                                                double beta, T *Y, int64_t ldy, int nct, int64_t nrt, int w_upper) {
+                                                double beta, T *Y, int64_t ldy, int nct, int64_t nrt, int w_upper,
+                                                const double *__restrict__ colss) {
   static_assert(TILE == 64 || TILE == 128, "tile is 64 or 128");
   constexpr int FB = TILE / 32, HALF = TILE / 2;
   // tile order: XCD x gets workgroups b = x + 8 t; t walks the column tiles of
@@ -327,6 +328,7 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
     for (int g = 0; g < FB; ++g) {
       const int col = c0 + qy + 16 * g + li;
       if (col >= c) continue;
+      const double sc = colss ? 1.0 / sqrt(colss[col]) : 1.0;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t row = r0 + qx + 16 * f + (kMma32 ? 4 * lk + e : lk + 4 * e);
@@ -334,6 +336,7 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T *__restrict__
         T *yp = Y + row * ldy + col;
         double v = alpha * (double)acc[f][g][e];
         if (beta != 0.0) v += beta * (double)(*yp);
+        if (colss) v *= sc;
         *yp = (T)v;
       }
     }
@@ -401,7 +404,7 @@ void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *w
 
 template <typename T>
 void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int c, double alpha, double beta,
-                   Blk<T> Y, hipStream_t s, bool w_upper, bool fp32_cores) {
+                   Blk<T> Y, hipStream_t s, bool w_upper, bool fp32_cores, const double *colss) {
   const int m = X.w;
   if (n == 0 || c == 0) return;
   // algorithmic flops: 2 n m c, or with W upper triangular 2 n sum_j min(m, j + 1)
@@ -427,13 +430,13 @@ void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int 
     float *yf = (float *)Y.p;
     if (tile == 128)
       hipLaunchKernelGGL((k_update<float, true, 128>), grid, dim3(256), 0, s, n, xf, X.ld, m, W, ldw, c, alpha,
-                         beta, yf, Y.ld, nct, nrt, wu);
+                         beta, yf, Y.ld, nct, nrt, wu, colss);
     else
       hipLaunchKernelGGL((k_update<float, true, 64>), grid, dim3(256), 0, s, n, xf, X.ld, m, W, ldw, c, alpha,
-                         beta, yf, Y.ld, nct, nrt, wu);
+                         beta, yf, Y.ld, nct, nrt, wu, colss);
   } else {
     hipLaunchKernelGGL((k_update<T, false, 64>), grid, dim3(256), 0, s, n, X.p, X.ld, m, W, ldw, c, alpha, beta,
-                       Y.p, Y.ld, nct, nrt, wu);
+                       Y.p, Y.ld, nct, nrt, wu, colss);
   }
   ARR_HIP(hipGetLastError());
 }
@@ -443,8 +446,8 @@ template void launch_gram<double>(int64_t, Blk<const double>, Blk<const double>,
 template void launch_gram<float>(int64_t, Blk<const float>, Blk<const float>, double *, double *, bool,
                                  hipStream_t, bool);
 template void launch_update<double>(int64_t, Blk<const double>, const double *, int64_t, int, double, double,
-                                    Blk<double>, hipStream_t, bool, bool);
+                                    Blk<double>, hipStream_t, bool, bool, const double *);
 template void launch_update<float>(int64_t, Blk<const float>, const double *, int64_t, int, double, double,
-                                   Blk<float>, hipStream_t, bool, bool);
+                                   Blk<float>, hipStream_t, bool, bool, const double *);
 
 }  // namespace arr

@@ -408,11 +408,13 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
         if (o_.inner_solver == ARR_INNER_GN) {
           // GN branch: no normalization; Y in Z's second segment, rho(A) Y in W
           gn_step<T>(A, X, B.Z(wp_, wp_), B.W(0, wp_), Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, s_);
+          if (nc_) project_out<T>(n, Qc, X, wk_, s_);
         } else {
+          // MPM: normalize the columns, then X - Qc (Qc^T X); the scaling rides
+          // in the projection's update when Qc is not empty
           poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, true, s_);
-          normalize_from_partial<T>(n, X, wk_, s_);
+          normalize_and_project<T>(n, Qc, X, wk_, s_);
         }
-        if (nc_) project_out<T>(n, Qc, X, wk_, s_);
         stats.poly_calls += 1;
         stats.spmm_degrees += d_;
         stats.spmm_cols += (int64_t)d_ * wp_;

@@ -40,8 +40,15 @@ template <typename T>
 void normalize_from_partial(int64_t n, Blk<T> X, Work &wk, hipStream_t s);
 template <typename T>
 void normalize(int64_t n, Blk<T> X, Work &wk, hipStream_t s);
+// X <- X - Q (Q^T X); with colss (device, X.w values) the result's column j
+// is also divided by sqrt(colss[j]) (the projection commutes with it).
 template <typename T>
-void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s);
+void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s, const double *colss = nullptr);
+// The multi-power normalization of the filter's output (column sums of
+// squares left in wk.partial by its last SpMM) fused with the projection out
+// of Q (deflation): one block pass instead of two when Q is not empty.
+template <typename T>
+void normalize_and_project(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s);
 // One GN inner iteration (Sec. 4, GN branch of Algorithm 8); Y, Z, Ya, Yb are
 // n x X.w scratch blocks.
 template <typename T>

@@ -169,13 +169,23 @@ void normalize(int64_t n, Blk<T> X, Work &wk, hipStream_t s) {
 }
 
 template <typename T>
-void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s) {
-  if (Q.w == 0 || X.w == 0) return;
+void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s, const double *colss) {
+  if (X.w == 0) return;
+  if (Q.w == 0) {
+    if (colss) launch_scale_columns<T>(n, X, colss, true, s);
+    return;
+  }
   wk.ensure_gram(n, Q.w, X.w);
   wk.proj.ensure(sizeof(double) * (size_t)Q.w * X.w);
   double *C = wk.proj.as<double>();
   launch_gram<T>(n, Q, Blk<const T>{X.p, X.ld, X.w}, C, wk.gramw.as<double>(), false, s);
-  launch_update<T>(n, Q, C, X.w, X.w, -1.0, 1.0, X, s);
+  launch_update<T>(n, Q, C, X.w, X.w, -1.0, 1.0, X, s, false, false, colss);
+}
+
+template <typename T>
+void normalize_and_project(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s) {
+  launch_reduce_groups(wk.partial.as<double>(), wk.groups, X.w, wk.colv.as<double>(), false, s);
+  project_out<T>(n, Q, X, wk, s, wk.colv.as<double>());
 }
 
 template <typename T>
@@ -330,7 +340,8 @@ std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, c
                               const FilterPoly &, int, Work &, bool, hipStream_t);                               \
   template void normalize_from_partial<T>(int64_t, Blk<T>, Work &, hipStream_t);                                 \
   template void normalize<T>(int64_t, Blk<T>, Work &, hipStream_t);                                              \
-  template void project_out<T>(int64_t, Blk<const T>, Blk<T>, Work &, hipStream_t);                             \
+  template void project_out<T>(int64_t, Blk<const T>, Blk<T>, Work &, hipStream_t, const double *);             \
+  template void normalize_and_project<T>(int64_t, Blk<const T>, Blk<T>, Work &, hipStream_t);                   \
   template void gn_step<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, Blk<T>, Blk<T>, double, double, double,    \
                            const FilterPoly &, int, Work &, hipStream_t);                                        \
   template double rcond_gram<T>(int64_t, Blk<const T>, Work &, hipStream_t);                                     \
