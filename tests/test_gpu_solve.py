@@ -157,6 +157,33 @@ def test_powerlaw_largest():
     check_pairs(A, ev, X, 1e-10)
 
 
+def test_powerlaw_largest_mixed():
+    """The power-law family (FP32 filter stage, FP64 closing iterations)."""
+    A = W.powerlaw_random(3000, seed=3, cap=200)
+    k, w = 16, 20
+    status, ev, X, res, st = solve(A, k, "LA", 1e-10, w=w, precision=arr.MIXED)
+    assert status == arr.ARR_OK, st
+    lam = np.sort(np.linalg.eigvalsh(A.to_scipy().toarray()))[::-1][:k]
+    assert np.abs(ev - lam).max() <= 1e-10 * max(1, np.abs(lam).max())
+    check_pairs(A, ev, X, 1e-10)
+
+
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_sbm_normalized_laplacian_smallest(precision):
+    """The SBM normalized-Laplacian family: with 16 blocks the 16 smallest
+    eigenvalues (0 and a cluster near 0.5) lie below the bulk; k = 24 takes
+    them and the start of the bulk. Spectrum in [0, 2] (checked); eigenvalues
+    against a dense eigensolve."""
+    A = W.sbm_normalized_laplacian(3008, 16, seed=5)
+    lam = np.linalg.eigvalsh(A.to_scipy().toarray())
+    assert lam[0] > -1e-12 and lam[-1] < 2 + 1e-12
+    k, w = 24, 36
+    status, ev, X, res, st = solve(A, k, "SA", 1e-10, w=w, precision=precision)
+    assert status == arr.ARR_OK, st
+    assert np.abs(ev - lam[:k]).max() <= 1e-10 * max(1, np.abs(lam[:k]).max())
+    check_pairs(A, ev, X, 1e-10)
+
+
 def test_deterministic_repeat():
     A, k, which, w, tol = W.workload("lap2d_40")
     a = solve(A, k, which, tol, w=w)
