@@ -182,10 +182,15 @@ def measured_traffic(kernel):
 
 
 def spmm_kernel_name(dtype, vec, cols_per_lane, flags):
-    """The SpMM kernel instance the solver timed: k_filter_spmm<T, VEC, NT,
-    overflow rows, Z operand, column sums>, as rocprofv3 names it."""
+    """The SpMM kernel instance the solver timed, as rocprofv3 names it:
+    k_filter_spmm<T, VEC, NT, overflow rows, Z operand, column sums>, or for
+    the paired row form (flag 8) k_filter_spmm_paired<T, VEC, NT, far slots,
+    Z operand, column sums>."""
     b = lambda bit: "true" if flags & bit else "false"
-    return f"k_filter_spmm<{dtype}, {vec}, {max(1, cols_per_lane // vec)}, {b(2)}, {b(1)}, {b(4)}>"
+    nt = max(1, cols_per_lane // vec)
+    if flags & 8:
+        return f"k_filter_spmm_paired<{dtype}, {vec}, {nt}, {1 if flags & 16 else 3}, {b(1)}, {b(4)}>"
+    return f"k_filter_spmm<{dtype}, {vec}, {nt}, {b(2)}, {b(1)}, {b(4)}>"
 
 
 def solve_run(A, k, w, tol, precision, args, label, which="SA"):

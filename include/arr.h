@@ -82,18 +82,36 @@ typedef struct {
   const double *val;     /* host, [nnz]                                  */
 } arr_csr_t;
 
+/* Row form of the matrix in the SpMM kernels. Plain: per row the three
+ * central entries, up to four other ("far") entries, and an overflow CSR for
+ * the rest. Paired: for matrices with a frequent column offset P (a grid
+ * operator's neighbour one grid line away), rows i and i + P of each block of
+ * 2P rows are processed together and each row's entry in the other's column
+ * is served from registers instead of a gather; chosen only when every row
+ * then has at most three far entries besides that one. ARR_ROW_AUTO takes the
+ * paired form where it applies. Both forms compute the same product. */
+typedef enum { ARR_ROW_AUTO = 0, ARR_ROW_PLAIN = 1 } arr_row_form_t;
+
+/* The row form the SpMM kernels use for a host CSR (same checks as
+ * arr_create; host only, no device needed): *pair = the pairing offset P (0
+ * for the plain form), *far_slots = far entries gathered per row (4 plain; 1
+ * or 3 paired), *overflow = entries in the plain form's overflow CSR. Any
+ * output pointer may be NULL, and so may csr->val (the form depends on the
+ * pattern only). ARR_EINVAL on a malformed CSR or an unknown form. */
+int arr_row_form(const arr_csr_t *csr, int32_t form, int64_t *pair, int32_t *far_slots, int64_t *overflow);
+
 /* Device CSR description used by the step-level entry points. val is a
  * device array of FP64 (dtype 0) or FP32 (dtype 1) values; column indices
  * strictly increase within each row. Each step call copies the matrix to the
  * host, checks it (ARR_EINVAL on a malformed CSR) and builds, in temporary
- * device memory, the split form its kernels read: the three central
- * diagonals as dense arrays plus a CSR of the other entries. */
+ * device memory, the row form its kernels read (arr_row_form_t). */
 typedef struct {
   int64_t n, nnz;
   const int64_t *rowptr; /* device [n+1] */
   const int32_t *colind; /* device [nnz] */
   const void *val;       /* device [nnz] */
   int32_t dtype;         /* 0 = FP64, 1 = FP32 */
+  int32_t row_form;      /* arr_row_form_t, 0 = ARR_ROW_AUTO */
 } arr_dev_csr_t;
 
 /* Parameters of Algorithm 8; arr_options_default fills the defaults of
@@ -117,6 +135,7 @@ typedef struct {
   int32_t keep_vectors;  /* served requests: keep eigenvectors on the host (default 1)    */
   int32_t inner_solver;  /* arr_inner_t, default ARR_INNER_MPM                              */
   int32_t poly_form;     /* arr_poly_form_t, default ARR_POLY_PRODUCT                       */
+  int32_t row_form;      /* arr_row_form_t, default ARR_ROW_AUTO                            */
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -164,7 +183,10 @@ typedef struct {
   double fp32_maxres;    /* ARR_MIXED: maxres of the last FP32-stage iteration (eq. resi) */
   /* flags of the SpMM variants above: 1 = recurrence block Z present,
    * 2 = matrix has rows with more than four entries off the central band,
-   * 4 = column sums of squares computed */
+   * 4 = column sums of squares computed, 8 = paired row form (rows i and
+   * i + P of a block of 2P rows processed together, P a frequent column
+   * offset of the matrix), 16 = paired form with one far entry per row
+   * (otherwise three) */
   int32_t spmm_flags, spmm32_flags;
 } arr_stats_t;
 

@@ -32,6 +32,8 @@ INNER_GN = 1
 POLY_PRODUCT = 0
 POLY_HORNER = 1
 POLY_CHEBYSHEV = 2
+ROW_AUTO = 0
+ROW_PLAIN = 1
 
 
 class ArrError(RuntimeError):
@@ -47,7 +49,8 @@ class arr_csr_t(ctypes.Structure):
 
 class arr_dev_csr_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
-                ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+                ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("row_form", ctypes.c_int32)]
 
 
 class arr_options_t(ctypes.Structure):
@@ -59,7 +62,8 @@ class arr_options_t(ctypes.Structure):
                 ("mixed_switch", ctypes.c_double), ("verbose", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("keep_vectors", ctypes.c_int32),
                 ("inner_solver", ctypes.c_int32),
-                ("poly_form", ctypes.c_int32)]
+                ("poly_form", ctypes.c_int32),
+                ("row_form", ctypes.c_int32)]
 
 
 class arr_server_opts_t(ctypes.Structure):
@@ -94,7 +98,7 @@ EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initia
            "arr_filter_coefficients", "arr_gram", "arr_block_update",
            "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
            "arr_server_create", "arr_footprint", "arr_submit", "arr_poll", "arr_wait", "arr_request_times",
-           "arr_server_destroy"]
+           "arr_server_destroy", "arr_row_form"]
 
 _lib = None
 
@@ -130,6 +134,7 @@ def lib() -> ctypes.CDLL:
     L.arr_filter.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, i32, i32, vp]
     L.arr_filter_roots.argtypes = [i32, vp, vp]
     L.arr_filter_coefficients.argtypes = [i32, vp]
+    L.arr_row_form.argtypes = [P(arr_csr_t), i32, vp, vp, vp]
     L.arr_gram.argtypes = [i32, i64, vp, i64, i32, vp, i64, i32, vp, vp]
     L.arr_block_update.argtypes = [i32, i64, i32, i32, f64, vp, i64, vp, i64, f64, vp, i64, vp]
     L.arr_rcond_gram.argtypes = [i32, i64, i32, vp, i64, vp, vp]
@@ -205,6 +210,17 @@ def arr_create(csr, n: int, k: int, which: int, tol: float, opts: arr_options_t 
     _check(code)
     del keep
     return Handle(h.value)
+
+
+def arr_row_form(csr, form: int = ROW_AUTO):
+    """Row form the SpMM kernels use for a host CSR: (pair offset P, 0 for
+    the plain form; far entries gathered per row; overflow entries)."""
+    c, keep = _host_csr(csr)
+    pair, far, ovf = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().arr_row_form(ctypes.byref(c), int(form), ctypes.addressof(pair), ctypes.addressof(far),
+                              ctypes.addressof(ovf)))
+    del keep
+    return pair.value, far.value, ovf.value
 
 
 def arr_set_initial_block(h: Handle, X0: np.ndarray) -> None:
@@ -316,7 +332,7 @@ def _stream():
 class DeviceCSR:
     """A CSR matrix resident on the device (torch tensors) plus its descriptor."""
 
-    def __init__(self, csr, dtype=None, device="cuda"):
+    def __init__(self, csr, dtype=None, device="cuda", row_form=ROW_AUTO):
         import torch
         dtype = dtype or torch.float64
         self.n = int(csr.n)
@@ -324,7 +340,8 @@ class DeviceCSR:
         self.colind = torch.as_tensor(np.asarray(csr.colind, dtype=np.int32)).to(device)
         self.val = torch.as_tensor(np.asarray(csr.val, dtype=np.float64)).to(device=device, dtype=dtype)
         self.desc = arr_dev_csr_t(self.n, int(self.colind.numel()), self.rowptr.data_ptr(),
-                                  self.colind.data_ptr(), self.val.data_ptr(), _dtype_code(self.val))
+                                  self.colind.data_ptr(), self.val.data_ptr(), _dtype_code(self.val),
+                                  int(row_form))
 
 
 def arr_filter_step(A: DeviceCSR, Yin, Z, Yout, alpha: float, beta: float, gamma: float, colsumsq=None):

@@ -51,6 +51,7 @@ template <typename T>
 std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
   ARR_REQUIRE(A && A->rowptr && A->n > 0 && A->nnz >= 0, "device CSR is NULL or empty");
   ARR_REQUIRE(A->nnz == 0 || (A->colind && A->val), "device CSR arrays are NULL");
+  ARR_REQUIRE(A->row_form == ARR_ROW_AUTO || A->row_form == ARR_ROW_PLAIN, "unknown row form");
   const int64_t n = A->n, nnz = A->nnz;
   std::vector<int64_t> rp(n + 1);
   std::vector<int32_t> ci(nnz);
@@ -70,7 +71,7 @@ std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
   }
   std::vector<double> v(vt.begin(), vt.end());
   arr::RowSplit sp;
-  arr::split_rows(n, rp.data(), ci.data(), v.data(), sp);
+  arr::split_rows(n, rp.data(), ci.data(), v.data(), sp, A->row_form == ARR_ROW_AUTO);
   std::vector<T> cv(sp.coef.begin(), sp.coef.end()), ov(sp.oval.begin(), sp.oval.end());
   auto d = std::make_unique<SplitDev<T>>();
   const int64_t no = (int64_t)sp.ocol.size();
@@ -92,7 +93,9 @@ std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
                         (const int32_t *)d->fcol.p,
                         no ? (const int64_t *)d->orp.p : nullptr,
                         no ? (const int32_t *)d->ocol.p : nullptr,
-                        no ? (const T *)d->oval.p : nullptr};
+                        no ? (const T *)d->oval.p : nullptr,
+                        sp.pair,
+                        sp.kf};
   return d;
 }
 
@@ -123,6 +126,37 @@ void arr_options_default(arr_options_t *o) {
   o->verbose = 0;
   o->timing = 0;
   o->keep_vectors = 1;
+}
+
+int arr_row_form(const arr_csr_t *csr, int32_t form, int64_t *pair, int32_t *far_slots, int64_t *overflow) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(csr && csr->n > 0 && csr->nnz >= 0 && csr->rowptr, "csr is NULL or empty");
+    ARR_REQUIRE(csr->nnz == 0 || csr->colind, "csr arrays are NULL");
+    ARR_REQUIRE(form == ARR_ROW_AUTO || form == ARR_ROW_PLAIN, "unknown row form");
+    const int64_t n = csr->n, *rp = csr->rowptr;
+    ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
+    for (int64_t i = 0; i < n; ++i) {
+      ARR_REQUIRE(rp[i] <= rp[i + 1], "rowptr must be non-decreasing");
+      for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+        ARR_REQUIRE(csr->colind[q] >= 0 && csr->colind[q] < n, "column index out of range");
+        ARR_REQUIRE(q == rp[i] || csr->colind[q - 1] < csr->colind[q],
+                    "column indices must be strictly increasing within a row");
+      }
+    }
+    // the form depends on the pattern only: unit values stand in when val is NULL
+    std::vector<double> ones;
+    const double *val = csr->val;
+    if (!val) {
+      ones.assign((size_t)csr->nnz, 1.0);
+      val = ones.data();
+    }
+    arr::RowSplit sp;
+    arr::split_rows(n, rp, csr->colind, val, sp, form == ARR_ROW_AUTO);
+    if (pair) *pair = sp.pair;
+    if (far_slots) *far_slots = sp.kf;
+    if (overflow) *overflow = (int64_t)sp.ocol.size();
+    return ARR_OK;
+  });
 }
 
 int arr_create_ex(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,

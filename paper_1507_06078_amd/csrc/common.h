@@ -33,12 +33,23 @@ struct Error : std::runtime_error {
   } while (0)
 
 // Device matrix in the row form the SpMM kernels read. Per row i: coef[8i ..
-// 8i+7] = {A[i][i-1], A[i][i], A[i][i+1], f0, f1, f2, f3, 0} (zero where an
+// 8i+7] = {A[i][i-1], A[i][i], A[i][i+1], f0, f1, f2, f3, a_p} (zero where an
 // entry is absent) and fcol[4i .. 4i+3] the columns of the first four other
 // ("far") entries f0..f3 (unused slots: column i, value 0). Far entries past
 // the fourth are an overflow CSR (orp int64 [n+1], ocol int32, oval in T);
 // orp is null when no row has more than four. nnz counts every entry of the
 // matrix.
+//
+// Paired form (pair = P > 0): rows are grouped in blocks of 2P; row i is an
+// "upper" row when i mod 2P < P, with partner i + P, else a "lower" row with
+// partner i - P. a_p = A[i][partner(i)] (0 if absent or out of range) and the
+// partner entry is not among the far entries. A wave then processes a run of
+// upper rows together with the lower run P rows below it, so each row's
+// partner term comes from the other run's register window instead of a
+// gather. Only matrices whose rows then fit the far slots without overflow
+// use it; kf (1 or 3) is the number of far slots the kernel gathers (slots
+// past kf are unused in every row). In the plain form pair = 0, a_p = 0 and
+// kf = 4.
 template <typename T>
 struct DevCSR {
   int64_t n = 0, nnz = 0;
@@ -47,6 +58,8 @@ struct DevCSR {
   const int64_t *orp = nullptr;
   const int32_t *ocol = nullptr;
   const T *oval = nullptr;
+  int64_t pair = 0;
+  int kf = 4;
 };
 
 // Host form of the same split (FP64 values); orp is left empty when no row
@@ -57,10 +70,21 @@ struct RowSplit {
   std::vector<int64_t> orp;
   std::vector<int32_t> ocol;
   std::vector<double> oval;
+  int64_t pair = 0;
+  int kf = 4;
 };
 
-// Host split of a CSR with strictly increasing columns per row.
-void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out);
+// Rows per run of the paired form (a wave does two runs at once).
+constexpr int64_t kPairRun = 20;
+
+// Host split of a CSR with strictly increasing columns per row. Chooses the
+// paired form when the matrix has a frequent far offset P >= kPairRun (entries
+// A[i][i+P] in at least half of the rows), the runs of kPairRun rows cover a
+// half block of P rows with at most P/8 rows computed twice, and every row
+// then has at most three far entries besides its partner; otherwise the
+// plain form. allow_pair = false forces the plain form.
+void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out,
+                bool allow_pair = true);
 
 // A row-major view of columns [0, w) of a device block with leading
 // dimension ld.
@@ -157,13 +181,14 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
 // Optional HIP-event timing of kernel launches, per launch class, with the
 // algorithmic work of each launch (bytes for the SpMM, flops for the GEMMs).
 // Installed per thread by the solver. SpMM classes: columns per lane (0..4
-// for 1..16) + 5 for 16-byte loads + 10 for FP64 data. GEMM classes: see
-// GemmClass.
+// for 1..16) + 5 for 16-byte loads + 10 for FP64 data + 20 * flags (1 Z term,
+// 2 overflow rows, 4 column sums, 8 paired form, 16 paired with one far slot).
+// GEMM classes: see GemmClass.
 struct SpmmTimer {
   struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
-  static constexpr int kClasses = 160;
+  static constexpr int kClasses = 640;
   int64_t launches[kClasses] = {};
   double ms[kClasses] = {}, bytes[kClasses] = {};
   hipEvent_t get();

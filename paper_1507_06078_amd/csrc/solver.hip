@@ -95,6 +95,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
   ARR_REQUIRE(o.inner_solver == ARR_INNER_MPM || o.inner_solver == ARR_INNER_GN, "unknown inner solver");
   ARR_REQUIRE(o.poly_form == ARR_POLY_PRODUCT || o.poly_form == ARR_POLY_HORNER || o.poly_form == ARR_POLY_CHEBYSHEV,
               "unknown polynomial form");
+  ARR_REQUIRE(o.row_form == ARR_ROW_AUTO || o.row_form == ARR_ROW_PLAIN, "unknown row form");
   // validate CSR on the host
   const int64_t *rp = csr->rowptr;
   ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
@@ -117,7 +118,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
     }
   }
   // working operator (A, or -A for the smallest end) in the split form
-  split_rows(n, rp, csr->colind, csr->val, h_split_);
+  split_rows(n, rp, csr->colind, csr->val, h_split_, o.row_form == ARR_ROW_AUTO);
   nnz_ = csr->nnz;
   if (which == ARR_SMALLEST_ALGEBRAIC) {
     for (double &x : h_split_.coef) x = -x;
@@ -190,10 +191,10 @@ void Solver::ensure_device() {
   const int64_t *orp = no ? orp_.as<int64_t>() : nullptr;
   const int32_t *ocol = no ? ocol_.as<int32_t>() : nullptr;
   A64_ = DevCSR<double>{n, nnz_, coef64_.as<double>(), fcol_.as<int32_t>(), orp, ocol,
-                        no ? oval64_.as<double>() : nullptr};
+                        no ? oval64_.as<double>() : nullptr, h_split_.pair, h_split_.kf};
   if (mixed)
     A32_ = DevCSR<float>{n, nnz_, coef32_.as<float>(), fcol_.as<int32_t>(), orp, ocol,
-                         no ? oval32_.as<float>() : nullptr};
+                         no ? oval32_.as<float>() : nullptr, h_split_.pair, h_split_.kf};
   B64_.ldz = ldz_;
   B64_.ldq = ldq_;
   B32_.ldz = ldz_;
@@ -664,11 +665,11 @@ int Solver::solve() {
     stats.spmm_launches = timer.launches[best];
     stats.spmm_ms = timer.ms[best];
     stats.spmm_bytes = timer.bytes[best];
-    // class = slots + 5 vec4 + 10 fp64 + 20 Z + 40 overflow + 80 sums
+    // class = slots + 5 vec4 + 10 fp64 + 20 flags
     stats.spmm_cols_per_lane = 1 << (best % 5);
     stats.spmm_vec = (best % 10) >= 5 ? 4 : 1;
     stats.spmm_fp64 = (best % 20) >= 10 ? 1 : 0;
-    stats.spmm_flags = (best / 20) & 7;
+    stats.spmm_flags = best / 20;
     int best32 = 0;
     for (int c = 1; c < SpmmTimer::kClasses; ++c)
       if ((c % 20) < 10 && timer.ms[c] > timer.ms[best32]) best32 = c;
@@ -677,7 +678,7 @@ int Solver::solve() {
     stats.spmm32_bytes = timer.bytes[best32];
     stats.spmm32_cols_per_lane = 1 << (best32 % 5);
     stats.spmm32_vec = (best32 % 10) >= 5 ? 4 : 1;
-    stats.spmm32_flags = (best32 / 20) & 7;
+    stats.spmm32_flags = best32 / 20;
     gtimer.flush();
     auto sum = [&](std::initializer_list<int> cls, int64_t &l, double &ms, double &fl) {
       l = 0, ms = 0, fl = 0;

@@ -31,9 +31,17 @@
 //    multi-power normalization);
 //  * XCD-aware order: workgroup b runs on XCD b % 8; runs are dealt to the
 //    XCDs in chunks of kRunChunk so that all XCDs sweep the matrix together
-//    (small working set in the shared Infinity Cache).
+//    (small working set in the shared Infinity Cache);
+//  * paired form, for matrices with a frequent far offset P (grid operators:
+//    the neighbour one grid line away): a wave processes rows i and i + P
+//    together, and each row's entry in the other row's column is served from
+//    the other run's register window. The kernel is limited by the rows
+//    moved through each CU's vector memory path (six per output row in the
+//    plain form for a 3D 7-point operator: one window row, four gathers, one
+//    store), and the pairing drops one of the six.
 #include <algorithm>
 #include <exception>
+#include <map>
 
 #include "common.h"
 
@@ -327,11 +335,221 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
   }
 }
 
+// Paired form: a unit is an upper run [a0, a0 + kPairRun) of a block of 2P
+// rows together with the lower run [a0 + P, a0 + P + kPairRun); each row's
+// partner is the other run's centre row, already in registers. The runs of a
+// half block start at multiples of kPairRun, except the last, which starts
+// at P - kPairRun to stay inside the half: its first `skip` rows, done by the
+// previous run, are computed again but neither stored (their buffer resource
+// holds no records) nor summed. Rows past the last whole block take the
+// guarded row-at-a-time path.
+template <typename T, int VEC, int NT, int KF, bool HASZ, bool SUMS>
+__global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
+    int64_t n, int64_t P, const T *__restrict__ coef, const int32_t *__restrict__ fcol, int w,
+    const T *__restrict__ Yin, int64_t ldy, const T *Z, int64_t ldz, T *Yout, int64_t ldo, T alpha, T beta,
+    T gamma, double *__restrict__ partial, int wtot, int c0) {
+  typedef typename VecT<T, VEC>::type vec;
+  typedef BufIO<T, VEC> IO;
+  constexpr int R = (int)kPairRun;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = blockIdx.x % kXcd;
+  const int64_t wave_in_xcd = (int64_t)(blockIdx.x / kXcd) * kWaves + wv;
+  const int64_t waves_per_xcd = (int64_t)(gridDim.x / kXcd) * kWaves;
+  const int64_t half_runs = (P + R - 1) / R;
+  const int64_t blocks = n / (2 * P);
+  const int64_t paired_units = blocks * half_runs;
+  const int64_t tail0 = blocks * 2 * P;
+  const int64_t units = paired_units + (n - tail0 + R - 1) / R;
+  const int rowbytes = w * (int)sizeof(T);
+  int off[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) off[t] = (VEC * lane + 64 * VEC * t) * (int)sizeof(T);
+  auto ldrow = [&](const T *base, int64_t ld, int64_t j, vec *dst) {
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(base + j * ld, rowbytes);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) dst[t] = IO::ld(r, off[t]);
+  };
+  auto gather = [&](int64_t j, vec *dst) { ldrow(Yin, ldy, j, dst); };
+
+  double ss[NT][VEC];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) ss[t][v] = 0.0;
+
+  auto finish_row = [&](int64_t i, bool own, const vec *acc, const vec *yi, const vec *zi) {
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(Yout + i * ldo, own ? rowbytes : 0);
+    const double m = own ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      vec o = alpha * acc[t];
+      if (beta != T(0)) o += beta * yi[t];
+      if constexpr (HASZ) o += gamma * zi[t];
+      IO::st(o, r, off[t]);
+      if constexpr (SUMS) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double ov = lane_elem<VEC>(o, v);
+          ss[t][v] = fma(m * ov, ov, ss[t][v]);
+        }
+      }
+    }
+  };
+
+  for (int64_t k = wave_in_xcd;; k += waves_per_xcd) {
+    const int64_t u = xcd_run(k, x);
+    if (u >= units) break;
+    if (u < paired_units) {
+      const int64_t blk = u / half_runs, r = u % half_runs;
+      const int64_t st = min(r * R, P - R);
+      const int skip = (int)(r * R - st);
+      const int64_t a0 = blk * 2 * P + st, b0 = a0 + P;
+      // Row a0 - 1 is missing only for a0 = 0 and row b0 + R only for
+      // b0 + R = n; their coefficients are zero, so a row of the matrix
+      // stands in for them
+      vec wmA[NT], w0A[NT], wpA[NT], wmB[NT], w0B[NT], wpB[NT], gA[KF][NT], gB[KF][NT], zA[NT], zB[NT];
+      gather(a0 > 0 ? a0 - 1 : 0, wmA);
+      gather(a0, w0A);
+      gather(a0 + 1, wpA);
+      gather(b0 - 1, wmB);
+      gather(b0, w0B);
+      gather(b0 + 1, wpB);
+      RowCols cA = *(const RowCols *)(fcol + 4 * a0), cB = *(const RowCols *)(fcol + 4 * b0);
+      RowCoef<T> kA = *(const RowCoef<T> *)(coef + 8 * a0), kB = *(const RowCoef<T> *)(coef + 8 * b0);
+      RowCols cA1 = *(const RowCols *)(fcol + 4 * (a0 + 1)), cB1 = *(const RowCols *)(fcol + 4 * (b0 + 1));
+#pragma unroll
+      for (int e = 0; e < KF; ++e) {
+        gather(cA.v[e], gA[e]);
+        gather(cB.v[e], gB[e]);
+      }
+      if constexpr (HASZ) {
+        ldrow(Z, ldz, a0, zA);
+        ldrow(Z, ldz, b0, zB);
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int64_t i = a0 + q, j = b0 + q;
+        vec nxA[NT], nxB[NT], gnA[KF][NT], gnB[KF][NT], znA[NT], znB[NT];
+        RowCols cA2 = cA1, cB2 = cB1;
+        RowCoef<T> kA1 = kA, kB1 = kB;
+        if (q < R - 1) {
+          gather(i + 2, nxA);
+          gather(j + 2 < n ? j + 2 : n - 1, nxB);
+#pragma unroll
+          for (int e = 0; e < KF; ++e) {
+            gather(cA1.v[e], gnA[e]);
+            gather(cB1.v[e], gnB[e]);
+          }
+          if constexpr (HASZ) {
+            ldrow(Z, ldz, i + 1, znA);
+            ldrow(Z, ldz, j + 1, znB);
+          }
+          kA1 = *(const RowCoef<T> *)(coef + 8 * (i + 1));
+          kB1 = *(const RowCoef<T> *)(coef + 8 * (j + 1));
+        }
+        if (q < R - 2) {
+          cA2 = *(const RowCols *)(fcol + 4 * (i + 2));
+          cB2 = *(const RowCols *)(fcol + 4 * (j + 2));
+        }
+        vec accA[NT], accB[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          accA[t] = kA.v[0] * wmA[t] + kA.v[1] * w0A[t] + kA.v[2] * wpA[t] + kA.v[7] * w0B[t];
+          accB[t] = kB.v[0] * wmB[t] + kB.v[1] * w0B[t] + kB.v[2] * wpB[t] + kB.v[7] * w0A[t];
+#pragma unroll
+          for (int e = 0; e < KF; ++e) {
+            accA[t] += kA.v[3 + e] * gA[e][t];
+            accB[t] += kB.v[3 + e] * gB[e][t];
+          }
+        }
+        finish_row(i, q >= skip, accA, w0A, zA);
+        finish_row(j, q >= skip, accB, w0B, zB);
+        __builtin_amdgcn_sched_barrier(0);
+        if (q < R - 1) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            wmA[t] = w0A[t];
+            w0A[t] = wpA[t];
+            wpA[t] = nxA[t];
+            wmB[t] = w0B[t];
+            w0B[t] = wpB[t];
+            wpB[t] = nxB[t];
+            if constexpr (HASZ) {
+              zA[t] = znA[t];
+              zB[t] = znB[t];
+            }
+#pragma unroll
+            for (int e = 0; e < KF; ++e) {
+              gA[e][t] = gnA[e][t];
+              gB[e][t] = gnB[e][t];
+            }
+          }
+          kA = kA1;
+          kB = kB1;
+          cA1 = cA2;
+          cB1 = cB2;
+        }
+      }
+    } else {
+      // rows past the last whole block: guarded, one row at a time
+      const int64_t i0 = tail0 + (u - paired_units) * R, iend = min(n, i0 + R);
+      for (int64_t i = i0; i < iend; ++i) {
+        const RowCoef<T> kk = *(const RowCoef<T> *)(coef + 8 * i);
+        const RowCols ci = *(const RowCols *)(fcol + 4 * i);
+        const int64_t pi = (i % (2 * P)) < P ? i + P : i - P;
+        vec acc[NT], yi[NT], v[NT], zi[NT];
+        gather(i, yi);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = kk.v[1] * yi[t];
+        if (i > 0) {
+          gather(i - 1, v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] += kk.v[0] * v[t];
+        }
+        if (i + 1 < n) {
+          gather(i + 1, v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] += kk.v[2] * v[t];
+        }
+        if (pi < n) {
+          gather(pi, v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] += kk.v[7] * v[t];
+        }
+#pragma unroll
+        for (int e = 0; e < KF; ++e) {
+          gather(ci.v[e], v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] += kk.v[3 + e] * v[t];
+        }
+        if constexpr (HASZ) ldrow(Z, ldz, i, zi);
+        finish_row(i, true, acc, yi, zi);
+      }
+    }
+  }
+
+  if constexpr (SUMS) {
+    __shared__ double red[kWaves][64 * VEC * NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) red[wv][VEC * lane + 64 * VEC * t + v] = ss[t][v];
+    __syncthreads();
+    for (int c = threadIdx.x; c < w; c += kThreads) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) s += red[q][c];
+      partial[(int64_t)blockIdx.x * wtot + c0 + c] = s;
+    }
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_spmv(int64_t n, const T *__restrict__ coef, const int32_t *__restrict__ fcol,
-                                              const int64_t *__restrict__ orp, const int32_t *__restrict__ ocol,
-                                              const T *__restrict__ oval, const T *__restrict__ x,
-                                              T *__restrict__ y) {
+__global__ __launch_bounds__(256) void k_spmv(int64_t n, int64_t P, const T *__restrict__ coef,
+                                              const int32_t *__restrict__ fcol, const int64_t *__restrict__ orp,
+                                              const int32_t *__restrict__ ocol, const T *__restrict__ oval,
+                                              const T *__restrict__ x, T *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const T *k = coef + 8 * i;
@@ -339,6 +557,10 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const T *__restrict__ c
   if (i > 0) s = fma(k[0], x[i - 1], s);
   if (i + 1 < n) s = fma(k[2], x[i + 1], s);
   for (int e = 0; e < 4; ++e) s = fma(k[3 + e], x[fcol[4 * i + e]], s);
+  if (P) {
+    const int64_t pi = (i % (2 * P)) < P ? i + P : i - P;
+    if (pi < n) s = fma(k[7], x[pi], s);
+  }
   if (orp)
     for (int64_t p = orp[i]; p < orp[i + 1]; ++p) s = fma(oval[p], x[ocol[p]], s);
   y[i] = s;
@@ -373,6 +595,47 @@ void launch_nt(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout
     ARR_SPMM_CASE(7, true, true, true)
   }
 #undef ARR_SPMM_CASE
+}
+
+template <typename T, int VEC, int NT, int KF, bool HASZ, bool SUMS>
+void launch_paired_variant(const DevCSR<T> &A, Blk<const T> Yin, const T *zp, int64_t ldz, Blk<T> Yout, int w, int c0,
+                           T alpha, T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+  hipLaunchKernelGGL((k_filter_spmm_paired<T, VEC, NT, KF, HASZ, SUMS>), dim3(groups), dim3(kThreads), 0, s, A.n,
+                     A.pair, A.coef, A.fcol, w, Yin.p + c0, Yin.ld, zp, ldz, Yout.p + c0, Yout.ld, alpha, beta, gamma,
+                     partial, wtot, c0);
+}
+
+template <typename T, int VEC, int NT>
+void launch_paired_nt(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w, int c0, T alpha,
+                      T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+  const T *zp = Z.p ? Z.p + c0 : nullptr;
+  const int sel = (A.kf == 1 ? 4 : 0) + (zp ? 2 : 0) + (partial ? 1 : 0);
+#define ARR_SPMM_CASE(k, KF, H, S)                                                                              \
+  case k:                                                                                                      \
+    launch_paired_variant<T, VEC, NT, KF, H, S>(A, Yin, zp, Z.ld, Yout, w, c0, alpha, beta, gamma, partial, wtot, \
+                                                groups, s);                                                    \
+    break;
+  switch (sel) {
+    ARR_SPMM_CASE(0, 3, false, false)
+    ARR_SPMM_CASE(1, 3, false, true)
+    ARR_SPMM_CASE(2, 3, true, false)
+    ARR_SPMM_CASE(3, 3, true, true)
+    ARR_SPMM_CASE(4, 1, false, false)
+    ARR_SPMM_CASE(5, 1, false, true)
+    ARR_SPMM_CASE(6, 1, true, false)
+    ARR_SPMM_CASE(7, 1, true, true)
+  }
+#undef ARR_SPMM_CASE
+}
+
+// Either form's kernel for one column chunk.
+template <typename T, int VEC, int NT>
+void launch_form(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w, int c0, T alpha,
+                 T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+  if (A.pair)
+    launch_paired_nt<T, VEC, NT>(A, Yin, Z, Yout, w, c0, alpha, beta, gamma, partial, wtot, groups, s);
+  else
+    launch_nt<T, VEC, NT>(A, Yin, Z, Yout, w, c0, alpha, beta, gamma, partial, wtot, groups, s);
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -455,33 +718,95 @@ int spmm_groups(int64_t n) {
   return (int)g;
 }
 
-void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out) {
-  out.coef.assign(8 * n, 0.0);
-  out.fcol.assign(4 * n, 0);
-  out.orp.assign(n + 1, 0);
-  out.ocol.clear();
-  out.oval.clear();
-  for (int64_t i = 0; i < n; ++i) {
-    int slot = 0;
-    for (int e = 0; e < 4; ++e) out.fcol[4 * i + e] = (int32_t)i;  // padding: column i, value 0
-    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-      const int64_t j = col[q];
-      if (j == i - 1)
-        out.coef[8 * i] = val[q];
-      else if (j == i)
-        out.coef[8 * i + 1] = val[q];
-      else if (j == i + 1)
-        out.coef[8 * i + 2] = val[q];
-      else if (slot < 4) {
-        out.fcol[4 * i + slot] = (int32_t)j;
-        out.coef[8 * i + 3 + slot] = val[q];
-        ++slot;
-      } else {
-        out.ocol.push_back((int32_t)j);
-        out.oval.push_back(val[q]);
-      }
+namespace {
+
+bool has_entry(const int64_t *rowptr, const int32_t *col, int64_t i, int64_t j) {
+  const int32_t *b = col + rowptr[i], *e = col + rowptr[i + 1];
+  const int32_t *f = std::lower_bound(b, e, (int32_t)j);
+  return f != e && *f == j;
+}
+
+// Pairing offset of the paired form, or 0: candidates are the offsets
+// d = j - i >= kPairRun seen in at least a quarter of a sample of rows; each
+// is then counted exactly. Ties keep the smaller offset.
+int64_t choose_pair(int64_t n, const int64_t *rowptr, const int32_t *col) {
+  if (n < 2 * kPairRun) return 0;
+  std::map<int64_t, int64_t> seen;
+  const int64_t ns = std::min<int64_t>(n, 1024);
+  for (int64_t t = 0; t < ns; ++t) {
+    const int64_t i = t * n / ns;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+      if (col[q] - i >= kPairRun) ++seen[col[q] - i];
+  }
+  int64_t best = 0, best_count = 0;
+  for (const auto &dc : seen) {
+    const int64_t d = dc.first;
+    const int64_t half_runs = (d + kPairRun - 1) / kPairRun;
+    if (4 * dc.second < ns || 2 * d > n || 8 * (half_runs * kPairRun - d) > d) continue;
+    int64_t c = 0;
+    for (int64_t i = 0; i + d < n; ++i) c += has_entry(rowptr, col, i, i + d);
+    if (2 * c >= n && c > best_count) best = d, best_count = c;
+  }
+  return best;
+}
+
+// One row of either form; false if a paired row has more than three far
+// entries besides its partner.
+bool split_row(int64_t i, int64_t P, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out,
+               int &far_max) {
+  const int64_t partner = P == 0 ? -1 : (i % (2 * P)) < P ? i + P : i - P;
+  const int slots = P == 0 ? 4 : 3;
+  int slot = 0;
+  for (int e = 0; e < 4; ++e) out.fcol[4 * i + e] = (int32_t)i;  // padding: column i, value 0
+  for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+    const int64_t j = col[q];
+    if (j == i - 1)
+      out.coef[8 * i] = val[q];
+    else if (j == i)
+      out.coef[8 * i + 1] = val[q];
+    else if (j == i + 1)
+      out.coef[8 * i + 2] = val[q];
+    else if (j == partner)
+      out.coef[8 * i + 7] = val[q];
+    else if (slot < slots) {
+      out.fcol[4 * i + slot] = (int32_t)j;
+      out.coef[8 * i + 3 + slot] = val[q];
+      ++slot;
+    } else if (P == 0) {
+      out.ocol.push_back((int32_t)j);
+      out.oval.push_back(val[q]);
+    } else {
+      return false;
     }
-    out.orp[i + 1] = (int64_t)out.ocol.size();
+  }
+  far_max = std::max(far_max, slot);
+  return true;
+}
+
+}  // namespace
+
+void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out,
+                bool allow_pair) {
+  int64_t P = allow_pair ? choose_pair(n, rowptr, col) : 0;
+  for (;;) {
+    out.coef.assign(8 * n, 0.0);
+    out.fcol.assign(4 * n, 0);
+    out.orp.assign(n + 1, 0);
+    out.ocol.clear();
+    out.oval.clear();
+    int far_max = 0;
+    bool fits = true;
+    for (int64_t i = 0; i < n && fits; ++i) {
+      fits = split_row(i, P, rowptr, col, val, out, far_max);
+      out.orp[i + 1] = (int64_t)out.ocol.size();
+    }
+    if (!fits) {
+      P = 0;  // a row too long for the paired form: plain form
+      continue;
+    }
+    out.pair = P;
+    out.kf = P == 0 ? 4 : far_max <= 1 ? 1 : 3;
+    break;
   }
   if (out.ocol.empty()) out.orp.clear();
 }
@@ -494,6 +819,8 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   ARR_REQUIRE(Yin.p != Yout.p, "filter_spmm: Yout must not alias Yin");
   ARR_REQUIRE(A.n == 0 || (A.coef && A.fcol), "filter_spmm: matrix rows missing");
   ARR_REQUIRE(!A.orp || (A.ocol && A.oval), "filter_spmm: overflow entries missing");
+  ARR_REQUIRE(A.pair == 0 || (!A.orp && A.pair >= kPairRun && 2 * A.pair <= A.n && (A.kf == 1 || A.kf == 3)),
+              "filter_spmm: invalid paired form");
   const int groups = spmm_groups(A.n);
   if (A.n == 0 || w == 0) return groups;
   SpmmTimer *timer = spmm_timer();
@@ -508,8 +835,10 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
     const int wc = std::min(chunk, w - c0);
     const T al = (T)alpha, be = (T)beta, ga = (T)gamma;
     const int slots = vec4 ? 4 * ((wc + 255) / 256) : (wc + 63) / 64;  // columns per lane
+    const int flags = (Z.p ? 1 : 0) + (A.orp ? 2 : 0) + (partial ? 4 : 0) + (A.pair ? 8 : 0) +
+                      (A.pair && A.kf == 1 ? 16 : 0);
     const int cls = (slots <= 1 ? 0 : slots <= 2 ? 1 : slots <= 4 ? 2 : slots <= 8 ? 3 : 4) + (vec4 ? 5 : 0) +
-                    (sizeof(T) == 8 ? 10 : 0) + (Z.p ? 20 : 0) + (A.orp ? 40 : 0) + (partial ? 80 : 0);
+                    (sizeof(T) == 8 ? 10 : 0) + 20 * flags;
     SpmmTimer::Pending pend{};
     if (timer) {
       pend.a = timer->get();
@@ -524,17 +853,17 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
     if (vec4) {
       if constexpr (sizeof(T) == 4) {
         if (wc <= 256)
-          launch_nt<T, 4, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+          launch_form<T, 4, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
         else
-          launch_nt<T, 4, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+          launch_form<T, 4, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
       }
     } else if (wc <= 64) {
-      launch_nt<T, 1, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+      launch_form<T, 1, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
     } else if constexpr (sizeof(T) == 8) {
       if (wc <= 128)
-        launch_nt<T, 1, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+        launch_form<T, 1, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
       else
-        launch_nt<T, 1, 4>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+        launch_form<T, 1, 4>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
     }
     if (timer) {
       ARR_HIP(hipEventRecord(pend.b, s));
@@ -549,8 +878,8 @@ template <typename T>
 void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s) {
   if (A.n == 0) return;
   const int64_t blocks = (A.n + 255) / 256;
-  hipLaunchKernelGGL((k_spmv<T>), dim3((unsigned)blocks), dim3(256), 0, s, A.n, A.coef, A.fcol, A.orp, A.ocol,
-                     A.oval, x, y);
+  hipLaunchKernelGGL((k_spmv<T>), dim3((unsigned)blocks), dim3(256), 0, s, A.n, A.pair, A.coef, A.fcol, A.orp,
+                     A.ocol, A.oval, x, y);
   ARR_HIP(hipGetLastError());
 }
 

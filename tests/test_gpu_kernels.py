@@ -53,8 +53,41 @@ def lap2d_holes(m=41, seed=4):
     return W.from_scipy(S, "lap2d_holes")
 
 
+def band_p40(n=1070, seed=6):
+    """Diagonals 0, +-1, +-3, +-40: the paired row form with P = 40 and three
+    far entries a row; n = 13 * 80 + 30 leaves a tail of upper and lower
+    rows past the last whole block of 80."""
+    rng = np.random.default_rng(seed)
+    diags, offs = [rng.standard_normal(n) + 8.0], [0]
+    for k in (1, 3, 40):
+        v = rng.standard_normal(n - k)
+        diags += [v, v]
+        offs += [k, -k]
+    return W.from_scipy(sp.diags(diags, offs, shape=(n, n), format="csr"), "band_p40")
+
+
+def lap2d_holes60(m=60, seed=8):
+    """Paired form with one far entry a row (P = 60), 40 rows and columns
+    removed: empty rows and rows without their partner inside full runs."""
+    rng = np.random.default_rng(seed)
+    S = W.laplacian_2d(m).to_scipy()
+    keep = np.ones(m * m)
+    keep[rng.choice(m * m, 40, replace=False)] = 0.0
+    S = sp.csr_matrix(sp.diags(keep) @ S @ sp.diags(keep))
+    S.eliminate_zeros()
+    return W.from_scipy(S, "lap2d_holes60")
+
+
+# Row forms: lap3d_12V paired (P = 144; the last run of each half block
+# starts 16 rows early), lap3d_11V plain with four far entries a row,
+# lap3d_23V paired (P = 529, 11 rows recomputed, a tail of 529 rows),
+# band_p40 and lap2d_holes60 paired, the others plain.
 MATS = {
     "lap3d_12V": lambda: W.laplacian_3d(12, potential_seed=1),
+    "lap3d_11V": lambda: W.laplacian_3d(11, potential_seed=3),
+    "lap3d_23V": lambda: W.laplacian_3d(23, potential_seed=5),
+    "band_p40": band_p40,
+    "lap2d_holes60": lap2d_holes60,
     "lap2d_holes": lap2d_holes,
     "powerlaw_4000": lambda: W.powerlaw_random(4000, seed=7, cap=300),
     "empty_rows": with_empty_rows,
@@ -188,6 +221,53 @@ def test_filter_step_no_z(mat, w, dtype, sums):
     assert np.all(np.abs(got - ref) <= kmax * u * bound + 1e-30)
     if sums:
         np.testing.assert_allclose(ss.cpu().numpy(), (got ** 2).sum(axis=0), rtol=1e-12)
+
+
+PAIRED = {"lap3d_20": lambda: W.laplacian_3d(20, potential_seed=2), "lap2d_107": lambda: W.laplacian_2d(107),
+          "lap3d_23V": MATS["lap3d_23V"], "band_p40": band_p40}
+
+
+@pytest.mark.parametrize("mat", list(PAIRED))
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("w", [1, 65, 240, 520])
+@pytest.mark.parametrize("zs", [(False, False), (True, False), (False, True), (True, True)])
+def test_filter_step_row_forms(mat, dtype, w, zs):
+    """The paired and the plain row form against the definition, every
+    variant (Z operand, column sums, FP32 16-byte and FP64 column chunks):
+    one run per half block (lap3d_20), one far slot with recomputed rows and
+    an upper-row tail (lap2d_107), three far slots with a tail (lap3d_23V),
+    a tail holding lower rows too (band_p40)."""
+    A = PAIRED[mat]()
+    pair, _, _ = arr.arr_row_form(A)
+    assert pair > 0
+    has_z, sums = zs
+    tdt, u = (torch.float32, 6e-8) if dtype == "f32" else (torch.float64, 1.2e-16)
+    vals = A.val.astype(np.float32).astype(np.float64) if dtype == "f32" else A.val
+    Sx = sp.csr_matrix((vals, A.colind, A.rowptr), shape=(A.n, A.n))
+    rng = np.random.default_rng(w)
+    Yin = rng.standard_normal((A.n, w))
+    Z = rng.standard_normal((A.n, w))
+    if dtype == "f32":
+        Yin = Yin.astype(np.float32).astype(np.float64)
+        Z = Z.astype(np.float32).astype(np.float64)
+    al, be, ga = 0.75, -0.5, (1.5 if has_z else 0.0)
+    ref = al * (Sx @ Yin) + be * Yin + ga * Z
+    bound = abs(al) * (abs(Sx) @ np.abs(Yin)) + abs(be) * np.abs(Yin) + abs(ga) * np.abs(Z)
+    kmax = int(np.diff(A.rowptr).max()) + 4
+    outs = []
+    for form in (arr.ROW_AUTO, arr.ROW_PLAIN):
+        Ad = arr.DeviceCSR(A, dtype=tdt, row_form=form)
+        Yd, Zd = dev(Yin, tdt), dev(Z, tdt)
+        Od = torch.zeros_like(Yd)
+        ss = torch.zeros(w, dtype=torch.float64, device="cuda") if sums else None
+        arr.arr_filter_step(Ad, Yd, Zd if has_z else None, Od, al, be, ga, colsumsq=ss)
+        torch.cuda.synchronize()
+        got = Od.double().cpu().numpy()
+        assert np.all(np.abs(got - ref) <= kmax * u * bound + 1e-30), form
+        if sums:
+            np.testing.assert_allclose(ss.cpu().numpy(), (got ** 2).sum(axis=0), rtol=1e-12)
+        outs.append(got)
+    assert np.all(np.abs(outs[0] - outs[1]) <= 2 * kmax * u * bound + 1e-30)
 
 
 @pytest.mark.parametrize("d", [3, 8, 15])

@@ -147,6 +147,25 @@ def test_3d_laplacian_potential_vs_dense_and_weyl():
     check_pairs(A, ev, X, 1e-10)
 
 
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_row_forms_agree_in_solve(precision):
+    """The 3D 7-point operator runs in the paired row form (P = 20) unless
+    the plain form is asked for; both solves reach the closed-form spectrum
+    and the timed SpMM variant reports the form it ran."""
+    A = W.laplacian_3d(20)
+    k, w, tol = 24, 30, 1e-10
+    exact = W.laplacian_3d_eigenvalues(20)[:k]
+    assert arr.arr_row_form(A) == (20, 3, 0)
+    for form, paired in ((arr.ROW_AUTO, 8), (arr.ROW_PLAIN, 0)):
+        status, ev, X, res, st = solve(A, k, "SA", tol, w=w, precision=precision, row_form=form, timing=1)
+        assert status == arr.ARR_OK, st
+        assert np.all(np.abs(ev - exact) <= 1e-10 * np.maximum(1, np.abs(exact)))
+        check_pairs(A, ev, X, tol)
+        assert st["spmm_flags"] & 8 == paired
+        if precision == arr.MIXED:
+            assert st["spmm32_flags"] & 8 == paired
+
+
 def test_powerlaw_largest():
     A = W.powerlaw_random(3000, seed=3, cap=200)
     k, w = 16, 20
