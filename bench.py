@@ -208,6 +208,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     o.verbose = 1 if args.verbose else 0
     o.inner_solver = arr.INNER_GN if args.inner == "gn" else arr.INNER_MPM
     o.poly_form = {"product": arr.POLY_PRODUCT, "horner": arr.POLY_HORNER, "chebyshev": arr.POLY_CHEBYSHEV}[args.poly]
+    o.row_form = arr.ROW_PLAIN if args.row_form == "plain" else arr.ROW_AUTO
     torch.cuda.synchronize()
     tc0 = time.perf_counter()
     h = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, tol, o)
@@ -318,6 +319,8 @@ def main():
     ap.add_argument("--poly", choices=["product", "horner", "chebyshev"], default="product",
                     help="filter: psi_d as a product over its roots (default), psi_d by Algorithm 7's "
                          "recurrence, or the classic Chebyshev polynomial T_d (eq. cheby-poly)")
+    ap.add_argument("--row-form", choices=["auto", "plain"], default="auto",
+                    help="SpMM row form: paired where the matrix allows it (default), or always plain")
     ap.add_argument("--workload", choices=["lap3d100", "powerlaw2e6"], default="lap3d100",
                     help="lap3d100: the headline workload; powerlaw2e6: the 2e6-row power-law graph")
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
@@ -373,7 +376,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": workload, "precision": head_prec, "inner_solver": args.inner, "filter": args.poly},
+        "config": {"workload": workload, "precision": head_prec, "inner_solver": args.inner, "filter": args.poly,
+                   "row_form": args.row_form},
         "converged": head["converged"],
         "max_res": head["max_res"],
         "cold_start_ms": head["cold_start_ms"],

@@ -30,8 +30,11 @@
 //    reduced later in a fixed order (deterministic column norms for the
 //    multi-power normalization);
 //  * XCD-aware order: workgroup b runs on XCD b % 8; runs are dealt to the
-//    XCDs in chunks of kRunChunk so that all XCDs sweep the matrix together
-//    (small working set in the shared Infinity Cache);
+//    XCDs in chunks of up to kMaxChunk consecutive runs, so that all XCDs
+//    sweep the matrix together while a run's neighbours one grid line away
+//    were mostly loaded by the same XCD (hits in its own L2). The chunk is the
+//    largest power of two up to kMaxChunk dividing the waves per XCD, so the
+//    first sweep of the waves covers whole chunks;
 //  * paired form, for matrices with a frequent far offset P (grid operators:
 //    the neighbour one grid line away): a wave processes rows i and i + P
 //    together, and each row's entry in the other row's column is served from
@@ -53,7 +56,7 @@ constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kXcd = 8;
 constexpr int64_t kRun = 32;      // consecutive rows per wave visit
-constexpr int64_t kRunChunk = 4;  // runs per XCD chunk (128 rows)
+constexpr int kMaxChunkLog = 5;   // at most 32 runs per XCD chunk
 constexpr int kMaxGroups = 1024;  // 4 waves per SIMD on 256 CUs
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit elements
 
@@ -114,10 +117,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *p, int by
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, kRsrcWord3);
 }
 
-// Run assigned to the k-th slot of XCD x.
-__device__ __forceinline__ int64_t xcd_run(int64_t k, int x) {
-  return (x + kXcd * (k / kRunChunk)) * kRunChunk + (k % kRunChunk);
+// Run assigned to the k-th slot of XCD x, chunks of 2^lg runs.
+__device__ __forceinline__ int64_t xcd_run(int64_t k, int x, int lg) {
+  return (((k >> lg) * kXcd + x) << lg) + (k & ((1 << lg) - 1));
 }
+
+// log2 of the chunk for w waves per XCD (w is a multiple of 4).
+__device__ __forceinline__ int chunk_log(int64_t w) { return min(kMaxChunkLog, (int)__builtin_ctzll(w)); }
 
 template <typename T>
 struct RowCoef {
@@ -140,6 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
   const int x = blockIdx.x % kXcd;
   const int64_t wave_in_xcd = (int64_t)(blockIdx.x / kXcd) * kWaves + wv;
   const int64_t waves_per_xcd = (int64_t)(gridDim.x / kXcd) * kWaves;
+  const int lg = chunk_log(waves_per_xcd);
   const int64_t nruns = (n + kRun - 1) / kRun;
   const int rowbytes = w * (int)sizeof(T);
   int off[NT];
@@ -202,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
   };
 
   for (int64_t k = wave_in_xcd;; k += waves_per_xcd) {
-    const int64_t r = xcd_run(k, x);
+    const int64_t r = xcd_run(k, x, lg);
     if (r >= nruns) break;
     const int64_t i0 = r * kRun;
     if constexpr (OVF) {
@@ -356,6 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
   const int x = blockIdx.x % kXcd;
   const int64_t wave_in_xcd = (int64_t)(blockIdx.x / kXcd) * kWaves + wv;
   const int64_t waves_per_xcd = (int64_t)(gridDim.x / kXcd) * kWaves;
+  const int lg = chunk_log(waves_per_xcd);
   const int64_t half_runs = (P + R - 1) / R;
   const int64_t blocks = n / (2 * P);
   const int64_t paired_units = blocks * half_runs;
@@ -398,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
   };
 
   for (int64_t k = wave_in_xcd;; k += waves_per_xcd) {
-    const int64_t u = xcd_run(k, x);
+    const int64_t u = xcd_run(k, x, lg);
     if (u >= units) break;
     if (u < paired_units) {
       const int64_t blk = u / half_runs, r = u % half_runs;
