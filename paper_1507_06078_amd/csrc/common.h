@@ -173,11 +173,13 @@ struct DevBuf {
 
 // Yout = alpha*A*Yin + beta*Yin + gamma*Z on the w columns of the views; if
 // partial != nullptr, per-workgroup column sums of squares of Yout are written
-// to partial[g*w + c] for g < returned group count. Returns the number of
-// workgroups (rows of `partial`).
+// to partial[g*w + c] for g < returned group count. With colss (device, w
+// values; needs partial) column c of Yout is also divided by sqrt(colss[c])
+// before it is stored and summed. Returns the number of workgroups (rows of
+// `partial`).
 template <typename T>
 int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, double alpha,
-                       double beta, double gamma, double *partial, hipStream_t s);
+                       double beta, double gamma, double *partial, hipStream_t s, const double *colss = nullptr);
 // Optional HIP-event timing of kernel launches, per launch class, with the
 // algorithmic work of each launch (bytes for the SpMM, flops for the GEMMs).
 // Installed per thread by the solver. SpMM classes: columns per lane (0..4

@@ -405,6 +405,10 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     double rc = std::numeric_limits<double>::infinity();
     wk_.ensure_cols(n, wp_);
     for (int i1 = 0; i1 < o_.maxit1; ++i1) {
+      // MPM with Qc empty: X's column normalization is deferred into the last
+      // launch of the next filter (the filter is linear in X) and applied on
+      // its own only before the inner stop check
+      bool pending = false;
       for (int i2 = 0; i2 < o_.maxit2; ++i2) {
         if (o_.inner_solver == ARR_INNER_GN) {
           // GN branch: no normalization; Y in Z's second segment, rho(A) Y in W
@@ -413,13 +417,20 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
         } else {
           // MPM: normalize the columns, then X - Qc (Qc^T X); the scaling rides
           // in the projection's update when Qc is not empty
-          poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, true, s_);
-          normalize_and_project<T>(n, Qc, X, wk_, s_);
+          poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, true, s_,
+                        pending ? wk_.colv.as<double>() : nullptr);
+          if (nc_) {
+            normalize_and_project<T>(n, Qc, X, wk_, s_);
+          } else {
+            launch_reduce_groups(wk_.partial.as<double>(), wk_.groups, wp_, wk_.colv.as<double>(), false, s_);
+            pending = true;
+          }
         }
         stats.poly_calls += 1;
         stats.spmm_degrees += d_;
         stats.spmm_cols += (int64_t)d_ * wp_;
       }
+      if (pending) launch_scale_columns<T>(n, X, wk_.colv.as<double>(), true, s_);
       const double rcp = rc;
       rc = rcond_gram<T>(n, Blk<const T>{X.p, X.ld, wp_}, wk_, s_);
       const double thr = fp32_stage ? std::max(tol_t_, 1e-6) : tol_t_;

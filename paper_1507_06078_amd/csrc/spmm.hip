@@ -77,6 +77,14 @@ __device__ __forceinline__ double lane_elem(const X &x, int v) {
     return (double)x[v];
 }
 
+template <int V, typename X, typename E>
+__device__ __forceinline__ void set_elem(X &x, int v, E e) {
+  if constexpr (V == 1)
+    x = e;
+  else
+    x[v] = e;
+}
+
 // Buffer loads and stores of one lane's slot (out-of-range offsets read 0 and
 // drop the store). Output rows are written once per launch: the streaming
 // hint keeps them from displacing gathered rows in L2.
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
     int64_t n, const T *__restrict__ coef, const int32_t *__restrict__ fcol, const int64_t *__restrict__ orp,
     const int32_t *__restrict__ ocol, const T *__restrict__ oval, int w, const T *__restrict__ Yin, int64_t ldy,
     const T *Z, int64_t ldz, T *Yout, int64_t ldo, T alpha, T beta, T gamma, double *__restrict__ partial,
-    int wtot, int c0) {
+    int wtot, int c0, const double *__restrict__ colss) {
   typedef typename VecT<T, VEC>::type vec;
   typedef BufIO<T, VEC> IO;
   const int lane = threadIdx.x & 63;
@@ -164,6 +172,18 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int v = 0; v < VEC; ++v) ss[t][v] = 0.0;
+  // launches with column sums may also scale the output's columns by
+  // 1/sqrt(colss[c]) (the normalization of the block the chain started from)
+  vec cs[NT];
+  if constexpr (SUMS) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int c = VEC * lane + 64 * VEC * t + v;
+        set_elem<VEC>(cs[t], v, (T)(colss && c < w ? 1.0 / sqrt(colss[c]) : 1.0));
+      }
+  }
 
   // beta*Yin + gamma*Z and the store of row i; column sums of squares
   auto finish_row = [&](int64_t i, const vec *acc, const vec *yi, const vec *zi) {
@@ -173,6 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
       vec o = alpha * acc[t];
       if (beta != T(0)) o += beta * yi[t];
       if constexpr (HASZ) o += gamma * zi[t];
+      if constexpr (SUMS) o *= cs[t];
       IO::st(o, r, off[t]);
       if constexpr (SUMS) {
 #pragma unroll
@@ -354,7 +375,7 @@ template <typename T, int VEC, int NT, int KF, bool HASZ, bool SUMS>
 __global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
     int64_t n, int64_t P, const T *__restrict__ coef, const int32_t *__restrict__ fcol, int w,
     const T *__restrict__ Yin, int64_t ldy, const T *Z, int64_t ldz, T *Yout, int64_t ldo, T alpha, T beta,
-    T gamma, double *__restrict__ partial, int wtot, int c0) {
+    T gamma, double *__restrict__ partial, int wtot, int c0, const double *__restrict__ colss) {
   typedef typename VecT<T, VEC>::type vec;
   typedef BufIO<T, VEC> IO;
   constexpr int R = (int)kPairRun;
@@ -385,6 +406,18 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int v = 0; v < VEC; ++v) ss[t][v] = 0.0;
+  // launches with column sums may also scale the output's columns by
+  // 1/sqrt(colss[c]) (the normalization of the block the chain started from)
+  vec cs[NT];
+  if constexpr (SUMS) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int c = VEC * lane + 64 * VEC * t + v;
+        set_elem<VEC>(cs[t], v, (T)(colss && c < w ? 1.0 / sqrt(colss[c]) : 1.0));
+      }
+  }
 
   auto finish_row = [&](int64_t i, bool own, const vec *acc, const vec *yi, const vec *zi) {
     const __amdgpu_buffer_rsrc_t r = row_rsrc(Yout + i * ldo, own ? rowbytes : 0);
@@ -394,6 +427,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
       vec o = alpha * acc[t];
       if (beta != T(0)) o += beta * yi[t];
       if constexpr (HASZ) o += gamma * zi[t];
+      if constexpr (SUMS) o *= cs[t];
       IO::st(o, r, off[t]);
       if constexpr (SUMS) {
 #pragma unroll
@@ -576,21 +610,22 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, int64_t P, const T *__r
 
 template <typename T, int VEC, int NT, bool OVF, bool HASZ, bool SUMS>
 void launch_variant(const DevCSR<T> &A, Blk<const T> Yin, const T *zp, int64_t ldz, Blk<T> Yout, int w, int c0,
-                    T alpha, T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+                    T alpha, T beta, T gamma, double *partial, int wtot, int groups, const double *colss,
+                    hipStream_t s) {
   hipLaunchKernelGGL((k_filter_spmm<T, VEC, NT, OVF, HASZ, SUMS>), dim3(groups), dim3(kThreads), 0, s, A.n, A.coef,
                      A.fcol, A.orp, A.ocol, A.oval, w, Yin.p + c0, Yin.ld, zp, ldz, Yout.p + c0, Yout.ld, alpha, beta,
-                     gamma, partial, wtot, c0);
+                     gamma, partial, wtot, c0, colss ? colss + c0 : nullptr);
 }
 
 template <typename T, int VEC, int NT>
 void launch_nt(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w, int c0, T alpha,
-               T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+               T beta, T gamma, double *partial, int wtot, int groups, const double *colss, hipStream_t s) {
   const T *zp = Z.p ? Z.p + c0 : nullptr;
   const int sel = (A.orp ? 4 : 0) + (zp ? 2 : 0) + (partial ? 1 : 0);
 #define ARR_SPMM_CASE(k, O, H, S)                                                                        \
   case k:                                                                                               \
     launch_variant<T, VEC, NT, O, H, S>(A, Yin, zp, Z.ld, Yout, w, c0, alpha, beta, gamma, partial, wtot, \
-                                        groups, s);                                                     \
+                                        groups, colss, s);                                              \
     break;
   switch (sel) {
     ARR_SPMM_CASE(0, false, false, false)
@@ -607,21 +642,23 @@ void launch_nt(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout
 
 template <typename T, int VEC, int NT, int KF, bool HASZ, bool SUMS>
 void launch_paired_variant(const DevCSR<T> &A, Blk<const T> Yin, const T *zp, int64_t ldz, Blk<T> Yout, int w, int c0,
-                           T alpha, T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+                           T alpha, T beta, T gamma, double *partial, int wtot, int groups, const double *colss,
+                           hipStream_t s) {
   hipLaunchKernelGGL((k_filter_spmm_paired<T, VEC, NT, KF, HASZ, SUMS>), dim3(groups), dim3(kThreads), 0, s, A.n,
                      A.pair, A.coef, A.fcol, w, Yin.p + c0, Yin.ld, zp, ldz, Yout.p + c0, Yout.ld, alpha, beta, gamma,
-                     partial, wtot, c0);
+                     partial, wtot, c0, colss ? colss + c0 : nullptr);
 }
 
 template <typename T, int VEC, int NT>
 void launch_paired_nt(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w, int c0, T alpha,
-                      T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+                      T beta, T gamma, double *partial, int wtot, int groups, const double *colss,
+                      hipStream_t s) {
   const T *zp = Z.p ? Z.p + c0 : nullptr;
   const int sel = (A.kf == 1 ? 4 : 0) + (zp ? 2 : 0) + (partial ? 1 : 0);
 #define ARR_SPMM_CASE(k, KF, H, S)                                                                              \
   case k:                                                                                                      \
     launch_paired_variant<T, VEC, NT, KF, H, S>(A, Yin, zp, Z.ld, Yout, w, c0, alpha, beta, gamma, partial, wtot, \
-                                                groups, s);                                                    \
+                                                groups, colss, s);                                             \
     break;
   switch (sel) {
     ARR_SPMM_CASE(0, 3, false, false)
@@ -639,11 +676,11 @@ void launch_paired_nt(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<
 // Either form's kernel for one column chunk.
 template <typename T, int VEC, int NT>
 void launch_form(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w, int c0, T alpha,
-                 T beta, T gamma, double *partial, int wtot, int groups, hipStream_t s) {
+                 T beta, T gamma, double *partial, int wtot, int groups, const double *colss, hipStream_t s) {
   if (A.pair)
-    launch_paired_nt<T, VEC, NT>(A, Yin, Z, Yout, w, c0, alpha, beta, gamma, partial, wtot, groups, s);
+    launch_paired_nt<T, VEC, NT>(A, Yin, Z, Yout, w, c0, alpha, beta, gamma, partial, wtot, groups, colss, s);
   else
-    launch_nt<T, VEC, NT>(A, Yin, Z, Yout, w, c0, alpha, beta, gamma, partial, wtot, groups, s);
+    launch_nt<T, VEC, NT>(A, Yin, Z, Yout, w, c0, alpha, beta, gamma, partial, wtot, groups, colss, s);
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -821,10 +858,11 @@ void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
 
 template <typename T>
 int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, double alpha,
-                       double beta, double gamma, double *partial, hipStream_t s) {
+                       double beta, double gamma, double *partial, hipStream_t s, const double *colss) {
   const int w = Yout.w;
   ARR_REQUIRE(Yin.w >= w && (!Z.p || Z.w >= w), "filter_spmm: block widths differ");
   ARR_REQUIRE(Yin.p != Yout.p, "filter_spmm: Yout must not alias Yin");
+  ARR_REQUIRE(!colss || partial, "filter_spmm: output column scaling needs the column sums");
   ARR_REQUIRE(A.n == 0 || (A.coef && A.fcol), "filter_spmm: matrix rows missing");
   ARR_REQUIRE(!A.orp || (A.ocol && A.oval), "filter_spmm: overflow entries missing");
   ARR_REQUIRE(A.pair == 0 || (!A.orp && A.pair >= kPairRun && 2 * A.pair <= A.n && (A.kf == 1 || A.kf == 3)),
@@ -861,17 +899,17 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
     if (vec4) {
       if constexpr (sizeof(T) == 4) {
         if (wc <= 256)
-          launch_form<T, 4, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+          launch_form<T, 4, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
         else
-          launch_form<T, 4, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+          launch_form<T, 4, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
       }
     } else if (wc <= 64) {
-      launch_form<T, 1, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+      launch_form<T, 1, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
     } else if constexpr (sizeof(T) == 8) {
       if (wc <= 128)
-        launch_form<T, 1, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+        launch_form<T, 1, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
       else
-        launch_form<T, 1, 4>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, s);
+        launch_form<T, 1, 4>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
     }
     if (timer) {
       ARR_HIP(hipEventRecord(pend.b, s));
@@ -892,9 +930,10 @@ void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s) {
 }
 
 template int launch_filter_spmm<double>(const DevCSR<double> &, Blk<const double>, Blk<const double>,
-                                        Blk<double>, double, double, double, double *, hipStream_t);
+                                        Blk<double>, double, double, double, double *, hipStream_t,
+                                        const double *);
 template int launch_filter_spmm<float>(const DevCSR<float> &, Blk<const float>, Blk<const float>, Blk<float>,
-                                       double, double, double, double *, hipStream_t);
+                                       double, double, double, double *, hipStream_t, const double *);
 template void launch_spmv<double>(const DevCSR<double> &, const double *, double *, hipStream_t);
 template void launch_spmv<float>(const DevCSR<float> &, const float *, float *, hipStream_t);
 

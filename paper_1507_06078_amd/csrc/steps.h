@@ -31,11 +31,16 @@ struct Work {
 // Algorithm 7 with the caller's monomial coefficients g (leading first).
 template <typename T>
 void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
-                       const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s);
-// psi_d in the chosen PolyForm.
+                       const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s,
+                       const double *in_colss = nullptr);
+// psi_d in the chosen PolyForm. With in_colss (device, X.w values; needs
+// want_norms) the result's column j is divided by sqrt(in_colss[j]) in the
+// last launch: the polynomial is linear in X, so this equals filtering X
+// with its columns normalized first (a deferred normalization).
 template <typename T>
 void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
-                const FilterPoly &fp, int form, Work &wk, bool want_norms, hipStream_t s);
+                const FilterPoly &fp, int form, Work &wk, bool want_norms, hipStream_t s,
+                const double *in_colss = nullptr);
 template <typename T>
 void normalize_from_partial(int64_t n, Blk<T> X, Work &wk, hipStream_t s);
 template <typename T>

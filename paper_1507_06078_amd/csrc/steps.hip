@@ -62,12 +62,13 @@ void Work::ensure_small(int m) {
 
 template <typename T>
 void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
-                const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s) {
+                const std::vector<double> &g, Work &wk, bool want_norms, hipStream_t s, const double *in_colss) {
   const int d = (int)g.size() - 1;
   ARR_REQUIRE(d >= 1, "poly: degree must be >= 1");
   ARR_REQUIRE(hi != lo, "poly: empty interval");
   const int w = X.w;
   double *partial = want_norms ? wk.partial.as<double>() : nullptr;
+  ARR_REQUIRE(!in_colss || want_norms, "poly: deferred normalization needs the column norms");
   const double c0 = (lo + hi) / (lo - hi), c1 = 2.0 / (hi - lo);
   const Blk<const T> Xc{X.p, X.ld, w};
   const Blk<const T> none{nullptr, 0, 0};
@@ -75,7 +76,7 @@ void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doubl
   const double al1 = c1 * g[0], be1 = g[0] * (c0 - c1 * shift) + g[1];
   const double al = c1, be = c0 - c1 * shift;
   if (d == 1) {
-    wk.groups = launch_filter_spmm<T>(A, Xc, none, Ya, al1, be1, 0.0, partial, s);
+    wk.groups = launch_filter_spmm<T>(A, Xc, none, Ya, al1, be1, 0.0, partial, s, in_colss);
     launch_copy<T>(A.n, w, X.p, X.ld, Ya.p, Ya.ld, s);
     return;
   }
@@ -86,7 +87,7 @@ void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doubl
     std::swap(cur, nxt);
   }
   // last degree writes X in place (Z = X is read row-locally before the store)
-  wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, Xc, X, al, be, g[d], partial, s);
+  wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, Xc, X, al, be, g[d], partial, s, in_colss);
 }
 
 // The same polynomial as a product of linear factors over its real roots
@@ -95,18 +96,20 @@ void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doubl
 // per degree; the last degree writes X and (optionally) its column norms.
 template <typename T>
 void poly_apply_product(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
-                        const std::vector<double> &roots, double lead, Work &wk, bool want_norms, hipStream_t s) {
+                        const std::vector<double> &roots, double lead, Work &wk, bool want_norms, hipStream_t s,
+                        const double *in_colss) {
   const int d = (int)roots.size();
   ARR_REQUIRE(d >= 1, "poly: degree must be >= 1");
   ARR_REQUIRE(hi != lo, "poly: empty interval");
   const int w = X.w;
   double *partial = want_norms ? wk.partial.as<double>() : nullptr;
+  ARR_REQUIRE(!in_colss || want_norms, "poly: deferred normalization needs the column norms");
   const double c0 = (lo + hi) / (lo - hi), c1 = 2.0 / (hi - lo);
   const Blk<const T> none{nullptr, 0, 0};
   auto beta = [&](int i) { return c0 - c1 * shift - roots[i]; };
   if (d == 1) {
     wk.groups = launch_filter_spmm<T>(A, Blk<const T>{X.p, X.ld, w}, none, Ya, lead * c1, lead * beta(0), 0.0,
-                                      partial, s);
+                                      partial, s, in_colss);
     launch_copy<T>(A.n, w, X.p, X.ld, Ya.p, Ya.ld, s);
     return;
   }
@@ -116,7 +119,8 @@ void poly_apply_product(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doub
     launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, none, nxt, c1, beta(i), 0.0, nullptr, s);
     std::swap(cur, nxt);
   }
-  wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, none, X, c1, beta(d - 1), 0.0, partial, s);
+  wk.groups =
+      launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, none, X, c1, beta(d - 1), 0.0, partial, s, in_colss);
 }
 
 // The classic Chebyshev filter (eq. cheby-poly) in place of psi_d:
@@ -126,33 +130,35 @@ void poly_apply_product(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doub
 // not a multiple of 3 the result is copied into X.
 template <typename T>
 void poly_apply_chebyshev(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
-                          int d, Work &wk, bool want_norms, hipStream_t s) {
+                          int d, Work &wk, bool want_norms, hipStream_t s, const double *in_colss) {
   ARR_REQUIRE(d >= 1, "poly: degree must be >= 1");
   ARR_REQUIRE(hi != lo, "poly: empty interval");
   const int w = X.w;
   double *partial = want_norms ? wk.partial.as<double>() : nullptr;
+  ARR_REQUIRE(!in_colss || want_norms, "poly: deferred normalization needs the column norms");
   const double c0 = (lo + hi) / (lo - hi), c1 = 2.0 / (hi - lo);
   const double b1 = c0 - c1 * shift;  // t = c1 A + b1 I
   const Blk<T> buf[3] = {Blk<T>{X.p, X.ld, w}, Blk<T>{Ya.p, Ya.ld, w}, Blk<T>{Yb.p, Yb.ld, w}};
   auto in = [&](int j) { return Blk<const T>{buf[j % 3].p, buf[j % 3].ld, w}; };
   const Blk<const T> none{nullptr, 0, 0};
-  int groups = launch_filter_spmm<T>(A, in(0), none, buf[1], c1, b1, 0.0, d == 1 ? partial : nullptr, s);
+  int groups = launch_filter_spmm<T>(A, in(0), none, buf[1], c1, b1, 0.0, d == 1 ? partial : nullptr, s,
+                                     d == 1 ? in_colss : nullptr);
   for (int j = 1; j < d; ++j)
     groups = launch_filter_spmm<T>(A, in(j), in(j - 1), buf[(j + 1) % 3], 2.0 * c1, 2.0 * b1, -1.0,
-                                   j == d - 1 ? partial : nullptr, s);
+                                   j == d - 1 ? partial : nullptr, s, j == d - 1 ? in_colss : nullptr);
   if (d % 3 != 0) launch_copy<T>(A.n, w, X.p, X.ld, buf[d % 3].p, buf[d % 3].ld, s);
   if (want_norms) wk.groups = groups;
 }
 
 template <typename T>
 void poly_apply(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, double shift, double lo, double hi,
-                const FilterPoly &fp, int form, Work &wk, bool want_norms, hipStream_t s) {
+                const FilterPoly &fp, int form, Work &wk, bool want_norms, hipStream_t s, const double *in_colss) {
   if (form == kPolyHorner)
-    poly_apply_horner<T>(A, X, Ya, Yb, shift, lo, hi, fp.gamma, wk, want_norms, s);
+    poly_apply_horner<T>(A, X, Ya, Yb, shift, lo, hi, fp.gamma, wk, want_norms, s, in_colss);
   else if (form == kPolyChebyshev)
-    poly_apply_chebyshev<T>(A, X, Ya, Yb, shift, lo, hi, (int)fp.gamma.size() - 1, wk, want_norms, s);
+    poly_apply_chebyshev<T>(A, X, Ya, Yb, shift, lo, hi, (int)fp.gamma.size() - 1, wk, want_norms, s, in_colss);
   else
-    poly_apply_product<T>(A, X, Ya, Yb, shift, lo, hi, fp.roots, fp.lead, wk, want_norms, s);
+    poly_apply_product<T>(A, X, Ya, Yb, shift, lo, hi, fp.roots, fp.lead, wk, want_norms, s, in_colss);
 }
 
 template <typename T>
@@ -335,9 +341,9 @@ std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, c
 
 #define ARR_INST(T)                                                                                              \
   template void poly_apply_horner<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, double, double, double,          \
-                                     const std::vector<double> &, Work &, bool, hipStream_t);                    \
+                                     const std::vector<double> &, Work &, bool, hipStream_t, const double *);    \
   template void poly_apply<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, double, double, double,                 \
-                              const FilterPoly &, int, Work &, bool, hipStream_t);                               \
+                              const FilterPoly &, int, Work &, bool, hipStream_t, const double *);               \
   template void normalize_from_partial<T>(int64_t, Blk<T>, Work &, hipStream_t);                                 \
   template void normalize<T>(int64_t, Blk<T>, Work &, hipStream_t);                                              \
   template void project_out<T>(int64_t, Blk<const T>, Blk<T>, Work &, hipStream_t, const double *);             \
