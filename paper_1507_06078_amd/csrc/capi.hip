@@ -543,10 +543,12 @@ int arr_augmented_rr(const arr_dev_csr_t *A, int64_t w, const double *X, int64_t
                                       arr::Blk<double>{Z.p + i * iw, m, iw}, 1.0, 0.0, 0.0, nullptr, s);
     const arr::Blk<const double> Q{Qc, ldq, nc};
     if (nc) arr::project_out<double>(n, Q, Z, wk, s);
-    arr::Blk<double> U = arr::orthonormalize<double>(n, Z, arr::Blk<double>{ub.as<double>(), m, m}, Q, wk, s, nullptr);
+    const double *rinv = nullptr;
+    arr::Blk<double> U =
+        arr::orthonormalize<double>(n, Z, arr::Blk<double>{ub.as<double>(), m, m}, Q, wk, s, nullptr, &rinv);
     std::vector<double> ev;
     arr::rayleigh_ritz<double>(M, n, arr::Blk<const double>{U.p, U.ld, m}, arr::Blk<double>{wb.as<double>(), m, m}, wk,
-                               ev, s);
+                               ev, s, rinv);
     const double *V = wk.small.as<double>() + (size_t)m * m;
     arr::launch_update<double>(n, arr::Blk<const double>{U.p, U.ld, m}, V, m, iw, 1.0, 0.0, arr::Blk<double>{Y, ldy, iw}, s);
     std::copy(ev.begin(), ev.begin() + iw, ritz_vals);

@@ -450,10 +450,12 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     const int m = (p_ + 1) * wp_;
     // ---- RR on the projection onto R(Qc)^perp (Algorithm 1, Sec. 6) ----
     const double td = now();
-    Blk<T> U = orthonormalize<T>(n, B.Z(0, m), B.U(0, m), Qc, wk_, s_, nullptr);
+    // the closing Cholesky QR factor rides in the small Rayleigh-Ritz problem
+    const double *rinv = nullptr;
+    Blk<T> U = orthonormalize<T>(n, B.Z(0, m), B.U(0, m), Qc, wk_, s_, nullptr, &rinv);
     Blk<T> Pfree = (U.p == B.Zb.template as<T>()) ? B.U(0, m) : B.Z(0, m);
     std::vector<double> ritz;
-    rayleigh_ritz<T>(A, n, Blk<const T>{U.p, U.ld, m}, B.W(0, m), wk_, ritz, s_);
+    rayleigh_ritz<T>(A, n, Blk<const T>{U.p, U.ld, m}, B.W(0, m), wk_, ritz, s_, rinv);
     stats.t_dense += now() - td;
     stats.arr_calls += 1;
     // ---- merge with (Qc, Sigma_c): keep the w leading (stable, Qc first) ----

@@ -63,13 +63,21 @@ template <typename T>
 double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s);
 // Orthonormal basis of R(Z) (and orthogonal to Q when Q.w > 0); Z and Zalt
 // are n x m buffers used alternately; returns the one holding the result.
+// With rinv != nullptr the factor of the closing Cholesky QR pass may be left
+// unapplied: the returned block is then Q1 with basis Q1 R^{-1}, *rinv points
+// to R^{-1} (upper triangular, m x m, ld m, inside wk.small, kept until the
+// next Cholesky QR or small solve); otherwise *rinv = nullptr.
 template <typename T>
-Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk, hipStream_t s, int *passes);
+Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk, hipStream_t s, int *passes,
+                      const double **rinv = nullptr);
 // W = A U, H = U^T W, eigendecomposition of H: evals (descending, host) and the
-// eigenvectors as columns of the m x m matrix at wk.small + m*m.
+// eigenvectors as columns of the m x m matrix at wk.small + m*m. With rinv
+// (from orthonormalize) the basis is U R^{-1}: H = R^{-T} (U^T W) R^{-1}, and
+// the matrix at wk.small + m*m is R^{-1} V, so that U (R^{-1} V) and
+// W (R^{-1} V) are the Ritz vectors and their images.
 template <typename T>
 void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work &wk, std::vector<double> &evals,
-                   hipStream_t s);
+                   hipStream_t s, const double *rinv = nullptr);
 template <typename T>
 std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, const double *mu_dev, Work &wk,
                                    hipStream_t s);

@@ -253,14 +253,16 @@ void gn_step(const DevCSR<T> &A, Blk<T> X, Blk<T> Y, Blk<T> Z, Blk<T> Ya, Blk<T>
 // (1-based) failing pivot column or 0.
 template <typename T>
 static int cholqr_pass(int64_t n, Blk<const T> Z, Blk<T> Zout, double shift_rel, bool allow_shift, Work &wk,
-                       hipStream_t s, int *shifted) {
+                       hipStream_t s, int *shifted, double **factor = nullptr) {
   const int m = Z.w;
   const size_t mm = (size_t)m * m;
   double *G = wk.small.as<double>();
-  double *Wt = G + mm;
-  double *nrm = Wt + mm;           // 2 doubles
+  double *nrm = G + 2 * mm;        // 2 doubles
   double *scratch = nrm + 64;      // 2 m^2 doubles
   double *Gsave = scratch + 2 * mm;
+  // R^{-1}: after G when applied here, else in the last m^2 of wk.small
+  // (kept through the Rayleigh-Ritz step that applies it)
+  double *Wt = factor ? Gsave + mm : G + mm;
   *shifted = 0;
   launch_gram<T>(n, Z, Z, G, wk.gramw.as<double>(), true, s);
   if (allow_shift) launch_copy<double>(m, m, Gsave, m, G, m, s);
@@ -281,12 +283,16 @@ static int cholqr_pass(int64_t n, Blk<const T> Z, Blk<T> Zout, double shift_rel,
   }
   if (info) return info;
   launch_tri_inv_t(m, G, m, Wt, m, scratch, s);
-  launch_update<T>(n, Z, Wt, m, m, 1.0, 0.0, Zout, s, true);
+  if (factor)
+    *factor = Wt;
+  else
+    launch_update<T>(n, Z, Wt, m, m, 1.0, 0.0, Zout, s, true);
   return 0;
 }
 
 template <typename T>
-Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk, hipStream_t s, int *passes) {
+Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk, hipStream_t s, int *passes,
+                      const double **rinv) {
   const int m = Z.w;
   wk.ensure_gram(n, m, m);
   wk.ensure_small(m);
@@ -296,15 +302,26 @@ Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk
   const double shift_rel = 11.0 * ((double)m * (double)n + (double)m * (m + 1)) * u;
   Blk<T> cur = Z, nxt = Zalt;
   int done_plain = 0, total = 0;
+  if (rinv) *rinv = nullptr;
   // up to 2 plain passes after any shifted ones; at most 6 in all
   while (done_plain < 2 && total < 6) {
     if (Q.w) project_out<T>(n, Q, cur, wk, s);
     int shifted = 0;
-    const int info = cholqr_pass<T>(n, Blk<const T>{cur.p, cur.ld, m}, nxt, shift_rel, true, wk, s, &shifted);
+    // the pass that closes the loop if it needs no shift may leave its factor
+    // to the caller; a shifted one is applied here after all
+    double *factor = nullptr;
+    const bool closing = rinv && done_plain == 1 && total < 5;
+    const int info = cholqr_pass<T>(n, Blk<const T>{cur.p, cur.ld, m}, nxt, shift_rel, true, wk, s, &shifted,
+                                    closing ? &factor : nullptr);
     if (info) throw Error(-5, "Cholesky QR broke down even with a diagonal shift");
+    ++total;
+    if (closing && !shifted) {
+      *rinv = factor;
+      break;
+    }
+    if (closing) launch_update<T>(n, Blk<const T>{cur.p, cur.ld, m}, factor, m, m, 1.0, 0.0, nxt, s, true);
     done_plain = shifted ? 0 : done_plain + 1;
     std::swap(cur, nxt);
-    ++total;
   }
   if (passes) *passes = total;
   return cur;
@@ -312,17 +329,33 @@ Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk
 
 template <typename T>
 void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work &wk, std::vector<double> &evals,
-                   hipStream_t s) {
+                   hipStream_t s, const double *rinv) {
   const int m = U.w;
   const Blk<const T> none{nullptr, 0, 0};
   launch_filter_spmm<T>(A, U, none, W, 1.0, 0.0, 0.0, nullptr, s);
   wk.ensure_gram(n, m, m);
   wk.ensure_small(m);
+  const size_t mm = (size_t)m * m;
   double *H = wk.small.as<double>();
-  double *V = H + (size_t)m * m;
+  double *V = H + mm;
+  double *T1 = V + mm + 64;  // below the factor rinv (last m^2 of wk.small)
   // H = U^T (A U) is symmetric: form its upper tiles and mirror them
   launch_gram<T>(n, U, Blk<const T>{W.p, W.ld, m}, H, wk.gramw.as<double>(), true, s, /*fp32_cores=*/true);
+  // the m x m products below run on the FP64 matrix cores as products with m
+  // rows (R^{-1} is upper triangular)
+  const Blk<const double> R{rinv, m, m};
+  if (rinv) {
+    // H <- R^{-T} (H R^{-1})
+    launch_update<double>(m, Blk<const double>{H, m, m}, rinv, m, m, 1.0, 0.0, Blk<double>{T1, m, m}, s, true);
+    wk.ensure_gram(m, m, m);
+    launch_gram<double>(m, R, Blk<const double>{T1, m, m}, H, wk.gramw.as<double>(), false, s);
+  }
   wk.jac.solve(m, H, V, evals, s, &wk.last_sweeps);
+  if (rinv) {
+    // V <- R^{-1} V
+    launch_update<double>(m, R, V, m, m, 1.0, 0.0, Blk<double>{T1, m, m}, s, false);
+    launch_copy<double>(m, m, V, m, T1, m, s);
+  }
 }
 
 template <typename T>
@@ -351,9 +384,10 @@ std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, c
   template void gn_step<T>(const DevCSR<T> &, Blk<T>, Blk<T>, Blk<T>, Blk<T>, Blk<T>, double, double, double,    \
                            const FilterPoly &, int, Work &, hipStream_t);                                        \
   template double rcond_gram<T>(int64_t, Blk<const T>, Work &, hipStream_t);                                     \
-  template Blk<T> orthonormalize<T>(int64_t, Blk<T>, Blk<T>, Blk<const T>, Work &, hipStream_t, int *);          \
+  template Blk<T> orthonormalize<T>(int64_t, Blk<T>, Blk<T>, Blk<const T>, Work &, hipStream_t, int *,          \
+                                    const double **);                                                           \
   template void rayleigh_ritz<T>(const DevCSR<T> &, int64_t, Blk<const T>, Blk<T>, Work &, std::vector<double> &, \
-                                 hipStream_t);                                                                   \
+                                 hipStream_t, const double *);                                                   \
   template std::vector<double> residual_norms<T>(int64_t, Blk<const T>, Blk<const T>, const double *, Work &,    \
                                                  hipStream_t);
 ARR_INST(double)
