@@ -4,7 +4,9 @@ the solver uses there.
 * 3D Laplacian 100^3 + potential (n = 1e6, k = 200, block 240): whole solves,
   FP64 and mixed, checked by properties that hold at any size: residuals
   recomputed on the CPU in FP64, orthonormality, Weyl's bounds against the
-  closed-form Laplacian spectrum (0 <= V <= I), and FP64/mixed agreement.
+  closed-form Laplacian spectrum (0 <= V <= I), and FP64/mixed agreement;
+  one filter degree in the solver's launch configuration (paired row form,
+  240 columns of an n x 960 block) on sampled rows.
 * Power-law graph (n = 2e6, rows up to ~2000 entries, block 600, FP32) and
   the SBM normalized Laplacian (n = 4e6, block 1200, FP32 and FP64): one
   filter degree on device-generated blocks, checked on sampled rows against
@@ -109,6 +111,39 @@ def _filter_case(A, w, dtype, n_samples=256, seed=11):
     ref_ss = (Od.double() ** 2).sum(dim=0)
     assert torch.allclose(ss, ref_ss, rtol=1e-10, atol=0)
     del Yd, Zd, Od, Ad
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lap3d_filter_step_paired_solver_layout_sampled(lap3d, dtype):
+    """The headline SpMM as the solver launches it: the paired row form
+    (P = 100, three far slots), 240 columns of an n x 960 block (the Krylov
+    array's leading dimension), no Z operand (the product form's factors),
+    with the column sums of the last degree."""
+    A = lap3d
+    assert arr.arr_row_form(A) == (100, 3, 0)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    Ad = arr.DeviceCSR(A, dtype=tdt)
+    w, ld = 240, 960
+    Yfull = _device_block(A.n, ld, tdt, 31)
+    Ofull = torch.zeros((A.n, ld), dtype=tdt, device="cuda")
+    Yd, Od = Yfull[:, :w], Ofull[:, w:2 * w]
+    ss = torch.zeros(w, dtype=torch.float64, device="cuda")
+    al, be = 0.25, -1.5  # exact in FP32
+    arr.arr_filter_step(Ad, Yd, None, Od, al, be, 0.0, colsumsq=ss)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(13)
+    rows = np.sort(rng.choice(A.n, 256, replace=False))
+    # both ends, and rows at the edges of the paired runs and blocks
+    edges = [0, 1, 19, 20, 99, 100, 119, 120, 199, 200, 10_000, 500_099, A.n - 101, A.n - 100, A.n - 2, A.n - 1]
+    rows = np.unique(np.concatenate([rows, edges]))
+    Zd = torch.zeros((A.n, 1), dtype=tdt, device="cuda").expand(A.n, w)
+    _sampled_filter_check(A, Yd, Zd, Od, al, be, 0.0, rows, U32 if dtype == "f32" else U64)
+    assert torch.equal(Ofull[:, :w], torch.zeros_like(Ofull[:, :w]))  # nothing written outside the view
+    assert torch.equal(Ofull[:, 2 * w:], torch.zeros_like(Ofull[:, 2 * w:]))
+    ref_ss = (Od.double() ** 2).sum(dim=0)
+    assert torch.allclose(ss, ref_ss, rtol=1e-10, atol=0)
+    del Yfull, Ofull, Ad
     torch.cuda.empty_cache()
 
 
