@@ -103,6 +103,23 @@ def test_c1_chebyshev_mode_matches_oracle_and_closed_form(precision, inner):
     assert_same_subspaces(ev, X, ref.evecs)
 
 
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_c1_horner_form_matches_oracle_and_closed_form(precision):
+    """Algorithm 8 with psi_d applied by Algorithm 7's recurrence (the Horner
+    form, whose last launch also carries the deferred column normalization)."""
+    A, k, which, w, tol = W.workload("lap2d_40")
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    status, ev, X, res, st = solve(A, k, which, tol, w=w, precision=precision, X0=X0,
+                                   poly_form=arr.POLY_HORNER)
+    assert status == arr.ARR_OK, st
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    ref = O.arrabit_mpm(A.to_scipy(), k, 1e-12, X0, which)
+    assert np.all(np.abs(ev - exact) <= 1e-10 * np.maximum(1, np.abs(exact)))
+    assert np.all(np.abs(ev - ref.evals) <= 1e-10 * np.maximum(1, np.abs(ref.evals)))
+    check_pairs(A, ev, X, tol)
+    assert_same_subspaces(ev, X, ref.evecs)
+
+
 @pytest.mark.parametrize("which", ["LA", "SA"])
 def test_gn_random_symmetric_vs_dense(which):
     n, k, w = 300, 8, 12
