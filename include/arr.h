@@ -166,7 +166,7 @@ typedef struct {
   double spmm_bytes;
   int32_t spmm_cols_per_lane; /* kernel variant: columns per lane (1, 2, 4, 8, 16) */
   int32_t spmm_fp64;          /* data type of that variant: 1 FP64, 0 FP32 */
-  int32_t spmm_vec;           /* columns per lane load: 1, or 4 (16-byte FP32 loads) */
+  int32_t spmm_vec;           /* columns per lane load: 1, 4 (16-byte FP32 loads) or 2 (16-byte FP64 loads) */
   /* HIP-event timing (timing = 1) of the dense products: Gram products X^T Y
    * (tile kernel plus its split reduction) and block updates X W. Work is
    * counted in algorithmic flops: 2 n mx my, n m (m + 1) for a symmetric

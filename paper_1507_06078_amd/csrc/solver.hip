@@ -678,9 +678,9 @@ int Solver::solve() {
     stats.spmm_launches = timer.launches[best];
     stats.spmm_ms = timer.ms[best];
     stats.spmm_bytes = timer.bytes[best];
-    // class = slots + 5 vec4 + 10 fp64 + 20 flags
+    // class = slots + 5 (16-byte loads) + 10 fp64 + 20 flags
     stats.spmm_cols_per_lane = 1 << (best % 5);
-    stats.spmm_vec = (best % 10) >= 5 ? 4 : 1;
+    stats.spmm_vec = (best % 10) >= 5 ? ((best % 20) >= 10 ? 2 : 4) : 1;
     stats.spmm_fp64 = (best % 20) >= 10 ? 1 : 0;
     stats.spmm_flags = best / 20;
     int best32 = 0;

@@ -23,7 +23,8 @@
 //    width: lanes past it read zeros and their stores are dropped, so no lane
 //    predicate splits the code; lane l owns columns l, l+64, ... (FP32 blocks
 //    with 16-byte aligned rows: 4 consecutive columns per lane, one 16-byte
-//    load), so every gathered row is read as full contiguous segments;
+//    load; FP64 blocks in the paired form: 2 consecutive columns per lane),
+//    so every gathered row is read as full contiguous segments;
 //  * the recurrence (beta*Yin + gamma*Z) is applied in the epilogue, so a
 //    degree makes exactly one pass over Yin (gathered), Z and Yout;
 //  * optional epilogue: per-workgroup column sums of squares of Yout in FP64,
@@ -98,6 +99,17 @@ struct BufIO<double, 1> {
   static __device__ __forceinline__ void st(double v, __amdgpu_buffer_rsrc_t r, int off) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
                                           off, 0, 2);
+  }
+};
+template <>
+struct BufIO<double, 2> {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ v2 ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(v2 v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
+                                           off, 0, 2);
   }
 };
 template <>
@@ -876,15 +888,23 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   // Column chunks: at most 4 slots per lane for FP64 (256 columns), 2 with
   // 16-byte FP32 loads (512 columns), 1 for FP32 rows that are not 16-byte
   // aligned (64 columns)
+  // FP64 in the paired form with 16-byte aligned rows and an even width: two
+  // consecutive columns per lane (128 columns per wave instruction); the
+  // plain form keeps 8-byte loads, which measured faster there
+  const bool vec2 = sizeof(T) == 8 && A.pair && Yin.ld % 2 == 0 && Yout.ld % 2 == 0 &&
+                    (!Z.p || Z.ld % 2 == 0) && aligned16(Yin.p) && aligned16(Yout.p) && (!Z.p || aligned16(Z.p)) &&
+                    w % 2 == 0;
   const int chunk = vec4 ? 512 : sizeof(T) == 8 ? 256 : 64;
   for (int c0 = 0; c0 < w; c0 += chunk) {
     const int wc = std::min(chunk, w - c0);
     const T al = (T)alpha, be = (T)beta, ga = (T)gamma;
-    const int slots = vec4 ? 4 * ((wc + 255) / 256) : (wc + 63) / 64;  // columns per lane
+    const int slots = vec4   ? 4 * ((wc + 255) / 256)
+                      : vec2 ? 2 * ((wc + 127) / 128)
+                             : (wc + 63) / 64;  // columns per lane
     const int flags = (Z.p ? 1 : 0) + (A.orp ? 2 : 0) + (partial ? 4 : 0) + (A.pair ? 8 : 0) +
                       (A.pair && A.kf == 1 ? 16 : 0);
-    const int cls = (slots <= 1 ? 0 : slots <= 2 ? 1 : slots <= 4 ? 2 : slots <= 8 ? 3 : 4) + (vec4 ? 5 : 0) +
-                    (sizeof(T) == 8 ? 10 : 0) + 20 * flags;
+    const int cls = (slots <= 1 ? 0 : slots <= 2 ? 1 : slots <= 4 ? 2 : slots <= 8 ? 3 : 4) +
+                    (vec4 || vec2 ? 5 : 0) + (sizeof(T) == 8 ? 10 : 0) + 20 * flags;
     SpmmTimer::Pending pend{};
     if (timer) {
       pend.a = timer->get();
@@ -902,6 +922,13 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
           launch_form<T, 4, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
         else
           launch_form<T, 4, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
+      }
+    } else if (vec2) {
+      if constexpr (sizeof(T) == 8) {
+        if (wc <= 128)
+          launch_paired_nt<T, 2, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
+        else
+          launch_paired_nt<T, 2, 2>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
       }
     } else if (wc <= 64) {
       launch_form<T, 1, 1>(A, Yin, Z, Yout, wc, c0, al, be, ga, partial, w, groups, colss, s);
