@@ -399,7 +399,12 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     double t = now();
     // ---- subspace update: MPM on A - aI over [0, b - a] ----
     Blk<T> X = B.Z(0, wp_);
-    Blk<T> Ya = B.U(0, wp_), Yb = B.U(wp_, wp_);
+    // the filter's ping-pong pair: two compact n x ldc blocks in U when they
+    // fit (rows of ldc values stream faster than rows strided by ldz)
+    const int64_t ldc = round_up((int64_t)wp_, 8);
+    const bool compact = 2 * ldc <= B.ldz;
+    Blk<T> Ya = compact ? Blk<T>{B.Ub.template as<T>(), ldc, wp_} : B.U(0, wp_);
+    Blk<T> Yb = compact ? Blk<T>{B.Ub.template as<T>() + n * ldc, ldc, wp_} : B.U(wp_, wp_);
     const Blk<const T> Qc{B.Qb.template as<T>(), B.ldq, nc_};
     const FilterPoly &g = coeffs(d_);
     double rc = std::numeric_limits<double>::infinity();
