@@ -89,7 +89,8 @@ typedef struct {
  * 2P rows are processed together and each row's entry in the other's column
  * is served from registers instead of a gather; chosen only when every row
  * then has at most three far entries besides that one. ARR_ROW_AUTO takes the
- * paired form where it applies. Both forms compute the same product. */
+ * paired form where it applies. Both forms compute the same product (the
+ * filter SpMM of Algorithm 7's loop body), up to the order of the sums. */
 typedef enum { ARR_ROW_AUTO = 0, ARR_ROW_PLAIN = 1 } arr_row_form_t;
 
 /* The row form the SpMM kernels use for a host CSR (same checks as
