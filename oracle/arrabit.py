@@ -410,12 +410,13 @@ def arrabit_mpm(A: sp.spmatrix, k: int, tol: float, X0: np.ndarray, which: str =
         rnorm = residual_norms(B, Xw, mu)
         res = rnorm / np.maximum(1.0, np.abs(mu))
         maxres = float(res[:k].max())
-        history.append(dict(outer=j, maxres=maxres, d=d, p=p, n_conv=int(Qc.shape[1]),
-                            tol_t=tol_t, a=a, b=b, width=int(X.shape[1])))
         if maxres < best_maxres:
             best_maxres, best_mu, since_best = maxres, (mu[k - 1], mu[w - 1]), 0
         else:
             since_best += 1
+        history.append(dict(outer=j, maxres=maxres, d=d, p=p, n_conv=int(Qc.shape[1]),
+                            tol_t=tol_t, a=a, b=b, width=int(X.shape[1]), res=res.copy(),
+                            mu=mu.copy(), since_best=since_best))
         if maxres <= tol:
             status = 0
             break
@@ -435,6 +436,7 @@ def arrabit_mpm(A: sp.spmatrix, k: int, tol: float, X0: np.ndarray, which: str =
         # deflation (eq. defl): converged pairs are re-collected from the merged set
         tol_d = max(1e-14, tol_t ** 2)
         conv = res <= tol_d
+        history[-1].update(locked=conv.copy(), tol_t_next=tol_t, b_next=b)
         Qc, sig_c, res_c = Xw[:, conv], mu[conv], res[conv]
         X = Xw[:, ~conv]
         # augmentation blocks (eq. block). Reading: ratio of shifted values
