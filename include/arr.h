@@ -19,7 +19,15 @@
  *    pairs are still retrievable; negative values are errors, with a message
  *    available from arr_last_error (handle API) or arr_last_global_error.
  *  - Dense blocks are ROW-MAJOR: element (i, j) of an n x w block with leading
- *    dimension ld (>= w) is at p[i*ld + j].
+ *    dimension ld (>= w) is at p[i*ld + j]. This is the one layout of the
+ *    library, for device blocks and for the eigenvectors arr_get_eigpairs
+ *    returns alike (eigenvector j is column j, entry i at evecs[i*ldv + j]):
+ *    a row of the block is what one SpMM gather reads, so results leave the
+ *    device without a transpose.
+ *  - Residual scalings: the stop rules use eq. resi, ||r||_2 / max(1,
+ *    |lambda|); arr_get_residuals also returns ||r||_2 / ||A||_2 (with the
+ *    Lanczos estimate of ||A||_2) and ||r||_2. When ||A||_2 >= 1 the first
+ *    bounds the second.
  *  - CSR matrices are 0-based with int64 row pointers and int32 column
  *    indices; both triangles are stored (A must be symmetric), duplicates are
  *    not allowed.
@@ -137,6 +145,10 @@ typedef struct {
   int32_t inner_solver;  /* arr_inner_t, default ARR_INNER_MPM                              */
   int32_t poly_form;     /* arr_poly_form_t, default ARR_POLY_PRODUCT                       */
   int32_t row_form;      /* arr_row_form_t, default ARR_ROW_AUTO                            */
+  /* Test hook for the non-finite guard, 0 (off) by default: n > 0 writes a
+   * NaN into the iterate right after the n-th filter application of the
+   * solve; n < 0 does so after every application from the |n|-th on. */
+  int32_t debug_nan_poly;
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -189,6 +201,15 @@ typedef struct {
    * offset of the matrix), 16 = paired form with one far entry per row
    * (otherwise three) */
   int32_t spmm_flags, spmm32_flags;
+  /* inner loops restarted by the non-finite guard: a filtered block with a
+   * NaN or Inf column norm is restored to the start of the outer iteration's
+   * filter stage, renormalized, and filtered again at half the degree (once
+   * per outer iteration; a second failure ends the solve with
+   * ARR_EBREAKDOWN) */
+  int32_t nan_retries;
+  /* max over the k returned pairs of the explicit FP64 residual, in the eq.
+   * resi scaling and as ||A x - lambda x||_2 / ||A||_2 with norm_est */
+  double maxres_explicit, maxres_norm_a;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;
@@ -224,10 +245,22 @@ int arr_solve(arr_handle_t h);
 
 /* Copy results to caller-owned host buffers (any pointer may be NULL):
  * evals [k] (descending for LARGEST, ascending for SMALLEST), evecs n x k
- * row-major with leading dimension ldv >= k (unit columns, sign chosen so the
- * entry of largest magnitude is positive), resid [k] = ||A x - lambda x||_2 /
- * max(1, |lambda|) (eq. resi). */
+ * ROW-MAJOR with leading dimension ldv >= k (column j is eigenvector j; unit
+ * columns, sign chosen so the entry of largest magnitude is positive; the
+ * library's one layout for blocks, see the conventions above), resid [k] =
+ * ||A x - lambda x||_2 / max(1, |lambda|) (eq. resi, the scaling of the stop
+ * rule eq. out-stop). Residuals are recomputed for the returned vectors with
+ * an explicit FP64 SpMM; ARR_OK is returned by arr_solve only if every one of
+ * them meets the accepting rule (tol, or (1 + 9h/k) tol under rule (iii)). */
 int arr_get_eigpairs(arr_handle_t h, double *evals, double *evecs, int64_t ldv, double *resid);
+
+/* The residuals of the returned pairs in every scaling (host buffers of k
+ * values, any may be NULL): resid = ||r||_2 / max(1, |lambda|) (eq. resi),
+ * resid_norm_a = ||r||_2 / ||A||_2 with ||A||_2 estimated by the extreme
+ * Lanczos Ritz values of the interval setup (a lower bound of ||A||_2, so
+ * this is an upper bound of the exact scaled residual), rnorm = ||r||_2,
+ * r = A x - lambda x. ARR_ESTATE before a solve. */
+int arr_get_residuals(arr_handle_t h, double *resid, double *resid_norm_a, double *rnorm);
 
 int arr_get_stats(arr_handle_t h, arr_stats_t *s);
 const char *arr_last_error(arr_handle_t h);

@@ -50,7 +50,8 @@ class arr_csr_t(ctypes.Structure):
 class arr_dev_csr_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
                 ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32),
-                ("row_form", ctypes.c_int32)]
+                ("row_form", ctypes.c_int32),
+                ("debug_nan_poly", ctypes.c_int32)]
 
 
 class arr_options_t(ctypes.Structure):
@@ -63,7 +64,8 @@ class arr_options_t(ctypes.Structure):
                 ("keep_vectors", ctypes.c_int32),
                 ("inner_solver", ctypes.c_int32),
                 ("poly_form", ctypes.c_int32),
-                ("row_form", ctypes.c_int32)]
+                ("row_form", ctypes.c_int32),
+                ("debug_nan_poly", ctypes.c_int32)]
 
 
 class arr_server_opts_t(ctypes.Structure):
@@ -89,11 +91,13 @@ class arr_stats_t(ctypes.Structure):
                 ("upd32_ms", ctypes.c_double), ("upd32_flops", ctypes.c_double),
                 ("spmm32_launches", ctypes.c_int64), ("spmm32_ms", ctypes.c_double), ("spmm32_bytes", ctypes.c_double),
                 ("spmm32_cols_per_lane", ctypes.c_int32), ("spmm32_vec", ctypes.c_int32),
-                ("fp32_maxres", ctypes.c_double), ("spmm_flags", ctypes.c_int32), ("spmm32_flags", ctypes.c_int32)]
+                ("fp32_maxres", ctypes.c_double), ("spmm_flags", ctypes.c_int32), ("spmm32_flags", ctypes.c_int32),
+                ("nan_retries", ctypes.c_int32), ("maxres_explicit", ctypes.c_double),
+                ("maxres_norm_a", ctypes.c_double)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
-           "arr_get_eigpairs", "arr_get_stats", "arr_last_error", "arr_last_global_error", "arr_destroy",
+           "arr_get_eigpairs", "arr_get_residuals", "arr_get_stats", "arr_last_error", "arr_last_global_error", "arr_destroy",
            "arr_filter_step", "arr_poly", "arr_filter", "arr_filter_roots", "arr_gn_step",
            "arr_filter_coefficients", "arr_gram", "arr_block_update",
            "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
@@ -121,6 +125,7 @@ def lib() -> ctypes.CDLL:
     L.arr_set_initial_block.argtypes = [vp, vp, i64]
     L.arr_solve.argtypes = [vp]
     L.arr_get_eigpairs.argtypes = [vp, vp, vp, i64, vp]
+    L.arr_get_residuals.argtypes = [vp, vp, vp, vp]
     L.arr_get_stats.argtypes = [vp, P(arr_stats_t)]
     L.arr_last_error.argtypes = [vp]
     L.arr_last_error.restype = ctypes.c_char_p
@@ -239,6 +244,14 @@ def arr_get_eigpairs(h: Handle, k: int, n: int, vectors: bool = True):
     _check(lib().arr_get_eigpairs(h.ptr, ev.ctypes.data, X.ctypes.data if vectors else None, k, res.ctypes.data),
            h.ptr)
     return ev, X, res
+
+
+def arr_get_residuals(h: Handle, k: int):
+    """(resid, resid_norm_a, rnorm): ||r|| / max(1, |lambda|) (eq. resi),
+    ||r|| / ||A||_2 (Lanczos estimate) and ||r||, each k values."""
+    out = [np.zeros(k) for _ in range(3)]
+    _check(lib().arr_get_residuals(h.ptr, *(o.ctypes.data for o in out)), h.ptr)
+    return tuple(out)
 
 
 def arr_get_stats(h: Handle) -> dict:

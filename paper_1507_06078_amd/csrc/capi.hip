@@ -205,6 +205,18 @@ int arr_get_eigpairs(arr_handle_t h, double *evals, double *evecs, int64_t ldv, 
   });
 }
 
+int arr_get_residuals(arr_handle_t h, double *resid, double *resid_norm_a, double *rnorm) {
+  if (!h) return ARR_EINVAL;
+  if (!h->s->solved) {
+    h->err = "arr_get_residuals called before arr_solve";
+    return ARR_ESTATE;
+  }
+  return guarded(&h->err, [&]() {
+    h->s->get_residuals(resid, resid_norm_a, rnorm);
+    return ARR_OK;
+  });
+}
+
 int arr_get_stats(arr_handle_t h, arr_stats_t *s) {
   if (!h || !s) return ARR_EINVAL;
   *s = h->s->stats;

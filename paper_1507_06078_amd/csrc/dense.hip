@@ -685,10 +685,15 @@ void Jacobi::solve(int m, const double *H, double *V, std::vector<double> &evals
   double hn[2];
   ARR_HIP(hipMemcpyAsync(hn, nrm, sizeof(hn), hipMemcpyDeviceToHost, s));
   ARR_HIP(hipStreamSynchronize(s));
-  const double tiny = std::max(1e-300, 1e-18 * hn[1]);
+  // A rotation is skipped when |a_pq| <= eps |H|_F (a perturbation within
+  // the rounding of H itself) or <= eps sqrt(|a_pp a_qq|). Without the
+  // absolute bound, clusters of zero eigenvalues keep rotating on
+  // rounding-level entries and never meet the relative one.
+  const double tiny = std::max(1e-300, 2.2e-16 * hn[1]);
   const int nchunk = (me + 63) / 64;
+  constexpr int kMaxSweeps = 40;
   int sweeps = 0;
-  for (; sweeps < 40; ++sweeps) {
+  for (; sweeps < kMaxSweeps; ++sweeps) {
     launch_fill<int>(flag, 1, 0, s);
     const int steps = nb > 1 ? nb - 1 : 1;
     for (int st = 0; st < steps; ++st) {
@@ -703,6 +708,12 @@ void Jacobi::solve(int m, const double *H, double *V, std::vector<double> &evals
     if (!hf) break;
   }
   if (sweeps_out) *sweeps_out = sweeps;
+  // every sweep so far still rotated some pair: the off-diagonal part has not
+  // fallen below the threshold (cyclic Jacobi converges quadratically, so this
+  // points at non-finite or badly scaled input)
+  if (sweeps == kMaxSweeps)
+    throw Error(-5, "small eigensolve: Jacobi did not converge in " + std::to_string(kMaxSweeps) +
+                        " sweeps (order " + std::to_string(m) + ")");
   hipLaunchKernelGGL(k_jacobi_diag, dim3((me + 255) / 256), dim3(256), 0, s, me, A, bufEval.as<double>());
   ARR_HIP(hipGetLastError());
   std::vector<double> d(me);

@@ -50,6 +50,7 @@ class Solver {
   void set_initial_block(const double *X0, int64_t ld);
   int solve();
   void get(double *evals, double *evecs, int64_t ldv, double *resid);
+  void get_residuals(double *resid, double *resid_norm_a, double *rnorm);
   // Device bytes ensure_device() allocates (every buffer of a solve).
   size_t footprint() const { return const_cast<Solver *>(this)->device_plan(false); }
   void ensure_device();
@@ -96,15 +97,18 @@ class Solver {
   std::vector<double> sig_c_, res_c_;
   double best_maxres_ = 0, maxresp_ = -1, best_mu_k_ = 0, best_mu_w_ = 0;
   int since_best_ = 0;
-  std::vector<double> out_vals_, out_res_;
+  std::vector<double> out_vals_, out_res_, out_rn_;
+  int poly_count_ = 0;  // filter applications so far (for the debug_nan_poly hook)
 
   const FilterPoly &coeffs(int d);
   void setup_interval();
   template <typename T>
   int outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage);
   template <typename T>
-  void finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src, const std::vector<int64_t> &lds,
-              const std::vector<int32_t> &cols, const std::vector<double> &mu);
+  double finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src, const std::vector<int64_t> &lds,
+                const std::vector<int32_t> &cols, const std::vector<double> &mu);
+  template <typename T>
+  void poly_hook(Blk<T> X);
   template <typename T>
   void gather(int64_t n, int w, T *dst, int64_t lddst, const std::vector<const T *> &src,
               const std::vector<int64_t> &lds, const std::vector<int32_t> &cols);

@@ -353,10 +353,12 @@ void Solver::gather(int64_t n, int w, T *dst, int64_t lddst, const std::vector<c
 }
 
 // Final output: the k leading merged pairs, re-checked with an explicit FP64
-// SpMM (eq. resi scaling).
+// SpMM. Returns the largest of their residuals in the eq. resi scaling. Uses
+// only outv_ and the FP64 W block, which no later step of an outer iteration
+// reads before writing, so the iteration may continue after it.
 template <typename T>
-void Solver::finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src,
-                    const std::vector<int64_t> &lds, const std::vector<int32_t> &cols, const std::vector<double> &mu) {
+double Solver::finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src,
+                      const std::vector<int64_t> &lds, const std::vector<int32_t> &cols, const std::vector<double> &mu) {
   (void)A;
   const int64_t n = n_;
   const int k = k_;
@@ -371,7 +373,7 @@ void Solver::finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T 
   }
   // explicit FP64 residuals
   Blk<double> X{outv_.as<double>(), k, k};
-  Blk<double> AX = B64_.U(0, k);
+  Blk<double> AX = B64_.W(0, k);
   const Blk<const double> none{nullptr, 0, 0};
   launch_filter_spmm<double>(A64_, Blk<const double>{X.p, X.ld, k}, none, AX, 1.0, 0.0, 0.0, nullptr, s_);
   ARR_HIP(hipMemcpyAsync(mu_.p, mu.data(), sizeof(double) * k, hipMemcpyHostToDevice, s_));
@@ -379,9 +381,33 @@ void Solver::finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T 
                                                   Blk<const double>{X.p, X.ld, k}, mu_.as<double>(), wk_, s_);
   out_vals_.assign(mu.begin(), mu.begin() + k);
   out_res_.resize(k);
-  for (int i = 0; i < k; ++i) out_res_[i] = rn[i] / std::max(1.0, std::fabs(mu[i]));
+  out_rn_.assign(rn.begin(), rn.begin() + k);
+  double worst = 0.0, worst_a = 0.0;
+  for (int i = 0; i < k; ++i) {
+    out_res_[i] = rn[i] / std::max(1.0, std::fabs(mu[i]));
+    worst = std::max(worst, out_res_[i]);
+    worst_a = std::max(worst_a, rn[i] / norm_);
+    if (!(out_res_[i] == out_res_[i])) worst = worst_a = std::numeric_limits<double>::infinity();
+  }
+  stats.maxres_explicit = worst;
+  stats.maxres_norm_a = worst_a;
   if (which_ == ARR_SMALLEST_ALGEBRAIC)
     for (double &v : out_vals_) v = -v;
+  return worst;
+}
+
+// Test hook of the non-finite guard: a NaN written into X(0, 0) after the
+// filter application chosen by debug_nan_poly.
+template <typename T>
+void Solver::poly_hook(Blk<T> X) {
+  ++poly_count_;
+  const int at = o_.debug_nan_poly;
+  if (at == 0 || X.w == 0) return;
+  if ((at > 0 && poly_count_ == at) || (at < 0 && poly_count_ >= -at)) {
+    const T nan = std::numeric_limits<T>::quiet_NaN();
+    ARR_HIP(hipMemcpyAsync(X.p, &nan, sizeof(T), hipMemcpyHostToDevice, s_));
+    ARR_HIP(hipStreamSynchronize(s_));
+  }
 }
 
 // Outer iterations of Algorithm 8 in block precision T. Returns a status
@@ -406,9 +432,17 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     Blk<T> Ya = compact ? Blk<T>{B.Ub.template as<T>(), ldc, wp_} : B.U(0, wp_);
     Blk<T> Yb = compact ? Blk<T>{B.Ub.template as<T>() + n * ldc, ldc, wp_} : B.U(wp_, wp_);
     const Blk<const T> Qc{B.Qb.template as<T>(), B.ldq, nc_};
+    wk_.ensure_cols(n, wp_);
+    // Non-finite guard: the MPM iterate is kept in W (free until the
+    // Rayleigh-Ritz step) at the start of the filter stage. A check that finds
+    // a NaN or Inf column norm restores it, renormalizes and restarts the
+    // inner loop at half the degree, once per outer iteration.
+    const bool mpm = o_.inner_solver != ARR_INNER_GN;
+    if (mpm) launch_copy<T>(n, wp_, B.W(0, wp_).p, B.ldz, X.p, X.ld, s_);
+    int retries = 0;
+  restart_inner:
     const FilterPoly &g = coeffs(d_);
     double rc = std::numeric_limits<double>::infinity();
-    wk_.ensure_cols(n, wp_);
     for (int i1 = 0; i1 < o_.maxit1; ++i1) {
       // MPM with Qc empty: X's column normalization is deferred into the last
       // launch of the next filter (the filter is linear in X) and applied on
@@ -418,12 +452,14 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
         if (o_.inner_solver == ARR_INNER_GN) {
           // GN branch: no normalization; Y in Z's second segment, rho(A) Y in W
           gn_step<T>(A, X, B.Z(wp_, wp_), B.W(0, wp_), Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, s_);
+          poly_hook<T>(X);
           if (nc_) project_out<T>(n, Qc, X, wk_, s_);
         } else {
           // MPM: normalize the columns, then X - Qc (Qc^T X); the scaling rides
           // in the projection's update when Qc is not empty
           poly_apply<T>(A, X, Ya, Yb, a_, 0.0, b_ - a_, g, o_.poly_form, wk_, true, s_,
                         pending ? wk_.colv.as<double>() : nullptr);
+          poly_hook<T>(X);
           if (nc_) {
             normalize_and_project<T>(n, Qc, X, wk_, s_);
           } else {
@@ -438,6 +474,25 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       if (pending) launch_scale_columns<T>(n, X, wk_.colv.as<double>(), true, s_);
       const double rcp = rc;
       rc = rcond_gram<T>(n, Blk<const T>{X.p, X.ld, wp_}, wk_, s_);
+      // the last filter application's column norms (MPM) or the Gram (GN)
+      bool finite = std::isfinite(rc);
+      if (mpm && finite) {
+        std::vector<double> cs(wp_);
+        ARR_HIP(hipMemcpy(cs.data(), wk_.colv.as<double>(), sizeof(double) * wp_, hipMemcpyDeviceToHost));
+        for (double v : cs) finite = finite && std::isfinite(v);
+      }
+      if (!finite) {
+        if (!mpm || retries > 0)
+          throw Error(ARR_EBREAKDOWN, "non-finite values in the filtered block (outer iteration " +
+                                          std::to_string(j_) + ", degree " + std::to_string(d_) + ")");
+        ++retries;
+        stats.nan_retries += 1;
+        d_ = std::max(1, d_ / 2);
+        launch_copy<T>(n, wp_, X.p, X.ld, B.W(0, wp_).p, B.ldz, s_);
+        normalize<T>(n, X, wk_, s_);
+        if (nc_) project_out<T>(n, Qc, X, wk_, s_);
+        goto restart_inner;
+      }
       const double thr = fp32_stage ? std::max(tol_t_, 1e-6) : tol_t_;
       if (rc <= thr || rc / rcp > 0.99) break;
     }
@@ -529,18 +584,25 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       ++since_best_;
     }
     int status = -1;
+    double accept = tol_;  // bound the explicit residuals must meet for ARR_OK
     if (!fp32_stage) {
       if (maxres <= tol_) status = ARR_OK;
       if (status < 0 && o_.paper_faithful) {
         int h = 0;
         for (int q = 0; q < k; ++q) h += res[q] < 0.1 * tol_;
-        if (maxres < (1.0 + 9.0 * h / k) * tol_) status = ARR_OK;
+        accept = (1.0 + 9.0 * h / k) * tol_;
+        if (maxres < accept) status = ARR_OK;
       }
       if (status < 0 && since_best_ >= 3) status = ARR_STAGNATED;
       if (status < 0 && j_ == o_.maxit) status = ARR_NOT_CONVERGED;
     }
     if (status >= 0) {
-      finish<T>(B, A, src, lds, cols, mu);
+      const double explicit_max = finish<T>(B, A, src, lds, cols, mu);
+      // an accepted result must also pass the explicit FP64 check; if it does
+      // not, iterate on (or report the result as not converged at maxit)
+      if (status == ARR_OK && !(explicit_max <= accept)) status = j_ < o_.maxit ? -1 : ARR_NOT_CONVERGED;
+    }
+    if (status >= 0) {
       stats.final_p = p_;
       stats.final_d = d_;
       stats.n_locked = nc_;
@@ -592,11 +654,11 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       std::vector<int64_t> l2;
       std::vector<int32_t> c2;
       for (int q = 0; q < nc_; ++q) { s2.push_back(B.Qb.template as<T>()); l2.push_back(B.ldq); c2.push_back(q); }
-      finish<T>(B, A, s2, l2, c2, sig_c_);
+      const double explicit_max = finish<T>(B, A, s2, l2, c2, sig_c_);
       stats.final_p = p_;
       stats.final_d = d_;
       stats.n_locked = nc_;
-      return maxres <= tol_ ? ARR_OK : ARR_NOT_CONVERGED;
+      return (maxres <= tol_ && explicit_max <= tol_) ? ARR_OK : ARR_NOT_CONVERGED;
     }
     if (fp32_stage) {
       ++fp32_iters;
@@ -640,6 +702,7 @@ int Solver::solve() {
   d_ = o_.d0;
   p_ = o_.p0;
   j_ = 0;
+  poly_count_ = 0;
   nc_ = 0;
   wp_ = w_;
   sig_c_.clear();
@@ -713,6 +776,15 @@ int Solver::solve() {
   stats.norm_est = norm_;
   solved = true;
   return status;
+}
+
+void Solver::get_residuals(double *resid, double *resid_norm_a, double *rnorm) {
+  ARR_REQUIRE(solved, "arr_get_residuals called before a successful arr_solve");
+  for (int i = 0; i < k_; ++i) {
+    if (resid) resid[i] = out_res_[i];
+    if (resid_norm_a) resid_norm_a[i] = out_rn_[i] / norm_;
+    if (rnorm) rnorm[i] = out_rn_[i];
+  }
 }
 
 void Solver::get(double *evals, double *evecs, int64_t ldv, double *resid) {

@@ -157,3 +157,36 @@ def test_options_reject_unknown_filter_form_and_inner_solver():
         with pytest.raises(arr.ArrError) as e:
             arr.arr_create(A, A.n, 4, arr.SMALLEST, 1e-8, o)
         assert e.value.code == arr.ARR_EINVAL
+
+
+def test_results_before_solve_are_refused():
+    """arr_get_eigpairs and arr_get_residuals on a handle that has not been
+    solved return ARR_ESTATE (host-side state check, no device touched)."""
+    A = W.laplacian_2d(8)
+    o = arr.arr_options_default()
+    o.w = 6
+    assert o.debug_nan_poly == 0
+    h = arr.arr_create(A, A.n, 4, arr.SMALLEST, 1e-8, o)
+    L = arr.lib()
+    buf = np.zeros(4)
+    assert L.arr_get_residuals(h.ptr, buf.ctypes.data, None, None) == arr.ARR_ESTATE
+    assert L.arr_get_eigpairs(h.ptr, buf.ctypes.data, None, 4, None) == arr.ARR_ESTATE
+    h.close()
+
+
+def test_stats_struct_matches_header():
+    """The binding's arr_stats_t and arr_options_t list every field of the
+    header's structs, in order."""
+    text = open(os.path.join(ROOT, "include", "arr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    for cname, pyt in (("arr_stats_t", arr.arr_stats_t), ("arr_options_t", arr.arr_options_t)):
+        head = re.search(r"\}\s*" + cname + ";", text)
+        body = text[:head.start()].rsplit("typedef struct {", 1)[1]
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            parts = decl.split(None, 1)[1]
+            names += [x.strip().lstrip("*") for x in parts.split(",")]
+        assert names == [f for f, _ in pyt._fields_], cname

@@ -506,6 +506,19 @@ def test_syev_random(m):
     _check_syev(Hm)
 
 
+@pytest.mark.parametrize("m", [720, 960])
+def test_syev_rayleigh_ritz_sized_clustered(m):
+    """Orders the solver reaches on the 1e6-row benchmark (m = (p + 1) w' up
+    to 960), with a spectrum shaped like a Rayleigh-Ritz matrix near
+    convergence: a clustered wanted part (200 values within 1e-3, some
+    repeated to 1e-12), a gap, and a spread tail."""
+    rng = np.random.default_rng(m + 1)
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    lam = np.concatenate([12.5 - 1e-3 * rng.random(180), np.repeat(12.49, 20) + 1e-12 * rng.random(20),
+                          6.0 + 5.0 * rng.random(m - 200)])
+    _check_syev(Q @ np.diag(lam) @ Q.T)
+
+
 def test_syev_degenerate_and_zero():
     rng = np.random.default_rng(4)
     Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))

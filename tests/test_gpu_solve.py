@@ -241,3 +241,101 @@ def test_results_before_solve_is_state_error():
         arr.arr_get_eigpairs(h, k, A.n)
     assert e.value.code == arr.ARR_ESTATE
     h.close()
+
+
+def _lap2d(tol, **kw):
+    A, k, which, w, _ = W.workload("lap2d_40")
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    return A, k, which, w, X0, solve(A, k, which, tol, w=w, X0=X0, **kw)
+
+
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_stop_rule_ii_stagnation_status(precision):
+    """Stop rule (ii) of Sec. 6: at tol = 1e-16, below what FP64 residuals
+    reach, the oracle stagnates (status 2, pinned in test_oracle_sec6.py);
+    the library must return ARR_STAGNATED, with the best pairs still
+    retrievable and accurate."""
+    A, k, which, w, X0, (status, ev, X, res, st) = _lap2d(1e-16, precision=precision)
+    assert status == arr.ARR_STAGNATED, st
+    ref = O.arrabit_mpm(A.to_scipy(), k, 1e-16, X0, which)
+    assert ref.status == 2
+    assert st["outer_iters"] < 30
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    assert np.all(np.abs(ev - exact) <= 1e-12 * np.maximum(1, np.abs(exact)))
+    check_pairs(A, ev, X, 1e-12)
+
+
+def test_stop_rule_iii_paper_faithful_status():
+    """Stop rule (iii) (paper_faithful = 1), tol = 6e-11: the oracle stops in
+    its fourth outer iteration at about 3.5 tol with 16 of 20 pairs below 0.1
+    tol (pinned in test_oracle_sec6.py). The library must stop the same way:
+    ARR_OK with tol < maxres < (1 + 9h/k) tol < 10 tol, explicit residuals
+    within that bound, and fewer outer iterations than without rule (iii)."""
+    tol = 6e-11
+    A, k, which, w, X0, (status, ev, X, res, st) = _lap2d(tol, paper_faithful=1)
+    ref = O.arrabit_mpm(A.to_scipy(), k, tol, X0, which, O.Options(paper_faithful=True))
+    assert ref.status == 0 and ref.history[-1]["maxres"] > tol
+    assert status == arr.ARR_OK, st
+    assert tol < st["maxres"] < 10 * tol
+    h = int((res < 0.1 * tol).sum())
+    assert res.max() < (1.0 + 9.0 * h / k) * tol
+    assert st["outer_iters"] == len(ref.history)
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    assert np.all(np.abs(ev - exact) <= 1e-10 * np.maximum(1, np.abs(exact)))
+    _, _, _, _, _, (status2, _, _, res2, st2) = _lap2d(tol)
+    assert status2 == arr.ARR_OK and res2.max() <= tol
+    assert st2["outer_iters"] > st["outer_iters"]
+
+
+def test_residual_scalings():
+    """arr_get_residuals: eq. resi, ||r|| / ||A||_2 with the Lanczos estimate,
+    and ||r||, recomputed on the CPU from the returned pairs. The estimate is a
+    lower bound of ||A||_2 = 4 + 4 cos(pi/41) and close to it."""
+    A, k, which, w, _ = W.workload("lap2d_40")
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    o = arr.arr_options_default()
+    o.w = w
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-10, o)
+    arr.arr_set_initial_block(h, X0)
+    assert arr.arr_solve(h) == arr.ARR_OK
+    ev, X, res = arr.arr_get_eigpairs(h, k, A.n)
+    r1, r2, rn = arr.arr_get_residuals(h, k)
+    st = arr.arr_get_stats(h)
+    h.close()
+    norm_a = 4.0 + 4.0 * np.cos(np.pi / 41)
+    assert st["norm_est"] <= norm_a * (1 + 1e-14) and st["norm_est"] > norm_a * (1 - 1e-3)
+    rcpu = np.linalg.norm(A.to_scipy() @ X - X * ev[None, :], axis=0)
+    np.testing.assert_array_equal(r1, res)
+    np.testing.assert_allclose(rn, rcpu, rtol=1e-3, atol=1e-15)
+    np.testing.assert_allclose(r1, rn / np.maximum(1.0, np.abs(ev)), rtol=1e-14)
+    np.testing.assert_allclose(r2, rn / st["norm_est"], rtol=1e-14)
+    assert np.all(r2 <= r1)  # ||A||_2 >= max(1, |lambda|) here
+    assert st["maxres_explicit"] == r1.max() and st["maxres_norm_a"] == pytest.approx(r2.max(), rel=1e-14)
+
+
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_nonfinite_guard_recovers_once(precision):
+    """A NaN written into the iterate after the third filter application (the
+    debug_nan_poly hook) is caught at the next inner stop check: the iterate is
+    restored, the degree halved and the inner loop redone; the solve still
+    converges to the closed-form spectrum."""
+    A, k, which, w, X0, (status, ev, X, res, st) = _lap2d(1e-10, precision=precision, debug_nan_poly=3)
+    assert status == arr.ARR_OK, st
+    assert st["nan_retries"] == 1
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    assert np.all(np.abs(ev - exact) <= 1e-10 * np.maximum(1, np.abs(exact)))
+    check_pairs(A, ev, X, 1e-10)
+
+
+def test_nonfinite_guard_gives_up_with_breakdown():
+    """NaNs after every filter application: the one retry fails as well and
+    the solve ends with ARR_EBREAKDOWN and a message."""
+    A, k, which, w, _ = W.workload("lap2d_40")
+    o = arr.arr_options_default()
+    o.w = w
+    o.debug_nan_poly = -1
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-10, o)
+    with pytest.raises(arr.ArrError) as e:
+        arr.arr_solve(h)
+    h.close()
+    assert e.value.code == arr.ARR_EBREAKDOWN and "non-finite" in str(e.value)
