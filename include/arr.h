@@ -365,6 +365,22 @@ int arr_filter_coefficients(int32_t d, double *out);
 int arr_gram(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, const void *Y,
              int64_t ldy, int32_t my, double *G, void *stream);
 
+/* arr_gram without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same product G = X^T Y with the same arguments, but
+ * its split partial tiles live in a fixed 32 MiB device array of the library
+ * (2^22 doubles, one per device, held until the process ends) instead of a
+ * buffer allocated per call. Calls no hipMalloc/hipFree and does not
+ * synchronize: the work is enqueued on `stream` and G is ready when the
+ * stream reaches it. Every partial the reduction reads is written by the same
+ * call, so nothing needs clearing between calls. Requires mx * my <= 2^22
+ * (ARR_EINVAL otherwise, before anything is launched); larger products take
+ * fewer split partials than arr_gram, so the two agree to rounding, not
+ * bitwise. Calls that overlap on one device (several streams or host
+ * threads) share the array and race: serialize them. */
+int arr_gram_noalloc(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, const void *Y,
+                     int64_t ldy, int32_t my, double *G, void *stream);
+
 /* Block update Y = beta * Y + alpha * X W with X device n x m (ldx, dtype),
  * W device FP64 m x c row-major (ldw), Y device n x c (ldy, dtype). dtype: 0
  * FP64; 1 FP32 data with FP64 products and sums; 2 FP32 data with W rounded to

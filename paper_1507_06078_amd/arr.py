@@ -99,7 +99,7 @@ class arr_stats_t(ctypes.Structure):
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
            "arr_get_eigpairs", "arr_get_residuals", "arr_get_stats", "arr_last_error", "arr_last_global_error", "arr_destroy",
            "arr_filter_step", "arr_poly", "arr_filter", "arr_filter_roots", "arr_gn_step",
-           "arr_filter_coefficients", "arr_gram", "arr_block_update",
+           "arr_filter_coefficients", "arr_gram", "arr_gram_noalloc", "arr_block_update",
            "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
            "arr_server_create", "arr_footprint", "arr_submit", "arr_poll", "arr_wait", "arr_request_times",
            "arr_server_destroy", "arr_row_form"]
@@ -141,6 +141,7 @@ def lib() -> ctypes.CDLL:
     L.arr_filter_coefficients.argtypes = [i32, vp]
     L.arr_row_form.argtypes = [P(arr_csr_t), i32, vp, vp, vp]
     L.arr_gram.argtypes = [i32, i64, vp, i64, i32, vp, i64, i32, vp, vp]
+    L.arr_gram_noalloc.argtypes = [i32, i64, vp, i64, i32, vp, i64, i32, vp, vp]
     L.arr_block_update.argtypes = [i32, i64, i32, i32, f64, vp, i64, vp, i64, f64, vp, i64, vp]
     L.arr_rcond_gram.argtypes = [i32, i64, i32, vp, i64, vp, vp]
     L.arr_orthonormalize.argtypes = [i64, i32, vp, i64, vp]
@@ -392,6 +393,14 @@ def arr_gram(X, Y, G, fp32_cores: bool = False):
     code = 2 if (fp32_cores and _dtype_code(X) == 1) else _dtype_code(X)
     _check(lib().arr_gram(code, int(X.shape[0]), _ptr(X), _ld(X), int(X.shape[1]), _ptr(Y), _ld(Y),
                           int(Y.shape[1]), _ptr(G), _stream()))
+
+
+def arr_gram_noalloc(X, Y, G, fp32_cores: bool = False):
+    """arr_gram through the allocation-free entry point (asynchronous on the
+    current stream)."""
+    code = 2 if (fp32_cores and _dtype_code(X) == 1) else _dtype_code(X)
+    _check(lib().arr_gram_noalloc(code, int(X.shape[0]), _ptr(X), _ld(X), int(X.shape[1]), _ptr(Y), _ld(Y),
+                                  int(Y.shape[1]), _ptr(G), _stream()))
 
 
 def arr_block_update(X, W, Y, alpha: float = 1.0, beta: float = 0.0, fp32_cores: bool = False):

@@ -3,8 +3,16 @@
 // arr_last_global_error.
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "server.h"
+
+// Split-K partial tiles of arr_gram_noalloc: a fixed device array, so that the
+// call allocates nothing. Host code never passes this name to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device (scratch_on_device).
+constexpr int64_t kNoallocScratchDoubles = int64_t(1) << 22;  // 32 MiB on each device
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
 
 struct arr_solver {
   std::unique_ptr<arr::Solver> s;
@@ -100,6 +108,26 @@ std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Device address of `scratch` on the current device, looked up once per device
+// (each device holds its own copy of the array at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+double *scratch_on_device() {
+  int dev = -1;
+  ARR_HIP(hipGetDevice(&dev));
+  ARR_REQUIRE(dev >= 0 && dev < kMaxDevices, "device ordinal out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    ARR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ARR_REQUIRE(p != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -472,6 +500,29 @@ int arr_gram(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, c
                               arr::Blk<const float>{(const float *)Y, ldy, my}, G, work.as<double>(), sym, s,
                               dtype == 2);
     ARR_HIP(hipStreamSynchronize(s));
+    return ARR_OK;
+  });
+}
+
+int arr_gram_noalloc(int32_t dtype, int64_t n, const void *X, int64_t ldx, int32_t mx, const void *Y, int64_t ldy,
+                     int32_t my, double *G, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(X && Y && G && mx >= 0 && my >= 0 && ldx >= mx && ldy >= my && n >= 0, "gram_noalloc: bad arguments");
+    ARR_REQUIRE(dtype >= 0 && dtype <= 2, "gram_noalloc: dtype must be 0, 1 or 2");
+    ARR_REQUIRE((int64_t)mx * my <= kNoallocScratchDoubles,
+                "gram_noalloc: mx * my = " + std::to_string((int64_t)mx * my) + " exceeds the scratch array (" +
+                    std::to_string(kNoallocScratchDoubles) + " doubles); use arr_gram");
+    hipStream_t s = as_stream(stream);
+    double *work = scratch_on_device();
+    const bool sym = (X == Y && ldx == ldy && mx == my);
+    if (dtype == 0)
+      arr::launch_gram<double>(n, arr::Blk<const double>{(const double *)X, ldx, mx},
+                               arr::Blk<const double>{(const double *)Y, ldy, my}, G, work, sym, s, false,
+                               kNoallocScratchDoubles);
+    else
+      arr::launch_gram<float>(n, arr::Blk<const float>{(const float *)X, ldx, mx},
+                              arr::Blk<const float>{(const float *)Y, ldy, my}, G, work, sym, s, dtype == 2,
+                              kNoallocScratchDoubles);
     return ARR_OK;
   });
 }

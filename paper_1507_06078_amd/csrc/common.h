@@ -224,9 +224,11 @@ void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s);
 // known to be symmetric (mx == my): only its upper triangle is computed, then
 // mirrored. fp32_cores (FP32 data only): FP32 matrix cores on 32-row slices,
 // for well-conditioned products; otherwise products and sums are FP64.
+// work_cap > 0: work holds only work_cap doubles; the split count is capped to
+// fit, and a product whose single split does not fit is rejected (ARR_EINVAL).
 template <typename T>
 void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym,
-                 hipStream_t s, bool fp32_cores = false);
+                 hipStream_t s, bool fp32_cores = false, int64_t work_cap = 0);
 size_t gram_work_doubles(int64_t n, int mx, int my);
 // Upper bound of gram_work_doubles over all mx, my <= m_max.
 size_t gram_work_bound(int64_t n, int m_max);

@@ -47,7 +47,7 @@ struct GramPlan {
   int64_t chunk;
 };
 
-GramPlan gram_plan(int64_t n, int mx, int my, bool sym) {
+GramPlan gram_plan(int64_t n, int mx, int my, bool sym, int64_t work_cap = kGramWorkCap) {
   GramPlan p;
   // 128 tiles (4x the work per row of a 64 tile) once both sides reach 128
   p.tile = (mx >= 128 && my >= 128) ? 128 : 64;
@@ -60,7 +60,7 @@ GramPlan gram_plan(int64_t n, int mx, int my, bool sym) {
   const int64_t target = 4 * 512;
   int64_t want = std::max<int64_t>(1, target / p.ntiles);
   // the partial tiles stay within kGramWorkCap doubles (or one product)
-  want = std::min<int64_t>(want, std::max<int64_t>(1, kGramWorkCap / ((int64_t)mx * my)));
+  want = std::min<int64_t>(want, std::max<int64_t>(1, work_cap / ((int64_t)mx * my)));
   // at least 256 rows per split so each wave streams a useful amount
   want = std::min<int64_t>(want, std::max<int64_t>(1, n / 256));
   // whole rounds of the 512 slots once there is more than one
@@ -363,7 +363,7 @@ size_t gram_work_doubles(int64_t n, int mx, int my) {
 
 template <typename T>
 void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *work, bool sym, hipStream_t s,
-                 bool fp32_cores) {
+                 bool fp32_cores, int64_t work_cap) {
   const int mx = X.w, my = Y.w;
   if (mx == 0 || my == 0) return;
   if (sym) ARR_REQUIRE(mx == my, "gram: symmetric product needs equal widths");
@@ -371,7 +371,9 @@ void launch_gram(int64_t n, Blk<const T> X, Blk<const T> Y, double *G, double *w
     launch_fill<double>(G, (int64_t)mx * my, 0.0, s);
     return;
   }
-  const GramPlan p = gram_plan(n, mx, my, sym);
+  const GramPlan p = gram_plan(n, mx, my, sym, work_cap > 0 ? work_cap : kGramWorkCap);
+  if (work_cap > 0)
+    ARR_REQUIRE((int64_t)p.nsplit * mx * my <= work_cap, "gram: split partials exceed the work buffer");
   const dim3 grid(p.ntiles * p.nsplit);
   const bool big = p.tile == 128;
   // algorithmic flops: 2 n mx my, or n m (m + 1) for the upper triangle
@@ -442,9 +444,9 @@ void launch_update(int64_t n, Blk<const T> X, const double *W, int64_t ldw, int 
 }
 
 template void launch_gram<double>(int64_t, Blk<const double>, Blk<const double>, double *, double *, bool,
-                                  hipStream_t, bool);
+                                  hipStream_t, bool, int64_t);
 template void launch_gram<float>(int64_t, Blk<const float>, Blk<const float>, double *, double *, bool,
-                                 hipStream_t, bool);
+                                 hipStream_t, bool, int64_t);
 template void launch_update<double>(int64_t, Blk<const double>, const double *, int64_t, int, double, double,
                                     Blk<double>, hipStream_t, bool, bool, const double *);
 template void launch_update<float>(int64_t, Blk<const float>, const double *, int64_t, int, double, double,
