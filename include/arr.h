@@ -65,7 +65,7 @@ typedef enum { ARR_FP64 = 0, ARR_MIXED = 1 } arr_precision_t;
 
 /* Inner solver of Algorithm 8 (the subspace update between ARR projections):
  * ARR_INNER_MPM, the multi-power method (Sec. 3: filter, then normalize the
- * columns); ARR_INNER_GN, the Gauss-Newton iteration of Sec. 4 with unit step
+ * columns); ARR_INNER_GN, the Gauss-Newton iteration of Sec. 2.6 with unit step
  * (Y = X (X^T X)^{-1}, Z = rho(A) Y, X = Z - X (Y^T Z - I)/2). */
 typedef enum { ARR_INNER_MPM = 0, ARR_INNER_GN = 1 } arr_inner_t;
 
@@ -340,7 +340,7 @@ int arr_filter_roots(int32_t d, double *roots, double *lead);
 int arr_filter(const arr_dev_csr_t *A, int64_t w, void *X, int64_t ld, double shift, double lo, double hi,
                int32_t d, int32_t form, void *stream);
 
-/* One Gauss-Newton inner iteration (Sec. 4 with unit step, the GN branch of
+/* One Gauss-Newton inner iteration (Sec. 2.6 with unit step, the GN branch of
  * Algorithm 8) with rho = poly(A - shift I, ., lo, hi, Gamma_d):
  *   Y = X (X^T X)^{-1},  Z = rho(A) Y,  X <- Z - X (Y^T Z - I) / 2.
  * X is a device block n x w (ld, A's dtype), overwritten; w >= 1. X^T X is

@@ -125,13 +125,13 @@ def shifted(A: sp.spmatrix, a: float) -> Callable[[np.ndarray], np.ndarray]:
 
 
 # --------------------------------------------------------------------------
-# Section 4 (A Gauss-Newton Algorithm) and the GN branch of Algorithm 8
+# Section 2.6 (A Gauss-Newton Algorithm) and the GN branch of Algorithm 8
 # --------------------------------------------------------------------------
 
 
 def gn_update(X: np.ndarray, rho_op: Callable[[np.ndarray], np.ndarray]) -> np.ndarray:
     """One Gauss-Newton iteration with unit step for the least-squares fit of
-    X X^T to rho(A) (the GN algorithm of Sec. 4, as Algorithm 8 calls it):
+    X X^T to rho(A) (the GN algorithm of Sec. 2.6, as Algorithm 8 calls it):
     Y = X (X^T X)^{-1}, Z = rho(A) Y, X+ = Z - X (Y^T Z - I) / 2.
     ``rho_op`` applies rho(A) to a block."""
     G = X.T @ X

@@ -54,7 +54,7 @@ void project_out(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s, c
 // of Q (deflation): one block pass instead of two when Q is not empty.
 template <typename T>
 void normalize_and_project(int64_t n, Blk<const T> Q, Blk<T> X, Work &wk, hipStream_t s);
-// One GN inner iteration (Sec. 4, GN branch of Algorithm 8); Y, Z, Ya, Yb are
+// One GN inner iteration (Sec. 2.6, GN branch of Algorithm 8); Y, Z, Ya, Yb are
 // n x X.w scratch blocks.
 template <typename T>
 void gn_step(const DevCSR<T> &A, Blk<T> X, Blk<T> Y, Blk<T> Z, Blk<T> Ya, Blk<T> Yb, double shift, double lo,

@@ -210,7 +210,7 @@ double rcond_gram(int64_t n, Blk<const T> X, Work &wk, hipStream_t s) {
   return h;
 }
 
-// One GN inner iteration of Algorithm 8 (Sec. 4, unit step) with rho =
+// One GN inner iteration of Algorithm 8 (Sec. 2.6, unit step) with rho =
 // Algorithm 7's poly on A - shift I over [lo, hi]:
 //   Y = X (X^T X)^{-1},  Z = rho(A) Y,  X <- Z - X (Y^T Z - I) / 2.
 // (X^T X)^{-1} = L^{-T} L^{-1} from the FP64 Cholesky factor of the Gram.

@@ -346,7 +346,7 @@ def test_filter_product_fp32_more_accurate_than_horner():
 
 @pytest.mark.parametrize("d", [3, 8, 15])
 def test_gn_step_matches_oracle_fp64(d):
-    """The GN inner iteration of Algorithm 8 (Sec. 4) against the oracle."""
+    """The GN inner iteration of Algorithm 8 (Sec. 2.6) against the oracle."""
     A = W.laplacian_3d(12, potential_seed=1)
     S = -A.to_scipy()
     lam = np.linalg.eigvalsh(S.toarray())

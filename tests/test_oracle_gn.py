@@ -1,8 +1,8 @@
-"""Pins of the oracle's Gauss-Newton inner solver (Sec. 4, GN branch of
+"""Pins of the oracle's Gauss-Newton inner solver (Sec. 2.6, GN branch of
 Algorithm 8), each independent of the oracle's own formula:
 
 * the algorithm's update Z - X (Y^T Z - I)/2 equals the closed-form GN step
-  with unit step printed in Sec. 4, X + (I - X G^{-1} X^T / 2)(M X G^{-1} - X),
+  with unit step printed in Sec. 2.6, X + (I - X G^{-1} X^T / 2)(M X G^{-1} - X),
   G = X^T X (a different algebraic form of the same map);
 * X* = Q_k Lambda_k^{1/2} R (top-k eigenvectors scaled by the square roots of
   the eigenvalues, R orthogonal) is a fixed point, as the minimizer of
