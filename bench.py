@@ -183,11 +183,16 @@ def measured_traffic(kernel):
 
 def spmm_kernel_name(dtype, vec, cols_per_lane, flags):
     """The SpMM kernel instance the solver timed, as rocprofv3 names it:
-    k_filter_spmm<T, VEC, NT, overflow rows, Z operand, column sums>, or for
+    k_filter_spmm<T, VEC, NT, overflow rows, Z operand, column sums>, for
     the paired row form (flag 8) k_filter_spmm_paired<T, VEC, NT, far slots,
-    Z operand, column sums>."""
+    Z operand, column sums>, for the grid form (flag 32)
+    k_filter_spmm_grid<T, VEC, TX, TY, Z operand, column sums> with the 2D
+    tile 64 x 1 (flag 64) or the 3D tile 8 x 8."""
     b = lambda bit: "true" if flags & bit else "false"
     nt = max(1, cols_per_lane // vec)
+    if flags & 32:
+        tx, ty = (64, 1) if flags & 64 else (8, 8)
+        return f"k_filter_spmm_grid<{dtype}, {cols_per_lane}, {tx}, {ty}, {b(1)}, {b(4)}>"
     if flags & 8:
         return f"k_filter_spmm_paired<{dtype}, {vec}, {nt}, {1 if flags & 16 else 3}, {b(1)}, {b(4)}>"
     return f"k_filter_spmm<{dtype}, {vec}, {nt}, {b(2)}, {b(1)}, {b(4)}>"
@@ -208,7 +213,8 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     o.verbose = 1 if args.verbose else 0
     o.inner_solver = arr.INNER_GN if args.inner == "gn" else arr.INNER_MPM
     o.poly_form = {"product": arr.POLY_PRODUCT, "horner": arr.POLY_HORNER, "chebyshev": arr.POLY_CHEBYSHEV}[args.poly]
-    o.row_form = arr.ROW_PLAIN if args.row_form == "plain" else arr.ROW_AUTO
+    o.row_form = {"auto": arr.ROW_AUTO, "plain": arr.ROW_PLAIN, "paired": arr.ROW_PAIRED,
+                  "grid": arr.ROW_GRID}[args.row_form]
     torch.cuda.synchronize()
     tc0 = time.perf_counter()
     h = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, tol, o)
@@ -319,8 +325,9 @@ def main():
     ap.add_argument("--poly", choices=["product", "horner", "chebyshev"], default="product",
                     help="filter: psi_d as a product over its roots (default), psi_d by Algorithm 7's "
                          "recurrence, or the classic Chebyshev polynomial T_d (eq. cheby-poly)")
-    ap.add_argument("--row-form", choices=["auto", "plain"], default="auto",
-                    help="SpMM row form: paired where the matrix allows it (default), or always plain")
+    ap.add_argument("--row-form", choices=["auto", "plain", "paired", "grid"], default="auto",
+                    help="SpMM row form: automatic (grid form for 2D grids, else paired where the matrix "
+                         "allows it), plain, paired (never grid), or grid wherever it applies")
     ap.add_argument("--workload", choices=["lap3d100", "powerlaw2e6"], default="lap3d100",
                     help="lap3d100: the headline workload; powerlaw2e6: the 2e6-row power-law graph")
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")

@@ -96,18 +96,34 @@ typedef struct {
  * operator's neighbour one grid line away), rows i and i + P of each block of
  * 2P rows are processed together and each row's entry in the other's column
  * is served from registers instead of a gather; chosen only when every row
- * then has at most three far entries besides that one. ARR_ROW_AUTO takes the
- * paired form where it applies. Both forms compute the same product (the
- * filter SpMM of Algorithm 7's loop body), up to the order of the sums. */
-typedef enum { ARR_ROW_AUTO = 0, ARR_ROW_PLAIN = 1 } arr_row_form_t;
+ * then has at most three far entries besides that one. Grid: for matrices
+ * whose every entry is a neighbour of its row in a 7-point stencil on a
+ * gx x gy x gz grid, or a 5-point stencil on a gx x gz grid, in lexicographic
+ * order (x fastest; any values, Dirichlet boundary: no entry wraps from one
+ * grid line to the next); a workgroup streams an x-y tile of rows through LDS
+ * plane by plane, so each input row is read about once instead of once per
+ * stencil entry. ARR_ROW_AUTO takes the grid form for 2D (5-point) grids,
+ * else the paired form where it applies (on 3D grids the paired form measured
+ * faster); ARR_ROW_GRID takes the grid form wherever it applies, 3D included,
+ * else falls back as ARR_ROW_AUTO; ARR_ROW_PAIRED never takes the grid form;
+ * ARR_ROW_PLAIN always takes the plain form. All forms compute the same
+ * product (the filter SpMM of Algorithm 7's loop body), up to the order of
+ * the sums. */
+typedef enum { ARR_ROW_AUTO = 0, ARR_ROW_PLAIN = 1, ARR_ROW_PAIRED = 2, ARR_ROW_GRID = 3 } arr_row_form_t;
 
 /* The row form the SpMM kernels use for a host CSR (same checks as
  * arr_create; host only, no device needed): *pair = the pairing offset P (0
- * for the plain form), *far_slots = far entries gathered per row (4 plain; 1
- * or 3 paired), *overflow = entries in the plain form's overflow CSR. Any
- * output pointer may be NULL, and so may csr->val (the form depends on the
- * pattern only). ARR_EINVAL on a malformed CSR or an unknown form. */
+ * for the plain and grid forms), *far_slots = far entries gathered per row (4
+ * plain; 1 or 3 paired; 0 grid), *overflow = entries in the plain form's
+ * overflow CSR. Any output pointer may be NULL, and so may csr->val (the form
+ * depends on the pattern only). ARR_EINVAL on a malformed CSR or an unknown
+ * form. */
 int arr_row_form(const arr_csr_t *csr, int32_t form, int64_t *pair, int32_t *far_slots, int64_t *overflow);
+
+/* Grid dimensions of the grid form for a host CSR: dims[0..2] = (gx, gy, gz)
+ * (gy = 1 for a 5-point 2D grid), or zeros when the form `form` selects is
+ * not the grid form. Host only; same checks and errors as arr_row_form. */
+int arr_row_grid(const arr_csr_t *csr, int32_t form, int64_t *dims);
 
 /* Device CSR description used by the step-level entry points. val is a
  * device array of FP64 (dtype 0) or FP32 (dtype 1) values; column indices

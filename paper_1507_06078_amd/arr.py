@@ -34,6 +34,8 @@ POLY_HORNER = 1
 POLY_CHEBYSHEV = 2
 ROW_AUTO = 0
 ROW_PLAIN = 1
+ROW_PAIRED = 2
+ROW_GRID = 3
 
 
 class ArrError(RuntimeError):
@@ -102,7 +104,7 @@ EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initia
            "arr_filter_coefficients", "arr_gram", "arr_gram_noalloc", "arr_block_update",
            "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
            "arr_server_create", "arr_footprint", "arr_submit", "arr_poll", "arr_wait", "arr_request_times",
-           "arr_server_destroy", "arr_row_form"]
+           "arr_server_destroy", "arr_row_form", "arr_row_grid"]
 
 _lib = None
 
@@ -140,6 +142,7 @@ def lib() -> ctypes.CDLL:
     L.arr_filter_roots.argtypes = [i32, vp, vp]
     L.arr_filter_coefficients.argtypes = [i32, vp]
     L.arr_row_form.argtypes = [P(arr_csr_t), i32, vp, vp, vp]
+    L.arr_row_grid.argtypes = [P(arr_csr_t), i32, vp]
     L.arr_gram.argtypes = [i32, i64, vp, i64, i32, vp, i64, i32, vp, vp]
     L.arr_gram_noalloc.argtypes = [i32, i64, vp, i64, i32, vp, i64, i32, vp, vp]
     L.arr_block_update.argtypes = [i32, i64, i32, i32, f64, vp, i64, vp, i64, f64, vp, i64, vp]
@@ -227,6 +230,16 @@ def arr_row_form(csr, form: int = ROW_AUTO):
                               ctypes.addressof(ovf)))
     del keep
     return pair.value, far.value, ovf.value
+
+
+def arr_row_grid(csr, form: int = ROW_AUTO):
+    """Grid dimensions (gx, gy, gz) of the grid row form for a host CSR, or
+    (0, 0, 0) when the kernels do not use it."""
+    c, keep = _host_csr(csr)
+    dims = np.zeros(3, dtype=np.int64)
+    _check(lib().arr_row_grid(ctypes.byref(c), int(form), dims.ctypes.data))
+    del keep
+    return tuple(int(d) for d in dims)
 
 
 def arr_set_initial_block(h: Handle, X0: np.ndarray) -> None:

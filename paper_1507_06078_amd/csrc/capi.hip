@@ -59,7 +59,8 @@ template <typename T>
 std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
   ARR_REQUIRE(A && A->rowptr && A->n > 0 && A->nnz >= 0, "device CSR is NULL or empty");
   ARR_REQUIRE(A->nnz == 0 || (A->colind && A->val), "device CSR arrays are NULL");
-  ARR_REQUIRE(A->row_form == ARR_ROW_AUTO || A->row_form == ARR_ROW_PLAIN, "unknown row form");
+  ARR_REQUIRE(A->row_form >= ARR_ROW_AUTO && A->row_form <= ARR_ROW_GRID,
+              "unknown row form");
   const int64_t n = A->n, nnz = A->nnz;
   std::vector<int64_t> rp(n + 1);
   std::vector<int32_t> ci(nnz);
@@ -79,14 +80,16 @@ std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
   }
   std::vector<double> v(vt.begin(), vt.end());
   arr::RowSplit sp;
-  arr::split_rows(n, rp.data(), ci.data(), v.data(), sp, A->row_form == ARR_ROW_AUTO);
+  arr::split_rows(n, rp.data(), ci.data(), v.data(), sp, A->row_form);
   std::vector<T> cv(sp.coef.begin(), sp.coef.end()), ov(sp.oval.begin(), sp.oval.end());
   auto d = std::make_unique<SplitDev<T>>();
   const int64_t no = (int64_t)sp.ocol.size();
   d->coef.alloc(sizeof(T) * 8 * n);
-  d->fcol.alloc(sizeof(int32_t) * 4 * n);
   ARR_HIP(hipMemcpy(d->coef.p, cv.data(), sizeof(T) * 8 * n, hipMemcpyHostToDevice));
-  ARR_HIP(hipMemcpy(d->fcol.p, sp.fcol.data(), sizeof(int32_t) * 4 * n, hipMemcpyHostToDevice));
+  if (!sp.gx) {
+    d->fcol.alloc(sizeof(int32_t) * 4 * n);
+    ARR_HIP(hipMemcpy(d->fcol.p, sp.fcol.data(), sizeof(int32_t) * 4 * n, hipMemcpyHostToDevice));
+  }
   if (no) {
     d->orp.alloc(sizeof(int64_t) * (n + 1));
     d->ocol.alloc(sizeof(int32_t) * no);
@@ -103,11 +106,18 @@ std::unique_ptr<SplitDev<T>> dev_split(const arr_dev_csr_t *A) {
                         no ? (const int32_t *)d->ocol.p : nullptr,
                         no ? (const T *)d->oval.p : nullptr,
                         sp.pair,
-                        sp.kf};
+                        sp.kf,
+                        sp.gx,
+                        sp.gy,
+                        sp.gz};
   return d;
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Checks a host CSR (row pointers, column range and order) and splits it into
+// the row form `form` (arr_row_form_t) selects.
+void host_row_split(const arr_csr_t *csr, int32_t form, arr::RowSplit &sp);
 
 // Device address of `scratch` on the current device, looked up once per device
 // (each device holds its own copy of the array at its own address).
@@ -158,9 +168,35 @@ void arr_options_default(arr_options_t *o) {
 
 int arr_row_form(const arr_csr_t *csr, int32_t form, int64_t *pair, int32_t *far_slots, int64_t *overflow) {
   return guarded(nullptr, [&]() {
+    arr::RowSplit sp;
+    host_row_split(csr, form, sp);
+    if (pair) *pair = sp.pair;
+    if (far_slots) *far_slots = sp.kf;
+    if (overflow) *overflow = (int64_t)sp.ocol.size();
+    return ARR_OK;
+  });
+}
+
+int arr_row_grid(const arr_csr_t *csr, int32_t form, int64_t *dims) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(dims != nullptr, "dims is NULL");
+    arr::RowSplit sp;
+    host_row_split(csr, form, sp);
+    dims[0] = sp.gx;
+    dims[1] = sp.gy;
+    dims[2] = sp.gz;
+    return ARR_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+void host_row_split(const arr_csr_t *csr, int32_t form, arr::RowSplit &sp) {
+  {
     ARR_REQUIRE(csr && csr->n > 0 && csr->nnz >= 0 && csr->rowptr, "csr is NULL or empty");
     ARR_REQUIRE(csr->nnz == 0 || csr->colind, "csr arrays are NULL");
-    ARR_REQUIRE(form == ARR_ROW_AUTO || form == ARR_ROW_PLAIN, "unknown row form");
+    ARR_REQUIRE(form >= ARR_ROW_AUTO && form <= ARR_ROW_GRID, "unknown row form");
     const int64_t n = csr->n, *rp = csr->rowptr;
     ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
     for (int64_t i = 0; i < n; ++i) {
@@ -178,14 +214,12 @@ int arr_row_form(const arr_csr_t *csr, int32_t form, int64_t *pair, int32_t *far
       ones.assign((size_t)csr->nnz, 1.0);
       val = ones.data();
     }
-    arr::RowSplit sp;
-    arr::split_rows(n, rp, csr->colind, val, sp, form == ARR_ROW_AUTO);
-    if (pair) *pair = sp.pair;
-    if (far_slots) *far_slots = sp.kf;
-    if (overflow) *overflow = (int64_t)sp.ocol.size();
-    return ARR_OK;
-  });
+    arr::split_rows(n, rp, csr->colind, val, sp, form);
+  }
 }
+}  // namespace
+
+extern "C" {
 
 int arr_create_ex(const arr_csr_t *csr, int64_t n, int32_t k, arr_which_t which, double tol,
                   const arr_options_t *opts, arr_handle_t *out) {

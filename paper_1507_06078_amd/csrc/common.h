@@ -60,6 +60,8 @@ struct DevCSR {
   const T *oval = nullptr;
   int64_t pair = 0;
   int kf = 4;
+  // grid form (gx > 0): see split_rows; fcol and the overflow CSR are unused
+  int64_t gx = 0, gy = 0, gz = 0;
 };
 
 // Host form of the same split (FP64 values); orp is left empty when no row
@@ -72,19 +74,27 @@ struct RowSplit {
   std::vector<double> oval;
   int64_t pair = 0;
   int kf = 4;
+  int64_t gx = 0, gy = 0, gz = 0;
 };
 
 // Rows per run of the paired form (a wave does two runs at once).
 constexpr int64_t kPairRun = 20;
 
-// Host split of a CSR with strictly increasing columns per row. Chooses the
-// paired form when the matrix has a frequent far offset P >= kPairRun (entries
-// A[i][i+P] in at least half of the rows), the runs of kPairRun rows cover a
-// half block of P rows with at most P/8 rows computed twice, and every row
-// then has at most three far entries besides its partner; otherwise the
-// plain form. allow_pair = false forces the plain form.
+// Host split of a CSR with strictly increasing columns per row. form 3 (grid)
+// chooses the grid form when every entry is a neighbour of its row in a
+// 7-point stencil on a gx x gy x gz grid, or a 5-point stencil on a gx x gz
+// grid (gy = 1), lexicographic with x fastest; form 0 (automatic) does so for
+// the 2D case only. In the grid form the record of row i is
+// then {A[i][i - gx gy], A[i][i - gx], A[i][i - 1], A[i][i], A[i][i + 1],
+// A[i][i + gx], A[i][i + gx gy], 0} (zero for a neighbour outside the grid;
+// for gy = 1 the +-gx entries take the first and seventh slots) and fcol is
+// empty. Otherwise, and with form 2 (paired), the paired form when the matrix
+// has a frequent far offset P >= kPairRun (entries A[i][i+P] in at least half
+// of the rows), the runs of kPairRun rows cover a half block of P rows with
+// at most P/8 rows computed twice, and every row then has at most three far
+// entries besides its partner; otherwise, and with form 1, the plain form.
 void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out,
-                bool allow_pair = true);
+                int form = 0);
 
 // A row-major view of columns [0, w) of a device block with leading
 // dimension ld.
@@ -185,12 +195,12 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
 // Installed per thread by the solver. SpMM classes: columns per lane (0..4
 // for 1..16) + 5 for 16-byte loads + 10 for FP64 data + 20 * flags (1 Z term,
 // 2 overflow rows, 4 column sums, 8 paired form, 16 paired with one far slot).
-// GEMM classes: see GemmClass.
+// GEMM classes: see GemmClass. Flag 32 marks the grid form, 64 its 2D tile.
 struct SpmmTimer {
   struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
-  static constexpr int kClasses = 640;
+  static constexpr int kClasses = 2048;
   int64_t launches[kClasses] = {};
   double ms[kClasses] = {}, bytes[kClasses] = {};
   hipEvent_t get();

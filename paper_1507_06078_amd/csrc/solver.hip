@@ -95,7 +95,8 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
   ARR_REQUIRE(o.inner_solver == ARR_INNER_MPM || o.inner_solver == ARR_INNER_GN, "unknown inner solver");
   ARR_REQUIRE(o.poly_form == ARR_POLY_PRODUCT || o.poly_form == ARR_POLY_HORNER || o.poly_form == ARR_POLY_CHEBYSHEV,
               "unknown polynomial form");
-  ARR_REQUIRE(o.row_form == ARR_ROW_AUTO || o.row_form == ARR_ROW_PLAIN, "unknown row form");
+  ARR_REQUIRE(o.row_form >= ARR_ROW_AUTO && o.row_form <= ARR_ROW_GRID,
+              "unknown row form");
   // validate CSR on the host
   const int64_t *rp = csr->rowptr;
   ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
@@ -118,7 +119,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
     }
   }
   // working operator (A, or -A for the smallest end) in the split form
-  split_rows(n, rp, csr->colind, csr->val, h_split_, o.row_form == ARR_ROW_AUTO);
+  split_rows(n, rp, csr->colind, csr->val, h_split_, o.row_form);
   nnz_ = csr->nnz;
   if (which == ARR_SMALLEST_ALGEBRAIC) {
     for (double &x : h_split_.coef) x = -x;
@@ -140,7 +141,7 @@ size_t Solver::device_plan(bool allocate) {
     if (allocate) b.alloc(bytes);
   };
   take(coef64_, sizeof(double) * 8 * n);
-  take(fcol_, sizeof(int32_t) * 4 * n);
+  if (!h_split_.gx) take(fcol_, sizeof(int32_t) * 4 * n);
   if (no) {
     take(orp_, sizeof(int64_t) * (n + 1));
     take(ocol_, sizeof(int32_t) * no);
@@ -178,7 +179,8 @@ void Solver::ensure_device() {
   const int64_t n = n_, no = (int64_t)h_split_.ocol.size();
   const bool mixed = o_.precision == ARR_MIXED;
   ARR_HIP(hipMemcpyAsync(coef64_.p, h_split_.coef.data(), sizeof(double) * 8 * n, hipMemcpyHostToDevice, s_));
-  ARR_HIP(hipMemcpyAsync(fcol_.p, h_split_.fcol.data(), sizeof(int32_t) * 4 * n, hipMemcpyHostToDevice, s_));
+  if (!h_split_.gx)
+    ARR_HIP(hipMemcpyAsync(fcol_.p, h_split_.fcol.data(), sizeof(int32_t) * 4 * n, hipMemcpyHostToDevice, s_));
   if (mixed) launch_convert<float, double>(8 * n, 1, coef32_.as<float>(), 1, coef64_.as<double>(), 1, s_);
   if (no) {
     ARR_HIP(hipMemcpyAsync(orp_.p, h_split_.orp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s_));
@@ -191,10 +193,12 @@ void Solver::ensure_device() {
   const int64_t *orp = no ? orp_.as<int64_t>() : nullptr;
   const int32_t *ocol = no ? ocol_.as<int32_t>() : nullptr;
   A64_ = DevCSR<double>{n, nnz_, coef64_.as<double>(), fcol_.as<int32_t>(), orp, ocol,
-                        no ? oval64_.as<double>() : nullptr, h_split_.pair, h_split_.kf};
+                        no ? oval64_.as<double>() : nullptr, h_split_.pair, h_split_.kf,
+                        h_split_.gx, h_split_.gy, h_split_.gz};
   if (mixed)
     A32_ = DevCSR<float>{n, nnz_, coef32_.as<float>(), fcol_.as<int32_t>(), orp, ocol,
-                         no ? oval32_.as<float>() : nullptr, h_split_.pair, h_split_.kf};
+                         no ? oval32_.as<float>() : nullptr, h_split_.pair, h_split_.kf,
+                         h_split_.gx, h_split_.gy, h_split_.gz};
   B64_.ldz = ldz_;
   B64_.ldq = ldq_;
   B32_.ldz = ldz_;

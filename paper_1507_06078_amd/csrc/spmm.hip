@@ -44,6 +44,7 @@
 //    plain form for a 3D 7-point operator: one window row, four gathers, one
 //    store), and the pairing drops one of the six.
 #include <algorithm>
+#include <climits>
 #include <exception>
 #include <map>
 
@@ -119,6 +120,17 @@ struct BufIO<float, 1> {
   }
   static __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, int off) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+  }
+};
+template <>
+struct BufIO<float, 2> {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ v2 ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(v2 v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          off, 0, 2);
   }
 };
 template <>
@@ -599,6 +611,264 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
   }
 }
 
+// Grid form: the operator of a 7-point stencil on a gx x gy x gz grid in
+// lexicographic order (row i = (z gy + y) gx + x), or of a 5-point stencil on
+// a gx x gz grid (gy = 1). Record of row i: {A[i][i - gx gy], A[i][i - gx],
+// A[i][i - 1], A[i][i], A[i][i + 1], A[i][i + gx], A[i][i + gx gy], 0}, zero
+// for a neighbour outside the grid (for gy = 1 the +-gx entries sit in the
+// first and seventh slots).
+//
+// A workgroup owns an x-y tile of TX x TY grid rows, a column chunk of
+// 64 VEC columns and a segment of z planes, and streams through the segment
+// plane by plane (2.5D blocking). The tile's rows of plane z and their x-y
+// halo sit in LDS; each thread keeps its rows of planes z - 1 and z + 1 in
+// registers. Every Yin row is thus read from memory about once (plus the x-y
+// halo, (2 TX + 2 TY)/(TX TY) of it, mostly an L2 hit for the neighbouring
+// tiles) instead of once per stencil entry: with the store that is about 2.5
+// row accesses per output row through the CU's vector memory path, against 5
+// in the paired form. Wave q takes the tile rows [q R, q R + R), R = TX TY / 4;
+// lane l holds columns [VEC l, VEC l + VEC) of the chunk, so one wave
+// instruction moves one 512-byte row segment.
+//
+// Work items (segment, tile, chunk) are dealt to the XCDs in contiguous
+// ranges: XCD x takes items [x I, x I + I) in order, chunks fastest, so the
+// column chunks of the same rows are read at the same time (whole rows from
+// each DRAM page) and a tile's x-y neighbours usually run on the same XCD at
+// the same time, so its halo rows hit that XCD's L2. Column sums of squares: one partial row per
+// (tile, segment), written for the chunk's columns.
+constexpr int kGridWaves = 8;     // waves per workgroup of the grid form
+constexpr int kGridThreads = 64 * kGridWaves;
+
+template <int TX, int TY>
+struct GridTile {
+  static constexpr bool kHY = TY > 1;                       // y neighbours exist
+  static constexpr int kR = TX * TY / kGridWaves;           // rows per wave
+  static constexpr int kW = TX + 2;                         // LDS slots per tile row
+  static constexpr int kSlots = kW * (TY + (kHY ? 2 : 0));  // tile rows plus x-y halo
+  static constexpr int kHalo = 2 * TY + (kHY ? 2 * TX : 0);
+  static constexpr int kHJ = (kHalo + kGridWaves - 1) / kGridWaves;  // halo rows per wave
+  static_assert(TX * TY % kGridWaves == 0, "tile shape");
+  static __device__ __forceinline__ int slot(int lx, int ly) { return (ly + (kHY ? 1 : 0)) * kW + lx + 1; }
+  // h-th halo row of the tile: left/right columns, then (3D) bottom/top rows
+  static __device__ __forceinline__ void halo(int h, int &lx, int &ly) {
+    if (h < 2 * TY) {
+      ly = h >> 1;
+      lx = (h & 1) ? TX : -1;
+    } else {
+      const int g = h - 2 * TY;
+      lx = g >> 1;
+      ly = (g & 1) ? TY : -1;
+    }
+  }
+};
+
+template <typename T, int VEC, int TX, int TY, bool HASZ, bool SUMS>
+__global__ __launch_bounds__(kGridThreads) void k_filter_spmm_grid(
+    int gx, int gy, int gz, int ntx, int ntile, int nseg, int zlen, int nchunk, int items, int per_xcd,
+    const T *__restrict__ coef, int w, const T *__restrict__ Yin, int64_t ldy, const T *Z, int64_t ldz, T *Yout,
+    int64_t ldo, T alpha, T beta, T gamma, double *__restrict__ partial, int wtot, const double *__restrict__ colss) {
+  typedef typename VecT<T, VEC>::type vec;
+  typedef BufIO<T, VEC> IO;
+  typedef GridTile<TX, TY> G;
+  constexpr int R = G::kR;
+  __shared__ vec L[G::kSlots][64];
+  __shared__ T Kc[TX * TY][8];  // the tile rows' records of the plane in LDS
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // work item of this workgroup: XCD x = blockIdx % 8 owns a contiguous range
+  const int item = (int)(blockIdx.x % kXcd) * per_xcd + (int)(blockIdx.x / kXcd);
+  if (item >= items) return;  // uniform over the workgroup, before any barrier
+  const int chunk = item % nchunk;
+  const int tile = (item / nchunk) % ntile;
+  const int seg = item / (ntile * nchunk);
+  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+  const int z0 = seg * zlen, z1 = min(gz, z0 + zlen);
+  const int c0 = chunk * 64 * VEC;
+  const int wc = min(64 * VEC, w - c0);
+  const bool lane_in = VEC * lane < wc;  // lanes past the chunk neither store nor sum
+  const int64_t plane = (int64_t)gx * gy;
+  const vec zero = vec(0);
+  // Rows are addressed through one buffer resource per plane and block (its
+  // records end with the plane) and a byte offset that depends only on the
+  // row's place in the plane, so a plane step changes one base address.
+  auto in_plane = [&](int lx, int ly) -> int { return (y0 + ly) * gx + x0 + lx; };
+  auto inside = [&](int lx, int ly) { return x0 + lx >= 0 && x0 + lx < gx && y0 + ly >= 0 && y0 + ly < gy; };
+  // A plane's records end with the last element of this chunk in its last
+  // row: lanes past the chunk may read into the next row (never stored), but
+  // nothing past the caller's block.
+  auto plane_rsrc = [&](const T *base, int64_t ld, int z) {
+    return row_rsrc(base + (int64_t)z * plane * ld, (int)(((plane - 1) * ld + c0 + wc) * (int64_t)sizeof(T)));
+  };
+  const int lane_off = (c0 + VEC * lane) * (int)sizeof(T);
+  auto qx = [&](int q) { return (wv * R + q) % TX; };
+  auto qy = [&](int q) { return (wv * R + q) / TX; };
+  uint32_t valid = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) valid |= inside(qx(q), qy(q)) ? (1u << q) : 0u;
+  valid = __builtin_amdgcn_readfirstlane(valid);
+  auto qv = [&](int q) { return (valid >> q) & 1u; };
+  vec cs = vec(1);
+  if constexpr (SUMS) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const int c = c0 + VEC * lane + v;
+      set_elem<VEC>(cs, v, (T)(colss && c < w ? 1.0 / sqrt(colss[c]) : 1.0));
+    }
+  }
+  double ss[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) ss[v] = 0.0;
+
+  // records: thread t loads value t % 8 of tile row t / 8
+  static_assert(TX * TY * 8 == kGridThreads, "one record value per thread");
+  const int kr = threadIdx.x >> 3, kp = threadIdx.x & 7;
+  const bool kin = inside(kr % TX, kr / TX);
+  const int64_t krow = in_plane(kr % TX, kr / TX);
+  auto load_coef = [&](int z, T &kv) { kv = (kin && z < gz) ? coef[8 * (z * plane + krow) + kp] : T(0); };
+
+  auto load_rows = [&](int z, vec *dst) {
+    if (z < 0 || z >= gz) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) dst[q] = zero;
+      return;
+    }
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(Yin, ldy, z);
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      dst[q] = qv(q) ? IO::ld(r, (int)(in_plane(qx(q), qy(q)) * ldy * (int64_t)sizeof(T)) + lane_off) : zero;
+  };
+  auto load_halo = [&](int z, vec *dst) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(Yin, ldy, z);
+#pragma unroll
+    for (int j = 0; j < G::kHJ; ++j) {
+      const int h = wv + kGridWaves * j;
+      int lx = 0, ly = 0;
+      if (h < G::kHalo) G::halo(h, lx, ly);
+      dst[j] = (h < G::kHalo && inside(lx, ly))
+                   ? IO::ld(r, (int)(in_plane(lx, ly) * ldy * (int64_t)sizeof(T)) + lane_off)
+                   : zero;
+    }
+  };
+  auto store_plane = [&](const vec *rows, const vec *hal) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) L[G::slot(qx(q), qy(q))][lane] = rows[q];
+#pragma unroll
+    for (int j = 0; j < G::kHJ; ++j) {
+      const int h = wv + kGridWaves * j;
+      if (h < G::kHalo) {
+        int lx, ly;
+        G::halo(h, lx, ly);
+        L[G::slot(lx, ly)][lane] = hal[j];
+      }
+    }
+  };
+
+  // Four register sets hold this wave's rows of planes z - 1, z, z + 1 and
+  // z + 2 at step z and rotate roles from step to step; two sets of halo
+  // rows and records (planes z + 1 and z + 2) alternate. Loads for plane
+  // z + 2 are issued a whole step before their use, and no register is copied
+  // to another (a copy would wait for its load).
+  vec S0[R], S1[R], S2[R], S3[R], HA[G::kHJ], HB[G::kHJ];
+  T KA, KB;
+  auto step = [&](int z, const vec *Pv, const vec *C, const vec *Nv, vec *N2, const vec *Hn, vec *Hn2, const T &Kn,
+                  T &Kn2) {
+    const bool more = z + 1 < z1;
+    if (more) load_rows(z + 2, N2);
+    if (z + 2 < z1) {
+      load_halo(z + 2, Hn2);
+      load_coef(z + 2, Kn2);
+    }
+    const __amdgpu_buffer_rsrc_t ro = plane_rsrc(Yout, ldo, z);
+    const __amdgpu_buffer_rsrc_t rz = plane_rsrc(HASZ ? Z : Yout, HASZ ? ldz : ldo, z);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (!qv(q)) continue;  // wave-uniform
+      const int lx = qx(q), ly = qy(q);
+      const T *k = Kc[wv * R + q];
+      vec acc = k[3] * C[q];
+      acc += k[2] * L[G::slot(lx - 1, ly)][lane];
+      acc += k[4] * L[G::slot(lx + 1, ly)][lane];
+      if constexpr (G::kHY) {
+        acc += k[1] * L[G::slot(lx, ly - 1)][lane];
+        acc += k[5] * L[G::slot(lx, ly + 1)][lane];
+      }
+      acc += k[0] * Pv[q];
+      acc += k[6] * Nv[q];
+      vec o = alpha * acc;
+      if (beta != T(0)) o += beta * C[q];
+      const int row = in_plane(lx, ly);
+      if constexpr (HASZ) o += gamma * IO::ld(rz, (int)(row * ldz * (int64_t)sizeof(T)) + lane_off);
+      if constexpr (SUMS) o *= cs;
+      if (lane_in) IO::st(o, ro, (int)(row * ldo * (int64_t)sizeof(T)) + lane_off);
+      if constexpr (SUMS) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double ov = lane_in ? lane_elem<VEC>(o, v) : 0.0;
+          ss[v] = fma(ov, ov, ss[v]);
+        }
+      }
+    }
+    if (more) {
+      __syncthreads();  // every wave is done with plane z in LDS
+      store_plane(Nv, Hn);
+      Kc[kr][kp] = Kn;
+      __syncthreads();
+    }
+  };
+
+  // prologue: plane z0 into LDS and S1, z0 - 1 in S0, z0 + 1 in S2 (with its
+  // halo and records in HA, KA)
+  load_rows(z0 - 1, S0);
+  load_rows(z0, S1);
+  load_halo(z0, HA);
+  load_coef(z0, KA);
+  store_plane(S1, HA);
+  Kc[kr][kp] = KA;
+  load_rows(z0 + 1, S2);
+  if (z0 + 1 < z1) {
+    load_halo(z0 + 1, HA);
+    load_coef(z0 + 1, KA);
+  }
+  __syncthreads();
+  for (int z = z0; z < z1; z += 4) {
+    step(z, S0, S1, S2, S3, HA, HB, KA, KB);
+    if (z + 1 < z1) step(z + 1, S1, S2, S3, S0, HB, HA, KB, KA);
+    if (z + 2 < z1) step(z + 2, S2, S3, S0, S1, HA, HB, KA, KB);
+    if (z + 3 < z1) step(z + 3, S3, S0, S1, S2, HB, HA, KB, KA);
+  }
+
+  if constexpr (SUMS) {
+    __syncthreads();  // the plane buffer is reused for the reduction
+    double *red = reinterpret_cast<double *>(&L[0][0]);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) red[wv * 64 * VEC + VEC * lane + v] = ss[v];
+    __syncthreads();
+    for (int c = threadIdx.x; c < wc; c += kGridThreads) {
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGridWaves; ++q) sum += red[q * 64 * VEC + c];
+      partial[(int64_t)(tile * nseg + seg) * wtot + c0 + c] = sum;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_spmv_grid(int64_t n, int64_t gx, int64_t gy, const T *__restrict__ coef,
+                                                   const T *__restrict__ x, T *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T *k = coef + 8 * i;
+  const int64_t plane = gx * gy;
+  T s = k[3] * x[i];
+  if (k[2] != T(0)) s = fma(k[2], x[i - 1], s);
+  if (k[4] != T(0)) s = fma(k[4], x[i + 1], s);
+  if (k[1] != T(0)) s = fma(k[1], x[i - gx], s);
+  if (k[5] != T(0)) s = fma(k[5], x[i + gx], s);
+  if (k[0] != T(0)) s = fma(k[0], x[i - plane], s);
+  if (k[6] != T(0)) s = fma(k[6], x[i + plane], s);
+  y[i] = s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_spmv(int64_t n, int64_t P, const T *__restrict__ coef,
                                               const int32_t *__restrict__ fcol, const int64_t *__restrict__ orp,
@@ -696,6 +966,64 @@ void launch_form(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yo
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// Work decomposition of the grid form for a block of w columns.
+struct GridPlan {
+  int tx, ty, vec, ntx, ntile, nchunk, nseg, zlen, items, per_xcd;
+};
+constexpr int kGridTargetItems = 3072;  // about four rounds of 3 workgroups on each of 256 CUs
+constexpr int kGridMinZlen = 8;         // planes per segment: bounds the z halo re-read to 1/4
+
+GridPlan grid_plan(int64_t gx, int64_t gy, int64_t gz, int w, int vec, int max_slots) {
+  GridPlan p;
+  p.tx = gy > 1 ? 8 : 64;
+  p.ty = gy > 1 ? 8 : 1;
+  p.vec = vec;
+  p.ntx = (int)((gx + p.tx - 1) / p.tx);
+  p.ntile = p.ntx * (int)((gy + p.ty - 1) / p.ty);
+  p.nchunk = (w + 64 * vec - 1) / (64 * vec);
+  const int64_t base = (int64_t)p.ntile * p.nchunk;
+  int64_t nseg = (kGridTargetItems + base - 1) / base;
+  nseg = std::min<int64_t>(nseg, std::max<int64_t>(1, gz / kGridMinZlen));
+  // one partial row of column sums per (tile, segment)
+  nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, max_slots / p.ntile));
+  p.zlen = (int)((gz + nseg - 1) / nseg);
+  p.nseg = (int)((gz + p.zlen - 1) / p.zlen);
+  p.items = (int)(base * p.nseg);
+  p.per_xcd = (p.items + kXcd - 1) / kXcd;
+  return p;
+}
+
+template <typename T, int VEC, int TX, int TY>
+void launch_grid_tile(const DevCSR<T> &A, const GridPlan &p, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w,
+                      T alpha, T beta, T gamma, double *partial, const double *colss, hipStream_t s) {
+  const int sel = (Z.p ? 2 : 0) + (partial ? 1 : 0);
+  const dim3 grid((unsigned)(p.per_xcd * kXcd)), block(kGridThreads);
+#define ARR_GRID_CASE(k, H, S)                                                                                  \
+  case k:                                                                                                      \
+    hipLaunchKernelGGL((k_filter_spmm_grid<T, VEC, TX, TY, H, S>), grid, block, 0, s, (int)A.gx, (int)A.gy,     \
+                       (int)A.gz, p.ntx, p.ntile, p.nseg, p.zlen, p.nchunk, p.items, p.per_xcd, A.coef, w, Yin.p, \
+                       Yin.ld, Z.p, Z.ld, Yout.p, Yout.ld, alpha, beta, gamma, partial, w, colss);             \
+    break;
+  switch (sel) {
+    ARR_GRID_CASE(0, false, false)
+    ARR_GRID_CASE(1, false, true)
+    ARR_GRID_CASE(2, true, false)
+    ARR_GRID_CASE(3, true, true)
+  }
+#undef ARR_GRID_CASE
+}
+
+template <typename T, int VEC>
+void launch_grid_vec(const DevCSR<T> &A, const GridPlan &p, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, int w,
+                     T alpha, T beta, T gamma, double *partial, const double *colss, hipStream_t s) {
+  if (p.ty > 1)
+    launch_grid_tile<T, VEC, 8, 8>(A, p, Yin, Z, Yout, w, alpha, beta, gamma, partial, colss, s);
+  else
+    launch_grid_tile<T, VEC, 64, 1>(A, p, Yin, Z, Yout, w, alpha, beta, gamma, partial, colss, s);
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7) == 0; }
 
 }  // namespace
 
@@ -840,10 +1168,89 @@ bool split_row(int64_t i, int64_t P, const int64_t *rowptr, const int32_t *col, 
   return true;
 }
 
+// Grid form: (gx, gy, gz) when every entry of the pattern is a neighbour of
+// its row in a 7-point stencil on a gx x gy x gz lexicographic grid (x
+// fastest), or in a 5-point stencil on a gx x gz grid (returned with gy = 1).
+// The strides are the positive column offsets above 1: exactly two, s2 < s3
+// with s3 = s2 gy and n = s3 gz (3D), or one, s2 = gx with n = gx gz (2D).
+// Every entry is then checked to stay inside the grid (no wrap-around from one
+// grid line to the next). The tiles of the kernel must fit the rows of column
+// sums (one per tile and segment).
+bool choose_grid(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t &gx, int64_t &gy, int64_t &gz) {
+  gx = gy = gz = 0;
+  if (n < 4) return false;
+  int64_t s2 = 0, s3 = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      const int64_t d = (int64_t)col[q] - i;
+      if (d <= 1 || d == s2 || d == s3) continue;
+      if (!s2) s2 = d;
+      else if (!s3) s3 = d;
+      else return false;  // a third stride
+    }
+  if (!s2) return false;
+  if (s3 && s3 < s2) std::swap(s2, s3);
+  int64_t X, Y, Zd;
+  if (s3) {
+    if (s3 % s2 || n % s3) return false;
+    X = s2, Y = s3 / s2, Zd = n / s3;
+  } else {
+    if (n % s2) return false;
+    X = s2, Y = 1, Zd = n / s2;
+  }
+  if (X < 2 || Zd < 2 || (s3 && Y < 2)) return false;
+  const int64_t plane = X * Y;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t x = i % X, y = (i / X) % Y, z = i / plane;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      const int64_t d = (int64_t)col[q] - i;
+      bool ok;
+      if (d == 0) ok = true;
+      else if (d == 1 || d == -1) ok = x + d >= 0 && x + d < X;
+      else if (Y > 1 && (d == X || d == -X)) ok = y + d / X >= 0 && y + d / X < Y;
+      else if (d == plane || d == -plane) ok = z + d / plane >= 0 && z + d / plane < Zd;
+      else ok = false;
+      if (!ok) return false;
+    }
+  }
+  // tiles of the kernel (8 x 8 in 3D, 64 x 1 in 2D) against the column-sum rows
+  const int64_t tiles = Y > 1 ? ((X + 7) / 8) * ((Y + 7) / 8) : (X + 63) / 64;
+  if (tiles > spmm_groups(n) || n > (int64_t)INT32_MAX) return false;
+  gx = X, gy = Y, gz = Zd;
+  return true;
+}
+
+// Rows in the grid form's record: {A[i][i - gx gy], A[i][i - gx], A[i][i - 1],
+// A[i][i], A[i][i + 1], A[i][i + gx], A[i][i + gx gy], 0}.
+void split_grid(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out) {
+  const int64_t plane = out.gx * out.gy;
+  out.coef.assign(8 * n, 0.0);
+  out.fcol.clear();
+  out.orp.clear();
+  out.ocol.clear();
+  out.oval.clear();
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      const int64_t d = (int64_t)col[q] - i;
+      const int slot = d == 0 ? 3 : d == -1 ? 2 : d == 1 ? 4 : d == -plane ? 0 : d == plane ? 6 : d < 0 ? 1 : 5;
+      out.coef[8 * i + slot] = val[q];
+    }
+  out.pair = 0;
+  out.kf = 0;
+}
+
 }  // namespace
 
 void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, RowSplit &out,
-                bool allow_pair) {
+                int form) {
+  // automatic: the grid form for 2D grids only (measured faster than the
+  // paired form there; slower on 3D grids, where it is taken only on request)
+  const bool allow_grid = form == 0 || form == 3, allow_pair = form != 1;
+  if (allow_grid && choose_grid(n, rowptr, col, out.gx, out.gy, out.gz) && (form == 3 || out.gy == 1)) {
+    split_grid(n, rowptr, col, val, out);
+    return;
+  }
+  out.gx = out.gy = out.gz = 0;
   int64_t P = allow_pair ? choose_pair(n, rowptr, col) : 0;
   for (;;) {
     out.coef.assign(8 * n, 0.0);
@@ -875,13 +1282,49 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   ARR_REQUIRE(Yin.w >= w && (!Z.p || Z.w >= w), "filter_spmm: block widths differ");
   ARR_REQUIRE(Yin.p != Yout.p, "filter_spmm: Yout must not alias Yin");
   ARR_REQUIRE(!colss || partial, "filter_spmm: output column scaling needs the column sums");
-  ARR_REQUIRE(A.n == 0 || (A.coef && A.fcol), "filter_spmm: matrix rows missing");
+  ARR_REQUIRE(A.n == 0 || (A.coef && (A.fcol || A.gx)), "filter_spmm: matrix rows missing");
   ARR_REQUIRE(!A.orp || (A.ocol && A.oval), "filter_spmm: overflow entries missing");
   ARR_REQUIRE(A.pair == 0 || (!A.orp && A.pair >= kPairRun && 2 * A.pair <= A.n && (A.kf == 1 || A.kf == 3)),
               "filter_spmm: invalid paired form");
   const int groups = spmm_groups(A.n);
   if (A.n == 0 || w == 0) return groups;
   SpmmTimer *timer = spmm_timer();
+  if (A.gx) {
+    ARR_REQUIRE(A.gx * A.gy * A.gz == A.n && A.pair == 0 && !A.orp, "filter_spmm: invalid grid form");
+    // FP32 rows with 8-byte alignment: two columns per lane (512-byte segments)
+    const bool v2 = sizeof(T) == 4 && w % 2 == 0 && Yin.ld % 2 == 0 && Yout.ld % 2 == 0 &&
+                    (!Z.p || Z.ld % 2 == 0) && aligned8(Yin.p) && aligned8(Yout.p) && (!Z.p || aligned8(Z.p));
+    const int vec = v2 ? 2 : 1;
+    const GridPlan p = grid_plan(A.gx, A.gy, A.gz, w, vec, groups);
+    // rows are addressed by 32-bit byte offsets within a plane of each block
+    const int64_t plane = A.gx * A.gy, lmax = std::max(Yin.ld, std::max(Yout.ld, Z.p ? Z.ld : (int64_t)0));
+    ARR_REQUIRE(plane * (lmax + 64 * vec) * (int64_t)sizeof(T) <= (int64_t)INT32_MAX,
+                "filter_spmm: grid plane too large for the block's leading dimension");
+    ARR_REQUIRE(!partial || p.ntile * p.nseg <= groups, "filter_spmm: grid tiles exceed the column-sum rows");
+    const int flags = (Z.p ? 1 : 0) + (partial ? 4 : 0) + 32 + (p.ty == 1 ? 64 : 0);
+    const int cls = (vec == 2 ? 1 : 0) + (sizeof(T) == 8 ? 10 : 0) + 20 * flags;
+    SpmmTimer::Pending pend{};
+    if (timer) {
+      pend.a = timer->get();
+      pend.b = timer->get();
+      pend.cls = cls;
+      pend.bytes = (double)(sizeof(T) + 4) * A.nnz + 8.0 * (A.n + 1) +
+                   (double)sizeof(T) * A.n * w * (2.0 + (Z.p ? 1.0 : 0.0));
+      ARR_HIP(hipEventRecord(pend.a, s));
+    }
+    const T al = (T)alpha, be = (T)beta, ga = (T)gamma;
+    if (v2) {
+      if constexpr (sizeof(T) == 4) launch_grid_vec<T, 2>(A, p, Yin, Z, Yout, w, al, be, ga, partial, colss, s);
+    } else {
+      launch_grid_vec<T, 1>(A, p, Yin, Z, Yout, w, al, be, ga, partial, colss, s);
+    }
+    ARR_HIP(hipGetLastError());
+    if (timer) {
+      ARR_HIP(hipEventRecord(pend.b, s));
+      timer->pending.push_back(pend);
+    }
+    return p.ntile * p.nseg;
+  }
   // FP32 with 16-byte aligned rows: 4 consecutive columns per lane
   const bool vec4 = sizeof(T) == 4 && Yin.ld % 4 == 0 && Yout.ld % 4 == 0 && (!Z.p || Z.ld % 4 == 0) &&
                     aligned16(Yin.p) && aligned16(Yout.p) && (!Z.p || aligned16(Z.p)) && w % 4 == 0;
@@ -951,8 +1394,11 @@ template <typename T>
 void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s) {
   if (A.n == 0) return;
   const int64_t blocks = (A.n + 255) / 256;
-  hipLaunchKernelGGL((k_spmv<T>), dim3((unsigned)blocks), dim3(256), 0, s, A.n, A.pair, A.coef, A.fcol, A.orp,
-                     A.ocol, A.oval, x, y);
+  if (A.gx)
+    hipLaunchKernelGGL((k_spmv_grid<T>), dim3((unsigned)blocks), dim3(256), 0, s, A.n, A.gx, A.gy, A.coef, x, y);
+  else
+    hipLaunchKernelGGL((k_spmv<T>), dim3((unsigned)blocks), dim3(256), 0, s, A.n, A.pair, A.coef, A.fcol, A.orp,
+                       A.ocol, A.oval, x, y);
   ARR_HIP(hipGetLastError());
 }
 

@@ -21,6 +21,8 @@ import bench  # noqa: E402
     (("double", 2, 4, 8), "k_filter_spmm_paired<double, 2, 2, 3, false, false>"),
     (("double", 1, 2, 8 | 16 | 4), "k_filter_spmm_paired<double, 1, 2, 1, false, true>"),
     (("float", 4, 8, 8 | 1), "k_filter_spmm_paired<float, 4, 2, 3, true, false>"),
+    (("double", 1, 1, 32), "k_filter_spmm_grid<double, 1, 8, 8, false, false>"),
+    (("float", 1, 2, 32 | 64 | 4), "k_filter_spmm_grid<float, 2, 64, 1, false, true>"),
 ])
 def test_spmm_kernel_names(args, name):
     assert bench.spmm_kernel_name(*args) == name

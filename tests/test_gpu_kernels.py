@@ -78,10 +78,34 @@ def lap2d_holes60(m=60, seed=8):
     return W.from_scipy(S, "lap2d_holes60")
 
 
+def grid3d(nx, ny, nz, seed=11, drop=0):
+    """7-point operator with random values on an nx x ny x nz grid (x
+    fastest), optionally with `drop` rows and columns removed (holes)."""
+    rng = np.random.default_rng(seed)
+    def d1(m):
+        return sp.diags([np.ones(m - 1), np.ones(m - 1)], [-1, 1])
+    I = lambda m: sp.identity(m)
+    P = (sp.kron(I(nz), sp.kron(I(ny), d1(nx))) + sp.kron(I(nz), sp.kron(d1(ny), I(nx)))
+         + (sp.kron(d1(nz), sp.kron(I(ny), I(nx))) if nz > 1 else 0))
+    P = sp.csr_matrix(P)
+    U = sp.triu(P, 1).tocoo()
+    v = rng.standard_normal(U.nnz)
+    S = sp.coo_matrix((v, (U.row, U.col)), shape=P.shape)
+    S = sp.csr_matrix(S + S.T + sp.diags(rng.standard_normal(P.shape[0]) + 6.0))
+    if drop:
+        keep = np.ones(P.shape[0])
+        keep[rng.choice(P.shape[0], drop, replace=False)] = 0.0
+        S = sp.csr_matrix(sp.diags(keep) @ S @ sp.diags(keep))
+        S.eliminate_zeros()
+    return W.from_scipy(S, f"grid{nx}x{ny}x{nz}")
+
+
 # Row forms: lap3d_12V paired (P = 144; the last run of each half block
 # starts 16 rows early), lap3d_11V plain with four far entries a row,
 # lap3d_23V paired (P = 529, 11 rows recomputed, a tail of 529 rows),
-# band_p40 and lap2d_holes60 paired, the others plain.
+# band_p40 and lap2d_holes60 paired; the grid operators named "grid" and
+# "*:grid" take the grid form (8 x 8 tiles in 3D, 64 x 1 in 2D; ragged tiles,
+# holes, a single tile, segments of one plane); the others plain.
 MATS = {
     "lap3d_12V": lambda: W.laplacian_3d(12, potential_seed=1),
     "lap3d_11V": lambda: W.laplacian_3d(11, potential_seed=3),
@@ -92,7 +116,29 @@ MATS = {
     "powerlaw_4000": lambda: W.powerlaw_random(4000, seed=7, cap=300),
     "empty_rows": with_empty_rows,
     "tridiagonal": tridiagonal,
+    "lap3d_23V:grid": lambda: W.laplacian_3d(23, potential_seed=5),
+    "grid_13x11x9": lambda: grid3d(13, 11, 9),
+    "grid_8x8x40_holes": lambda: grid3d(8, 8, 40, seed=12, drop=30),
+    "grid_3x17x5": lambda: grid3d(3, 17, 5, seed=13),
+    "lap2d_holes:grid": lap2d_holes,
+    "grid_130x37_2d": lambda: grid3d(130, 1, 37, seed=14),
 }
+# row form each matrix is tested in (default: automatic)
+FORMS = {"lap3d_12V": arr.ROW_PAIRED, "lap3d_11V": arr.ROW_PAIRED, "lap3d_23V": arr.ROW_PAIRED,
+         "lap2d_holes60": arr.ROW_PAIRED, "lap2d_holes": arr.ROW_PAIRED, "lap3d_23V:grid": arr.ROW_GRID,
+         "grid_13x11x9": arr.ROW_GRID, "grid_8x8x40_holes": arr.ROW_GRID, "grid_3x17x5": arr.ROW_GRID}
+
+
+def dcsr(mat, A, dtype=None):
+    return arr.DeviceCSR(A, dtype=dtype, row_form=FORMS.get(mat, arr.ROW_AUTO))
+
+
+def test_matrix_forms_are_the_intended_ones():
+    """Host check that each test matrix takes the row form it stands for."""
+    for mat, make in MATS.items():
+        A = make()
+        grid = arr.arr_row_grid(A, FORMS.get(mat, arr.ROW_AUTO))
+        assert (grid[0] > 0) == (mat.startswith("grid") or mat.endswith(":grid")), (mat, grid)
 
 
 @pytest.mark.parametrize("mat", list(MATS))
@@ -100,7 +146,7 @@ MATS = {
 def test_filter_step_fp64(mat, w):
     A = MATS[mat]()
     S = A.to_scipy()
-    Ad = arr.DeviceCSR(A)
+    Ad = dcsr(mat, A)
     rng = np.random.default_rng(w)
     ld = w + 3
     Yin = rng.standard_normal((A.n, ld))
@@ -125,7 +171,7 @@ def test_filter_step_fp32(mat, w, ld):
     """FP32 blocks: 16-byte loads when rows are 16-byte aligned (ld and w
     multiples of 4), one column per lane otherwise; several column chunks."""
     A = MATS[mat]()
-    Ad = arr.DeviceCSR(A, dtype=torch.float32)
+    Ad = dcsr(mat, A, dtype=torch.float32)
     S32 = sp.csr_matrix((A.val.astype(np.float32).astype(np.float64), A.colind, A.rowptr), shape=(A.n, A.n))
     rng = np.random.default_rng(w + ld)
     Yin = rng.standard_normal((A.n, ld)).astype(np.float32).astype(np.float64)
@@ -202,7 +248,7 @@ def test_filter_step_no_z(mat, w, dtype, sums):
     and without rows past four far entries."""
     A = NO_Z_MATS[mat]()
     tdt, u = (torch.float32, 6e-8) if dtype == "f32" else (torch.float64, 1.2e-16)
-    Ad = arr.DeviceCSR(A, dtype=tdt)
+    Ad = dcsr(mat, A, dtype=tdt)
     vals = A.val.astype(np.float32).astype(np.float64) if dtype == "f32" else A.val
     Sx = sp.csr_matrix((vals, A.colind, A.rowptr), shape=(A.n, A.n))
     rng = np.random.default_rng(1 + w)
@@ -224,7 +270,8 @@ def test_filter_step_no_z(mat, w, dtype, sums):
 
 
 PAIRED = {"lap3d_20": lambda: W.laplacian_3d(20, potential_seed=2), "lap2d_107": lambda: W.laplacian_2d(107),
-          "lap3d_23V": MATS["lap3d_23V"], "band_p40": band_p40}
+          "lap3d_23V": MATS["lap3d_23V"], "band_p40": band_p40, "grid_13x11x9": MATS["grid_13x11x9"],
+          "grid_130x37_2d": MATS["grid_130x37_2d"]}
 
 
 @pytest.mark.parametrize("mat", list(PAIRED))
@@ -232,14 +279,17 @@ PAIRED = {"lap3d_20": lambda: W.laplacian_3d(20, potential_seed=2), "lap2d_107":
 @pytest.mark.parametrize("w", [1, 65, 240, 520])
 @pytest.mark.parametrize("zs", [(False, False), (True, False), (False, True), (True, True)])
 def test_filter_step_row_forms(mat, dtype, w, zs):
-    """The paired and the plain row form against the definition, every
-    variant (Z operand, column sums, FP32 16-byte and FP64 column chunks):
-    one run per half block (lap3d_20), one far slot with recomputed rows and
-    an upper-row tail (lap2d_107), three far slots with a tail (lap3d_23V),
-    a tail holding lower rows too (band_p40)."""
+    """The grid, paired and plain row forms against the definition, every
+    variant (Z operand, column sums, FP32 16-byte / 8-byte and FP64 column
+    chunks): one run per half block (lap3d_20), one far slot with recomputed
+    rows and an upper-row tail (lap2d_107), three far slots with a tail
+    (lap3d_23V), a tail holding lower rows too (band_p40); grid form (forced,
+    and automatic for the 2D grids) on the grids (3D 8 x 8 tiles and 2D
+    64 x 1 tiles, ragged), paired form on all but the two whose grid strides
+    are below the run length."""
     A = PAIRED[mat]()
-    pair, _, _ = arr.arr_row_form(A)
-    assert pair > 0
+    pair, _, _ = arr.arr_row_form(A, arr.ROW_PAIRED)
+    assert pair > 0 or mat.startswith("grid")
     has_z, sums = zs
     tdt, u = (torch.float32, 6e-8) if dtype == "f32" else (torch.float64, 1.2e-16)
     vals = A.val.astype(np.float32).astype(np.float64) if dtype == "f32" else A.val
@@ -255,7 +305,7 @@ def test_filter_step_row_forms(mat, dtype, w, zs):
     bound = abs(al) * (abs(Sx) @ np.abs(Yin)) + abs(be) * np.abs(Yin) + abs(ga) * np.abs(Z)
     kmax = int(np.diff(A.rowptr).max()) + 4
     outs = []
-    for form in (arr.ROW_AUTO, arr.ROW_PLAIN):
+    for form in (arr.ROW_GRID, arr.ROW_AUTO, arr.ROW_PAIRED, arr.ROW_PLAIN):
         Ad = arr.DeviceCSR(A, dtype=tdt, row_form=form)
         Yd, Zd = dev(Yin, tdt), dev(Z, tdt)
         Od = torch.zeros_like(Yd)
@@ -267,7 +317,8 @@ def test_filter_step_row_forms(mat, dtype, w, zs):
         if sums:
             np.testing.assert_allclose(ss.cpu().numpy(), (got ** 2).sum(axis=0), rtol=1e-12)
         outs.append(got)
-    assert np.all(np.abs(outs[0] - outs[1]) <= 2 * kmax * u * bound + 1e-30)
+    for o in outs[1:]:
+        assert np.all(np.abs(outs[0] - o) <= 2 * kmax * u * bound + 1e-30)
 
 
 @pytest.mark.parametrize("d", [3, 8, 15])

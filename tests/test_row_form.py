@@ -1,5 +1,7 @@
-"""Host choice of the SpMM row form (no GPU): the paired form for operators
-with a frequent far column offset P whose rows keep at most three other far
+"""Host choice of the SpMM row form (no GPU): the grid form for 7-point (3D)
+and 5-point (2D) operators on a lexicographic grid with no entry wrapping
+from one grid line to the next; otherwise the paired form for operators with
+a frequent far column offset P whose rows keep at most three other far
 entries, the plain form otherwise. The pairing offset follows from the
 grid's strides, the run length of 20 rows and the at-most-P/8 recomputed
 rows per half block."""
@@ -43,8 +45,79 @@ def lap2d_9pt(m):
 def test_row_form_choice(make, expect):
     A = make()
     plain = (0, 4, plain_overflow(A))
-    assert arr.arr_row_form(A, arr.ROW_AUTO) == (expect or plain)
+    assert arr.arr_row_form(A, arr.ROW_PAIRED) == (expect or plain)
     assert arr.arr_row_form(A, arr.ROW_PLAIN) == plain
+    assert arr.arr_row_grid(A, arr.ROW_PAIRED) == (0, 0, 0)
+    assert arr.arr_row_grid(A, arr.ROW_PLAIN) == (0, 0, 0)
+
+
+def grid_operator(nx, ny, nz, wrap=False):
+    """Pattern of a 7-point (5-point if ny == 1 or nz == 1) operator on an
+    nx x ny x nz grid, x fastest; `wrap` adds one entry joining the end of an
+    x line to the start of the next (not a grid operator)."""
+    n = nx * ny * nz
+    idx = np.arange(n)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    rows, cols = [idx], [idx]
+    for ok, d in ((x + 1 < nx, 1), (y + 1 < ny, nx), (z + 1 < nz, nx * ny)):
+        r = idx[ok]
+        rows += [r, r + d]
+        cols += [r + d, r]
+    if wrap:
+        rows += [np.array([nx - 1, nx])]
+        cols += [np.array([nx, nx - 1])]
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    return W.from_scipy(sp.csr_matrix((np.ones(r.size), (r, c)), shape=(n, n)), "grid")
+
+
+@pytest.mark.parametrize("dims", [(20, 20, 20), (13, 11, 9), (3, 17, 5), (100, 1, 100), (130, 1, 37), (2, 2, 2),
+                                  (64, 64, 2)])
+def test_grid_form_detected_with_its_dimensions(dims):
+    """ARR_ROW_GRID takes the grid form, with the grid's dimensions (gy = 1
+    for a 2D grid), no pairing and no gathered far entries; the automatic
+    choice does so for 2D grids and leaves 3D grids to the paired form."""
+    nx, ny, nz = dims
+    A = grid_operator(nx, ny, nz)
+    assert arr.arr_row_grid(A, arr.ROW_GRID) == (nx, ny, nz)
+    assert arr.arr_row_form(A, arr.ROW_GRID) == (0, 0, 0)
+    if ny == 1:
+        assert arr.arr_row_grid(A, arr.ROW_AUTO) == (nx, ny, nz)
+    else:
+        assert arr.arr_row_grid(A, arr.ROW_AUTO) == (0, 0, 0)
+        assert arr.arr_row_form(A, arr.ROW_AUTO) == arr.arr_row_form(A, arr.ROW_PAIRED)
+
+
+def test_grid_form_of_the_workload_generators():
+    assert arr.arr_row_grid(W.laplacian_3d(30, potential_seed=2), arr.ROW_GRID) == (30, 30, 30)
+    assert arr.arr_row_grid(W.laplacian_3d(30, potential_seed=2)) == (0, 0, 0)
+    assert arr.arr_row_grid(W.laplacian_2d(41)) == (41, 1, 41)
+    assert arr.arr_row_grid(W.laplacian_2d_potential(50, potential_seed=3)) == (50, 1, 50)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: grid_operator(12, 10, 6, wrap=True),      # an entry wrapping from one x line to the next
+    lambda: grid_operator(40, 1, 30, wrap=True),
+    lambda: lap2d_9pt(20),                            # diagonal neighbours: four strides
+    lambda: banded(1070, (1, 3, 40)),                 # strides 3 and 40: 40 is not a multiple of 3
+    lambda: banded(1000, (1, 40)),                    # 40 x 25 grid strides, but the +-1 entries wrap
+    lambda: banded(1001, (1, 40)),                    # 1001 is no multiple of the stride 40
+    lambda: W.powerlaw_random(3000, seed=9, cap=500),
+])
+def test_grid_form_rejected(make):
+    A = make()
+    grid = arr.arr_row_grid(A, arr.ROW_GRID)
+    if grid != (0, 0, 0):
+        # a banded matrix whose strides happen to describe a grid is one:
+        # every entry must then be a neighbour inside it
+        nx, ny, nz = grid
+        assert nx * ny * nz == A.n
+        rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+        d = np.asarray(A.colind, dtype=np.int64) - rows
+        x = rows % nx
+        ok = (d == 0) | ((d == 1) & (x + 1 < nx)) | ((d == -1) & (x > 0)) | (np.abs(d) == nx) | (np.abs(d) == nx * ny)
+        assert ok.all()
+    else:
+        assert arr.arr_row_form(A, arr.ROW_GRID) == arr.arr_row_form(A, arr.ROW_PAIRED)
 
 
 def plain_overflow(A):
@@ -60,6 +133,7 @@ def test_row_form_irregular_matrix_is_plain():
     A = W.powerlaw_random(3000, seed=9, cap=500)
     pair, far, ovf = arr.arr_row_form(A)
     assert (pair, far) == (0, 4) and ovf > 0
+    assert arr.arr_row_grid(A) == (0, 0, 0)
 
 
 def test_row_form_rejects_bad_input():
