@@ -210,7 +210,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     o.timing = 1
     if args.mixed_switch is not None:
         o.mixed_switch = args.mixed_switch
-    o.verbose = 1 if args.verbose else 0
+    o.verbose = args.verbose_level if args.verbose else 0
     o.inner_solver = arr.INNER_GN if args.inner == "gn" else arr.INNER_MPM
     o.poly_form = {"product": arr.POLY_PRODUCT, "horner": arr.POLY_HORNER, "chebyshev": arr.POLY_CHEBYSHEV}[args.poly]
     o.row_form = {"auto": arr.ROW_AUTO, "plain": arr.ROW_PLAIN, "paired": arr.ROW_PAIRED,
@@ -317,6 +317,7 @@ def main():
                     help="headline is the FP64 path; 'both' adds the mixed path beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--verbose-level", type=int, default=1, help="with --verbose: 2 also prints each inner check")
     ap.add_argument("--mixed-switch", type=float, default=None)
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with three device copies of 2 GiB (reference kernel for counter scaling)")

@@ -155,7 +155,7 @@ typedef struct {
   int32_t device;        /* HIP device ordinal, default 0                                  */
   uint64_t seed;         /* seed of the device Gaussian starting block                     */
   double mixed_switch;   /* ARR_MIXED: leave FP32 once maxres <= this (default 1e-2)       */
-  int32_t verbose;       /* 1: one line per outer iteration on stderr                      */
+  int32_t verbose;       /* 1: one line per outer iteration on stderr; 2: also each inner check */
   int32_t timing;        /* 1: time filter SpMM launches with HIP events (stats)           */
   int32_t keep_vectors;  /* served requests: keep eigenvectors on the host (default 1)    */
   int32_t inner_solver;  /* arr_inner_t, default ARR_INNER_MPM                              */

@@ -685,15 +685,17 @@ void Jacobi::solve(int m, const double *H, double *V, std::vector<double> &evals
   double hn[2];
   ARR_HIP(hipMemcpyAsync(hn, nrm, sizeof(hn), hipMemcpyDeviceToHost, s));
   ARR_HIP(hipStreamSynchronize(s));
-  // A rotation is skipped when |a_pq| <= eps |H|_F (a perturbation within
-  // the rounding of H itself) or <= eps sqrt(|a_pp a_qq|). Without the
-  // absolute bound, clusters of zero eigenvalues keep rotating on
-  // rounding-level entries and never meet the relative one.
-  const double tiny = std::max(1e-300, 2.2e-16 * hn[1]);
+  // A rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|) or below an
+  // absolute floor of 1e-18 |H|_F. Clusters of zero eigenvalues never meet
+  // the relative bound and keep rotating on rounding-level entries; after
+  // kLooseSweeps sweeps the floor is raised to eps |H|_F (a perturbation
+  // within the rounding of H itself), which ends them.
+  double tiny = std::max(1e-300, 1e-18 * hn[1]);
   const int nchunk = (me + 63) / 64;
-  constexpr int kMaxSweeps = 40;
+  constexpr int kMaxSweeps = 40, kLooseSweeps = 20;
   int sweeps = 0;
   for (; sweeps < kMaxSweeps; ++sweeps) {
+    if (sweeps == kLooseSweeps) tiny = std::max(tiny, 2.2e-16 * hn[1]);
     launch_fill<int>(flag, 1, 0, s);
     const int steps = nb > 1 ? nb - 1 : 1;
     for (int st = 0; st < steps; ++st) {

@@ -429,13 +429,14 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     double t = now();
     // ---- subspace update: MPM on A - aI over [0, b - a] ----
     Blk<T> X = B.Z(0, wp_);
+    const Blk<const T> Qc{B.Qb.template as<T>(), B.ldq, nc_};
+    {
     // the filter's ping-pong pair: two compact n x ldc blocks in U when they
     // fit (rows of ldc values stream faster than rows strided by ldz)
     const int64_t ldc = round_up((int64_t)wp_, 8);
     const bool compact = 2 * ldc <= B.ldz;
     Blk<T> Ya = compact ? Blk<T>{B.Ub.template as<T>(), ldc, wp_} : B.U(0, wp_);
     Blk<T> Yb = compact ? Blk<T>{B.Ub.template as<T>() + n * ldc, ldc, wp_} : B.U(wp_, wp_);
-    const Blk<const T> Qc{B.Qb.template as<T>(), B.ldq, nc_};
     wk_.ensure_cols(n, wp_);
     // Non-finite guard: the MPM iterate is kept in W (free until the
     // Rayleigh-Ritz step) at the start of the filter stage. A check that finds
@@ -498,7 +499,13 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
         goto restart_inner;
       }
       const double thr = fp32_stage ? std::max(tol_t_, 1e-6) : tol_t_;
+      if (o_.verbose >= 2) {
+        std::fprintf(stderr, "[arr]   inner check %d (%d filter calls of degree %d): rcond %.3e\n", i1 + 1,
+                     (i1 + 1) * o_.maxit2, d_, rc);
+        std::fflush(stderr);
+      }
       if (rc <= thr || rc / rcp > 0.99) break;
+    }
     }
     ARR_HIP(hipStreamSynchronize(s_));
     stats.t_filter += now() - t;
