@@ -226,6 +226,10 @@ typedef struct {
   /* max over the k returned pairs of the explicit FP64 residual, in the eq.
    * resi scaling and as ||A x - lambda x||_2 / ||A||_2 with norm_est */
   double maxres_explicit, maxres_norm_a;
+  /* sum over the Rayleigh-Ritz steps of m^2, m the dimension of the projected
+   * subspace ((p + 1) w' columns): the dense work of a solve scales with n
+   * times this */
+  double arr_m2;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

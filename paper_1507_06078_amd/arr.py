@@ -95,7 +95,7 @@ class arr_stats_t(ctypes.Structure):
                 ("spmm32_cols_per_lane", ctypes.c_int32), ("spmm32_vec", ctypes.c_int32),
                 ("fp32_maxres", ctypes.c_double), ("spmm_flags", ctypes.c_int32), ("spmm32_flags", ctypes.c_int32),
                 ("nan_retries", ctypes.c_int32), ("maxres_explicit", ctypes.c_double),
-                ("maxres_norm_a", ctypes.c_double)]
+                ("maxres_norm_a", ctypes.c_double), ("arr_m2", ctypes.c_double)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",

@@ -55,7 +55,8 @@ class Server {
   std::deque<uint64_t> queue_;
   std::map<uint64_t, Request> reqs_;
   std::thread sched_;
-  std::vector<std::thread> workers_;
+  std::map<uint64_t, std::thread> workers_;  // running (or finished, not yet joined) requests
+  std::vector<uint64_t> finished_;            // workers done with their request, to be joined
   std::chrono::steady_clock::time_point t0_;
 };
 

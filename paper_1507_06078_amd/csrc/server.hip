@@ -97,8 +97,8 @@ Server::~Server() {
     cv_.notify_all();
   }
   if (sched_.joinable()) sched_.join();
-  for (std::thread &t : workers_)
-    if (t.joinable()) t.join();
+  for (auto &kv : workers_)
+    if (kv.second.joinable()) kv.second.join();
   // the handles outlive the server: drop their back-references
   for (auto &kv : reqs_)
     if (kv.second.solver && kv.second.solver->server == this) kv.second.solver->server = nullptr;
@@ -135,9 +135,23 @@ uint64_t Server::submit(Solver *s) {
 
 void Server::schedule() {
   std::unique_lock<std::mutex> lk(mu_);
+  // joins the threads of finished requests (their last step, under mu_, is
+  // to list themselves; they take no lock after it)
+  auto reap = [&] {
+    for (uint64_t id : finished_) {
+      auto it = workers_.find(id);
+      if (it != workers_.end()) {
+        if (it->second.joinable()) it->second.join();
+        workers_.erase(it);
+      }
+    }
+    finished_.clear();
+  };
   while (true) {
-    cv_.wait(lk, [&] { return stopping_ || (!queue_.empty() && active_ < slots_); });
+    cv_.wait(lk, [&] { return stopping_ || !finished_.empty() || (!queue_.empty() && active_ < slots_); });
+    reap();
     if (stopping_) break;
+    if (queue_.empty() || active_ >= slots_) continue;
     Request &r = reqs_[queue_.front()];
     size_t off = 0;
     if (!arena_.alloc(r.bytes, off)) {
@@ -150,7 +164,7 @@ void Server::schedule() {
     r.off = off;
     r.t_admit = now();
     ++active_;
-    workers_.emplace_back([this, id] { work(id); });
+    workers_.emplace(id, std::thread([this, id] { work(id); }));
   }
 }
 
@@ -195,6 +209,7 @@ void Server::work(uint64_t id) {
   r.t_done = now();
   r.done = true;
   --active_;
+  finished_.push_back(id);
   cv_.notify_all();
 }
 

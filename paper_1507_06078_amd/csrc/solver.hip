@@ -529,6 +529,7 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     rayleigh_ritz<T>(A, n, Blk<const T>{U.p, U.ld, m}, B.W(0, m), wk_, ritz, s_, rinv);
     stats.t_dense += now() - td;
     stats.arr_calls += 1;
+    stats.arr_m2 += (double)m * m;
     // ---- merge with (Qc, Sigma_c): keep the w leading (stable, Qc first) ----
     std::vector<int> order(nc_ + m);
     std::iota(order.begin(), order.end(), 0);
