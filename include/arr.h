@@ -165,6 +165,14 @@ typedef struct {
    * NaN into the iterate right after the n-th filter application of the
    * solve; n < 0 does so after every application from the |n|-th on. */
   int32_t debug_nan_poly;
+  /* 1: lean-memory mode. The n x m block A U of the Rayleigh-Ritz step is not
+   * kept: H = U^T (A U) is formed from column chunks of 256 (FP64) or 512
+   * (FP32) columns, and A X of the new Ritz vectors comes from one more SpMM;
+   * the returned eigenvectors stay in a block the solve no longer needs. Saves
+   * (p_max + 1) w + k columns of n values per precision (one of the three
+   * n x (p_max + 1) w blocks and the output block) for one extra SpMM of the
+   * new Ritz vectors per outer iteration. Needs the MPM inner solver. */
+  int32_t lean_memory;
 } arr_options_t;
 
 /* Counters and timings of the last solve. */

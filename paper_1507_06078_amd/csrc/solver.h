@@ -17,7 +17,8 @@ namespace arr {
 // Rayleigh-Ritz step. Q and Q2 (n x w) hold the locked pairs Qc.
 template <typename T>
 struct Blocks {
-  DevBuf Zb, Ub, Wb, Qb, Q2b;
+  DevBuf Zb, Ub, Wb, Qb, Q2b, Tb;  // Wb: not allocated in the lean-memory mode; Tb: its chunk buffer (n x ldt)
+  int64_t ldt = 0;
   int64_t ldz = 0, ldq = 0;
   bool ready = false;
   void alloc(int64_t n, int64_t ldz_, int64_t ldq_) {
@@ -31,7 +32,7 @@ struct Blocks {
     ready = true;
   }
   void release() {
-    Zb.release(); Ub.release(); Wb.release(); Qb.release(); Q2b.release();
+    Zb.release(); Ub.release(); Wb.release(); Qb.release(); Q2b.release(); Tb.release();
     ready = false;
   }
   Blk<T> Z(int c0, int w) const { return Blk<T>{Zb.as<T>() + c0, ldz, w}; }
@@ -39,6 +40,7 @@ struct Blocks {
   Blk<T> W(int c0, int w) const { return Blk<T>{Wb.as<T>() + c0, ldz, w}; }
   Blk<T> Q(int w) const { return Blk<T>{Qb.as<T>(), ldq, w}; }
   Blk<T> Q2(int w) const { return Blk<T>{Q2b.as<T>(), ldq, w}; }
+  Blk<T> Tc() const { return Blk<T>{Tb.as<T>(), ldt, (int)ldt}; }
 };
 
 class Solver {
@@ -81,6 +83,11 @@ class Solver {
   Blocks<float> B32_;
   Work wk_;
   DevBuf desc_, mu_, outv_, x0_;
+  // the returned eigenvectors (n x k, leading dimension outv_ld_): outv_, or
+  // in the lean-memory mode a free block of the solve
+  double *outv_p_ = nullptr;
+  int64_t outv_ld_ = 0;
+  bool lean_ = false;
   DevBuf lz_V_, lz_w_, lz_h_, lz_part_;  // Lanczos basis and scratch
   bool have_x0_ = false, device_ready_ = false, host_results_ = false;
   int64_t ldz_ = 0, ldq_ = 0;
@@ -104,9 +111,11 @@ class Solver {
   void setup_interval();
   template <typename T>
   int outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage);
+  // free: a block of the solve not holding any source (n x ldz, T); in the
+  // lean-memory mode it receives the output vectors
   template <typename T>
   double finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src, const std::vector<int64_t> &lds,
-                const std::vector<int32_t> &cols, const std::vector<double> &mu);
+                const std::vector<int32_t> &cols, const std::vector<double> &mu, T *free);
   template <typename T>
   void poly_hook(Blk<T> X);
   template <typename T>

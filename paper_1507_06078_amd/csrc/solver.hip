@@ -97,6 +97,9 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
               "unknown polynomial form");
   ARR_REQUIRE(o.row_form >= ARR_ROW_AUTO && o.row_form <= ARR_ROW_GRID,
               "unknown row form");
+  ARR_REQUIRE(o.lean_memory == 0 || o.lean_memory == 1, "lean_memory must be 0 or 1");
+  ARR_REQUIRE(o.lean_memory == 0 || o.inner_solver == ARR_INNER_MPM, "the lean-memory mode needs the MPM inner solver");
+  lean_ = o.lean_memory != 0;
   // validate CSR on the host
   const int64_t *rp = csr->rowptr;
   ARR_REQUIRE(rp[0] == 0 && rp[n] == csr->nnz, "rowptr[0] must be 0 and rowptr[n] must equal nnz");
@@ -151,15 +154,25 @@ size_t Solver::device_plan(bool allocate) {
     take(coef32_, sizeof(float) * 8 * n);
     if (no) take(oval32_, sizeof(float) * no);
   }
-  for (DevBuf *b : {&B64_.Zb, &B64_.Ub, &B64_.Wb}) take(*b, sizeof(double) * n * ldz_);
+  // lean: no A U block (chunks of ldt columns instead) and no output block
+  const int64_t ldt64 = std::min<int64_t>(ldz_, 256), ldt32 = std::min<int64_t>(ldz_, 512);
+  for (DevBuf *b : {&B64_.Zb, &B64_.Ub}) take(*b, sizeof(double) * n * ldz_);
+  if (lean_)
+    take(B64_.Tb, sizeof(double) * n * ldt64);
+  else
+    take(B64_.Wb, sizeof(double) * n * ldz_);
   for (DevBuf *b : {&B64_.Qb, &B64_.Q2b}) take(*b, sizeof(double) * n * ldq_);
   if (mixed) {
-    for (DevBuf *b : {&B32_.Zb, &B32_.Ub, &B32_.Wb}) take(*b, sizeof(float) * n * ldz_);
+    for (DevBuf *b : {&B32_.Zb, &B32_.Ub}) take(*b, sizeof(float) * n * ldz_);
+    if (lean_)
+      take(B32_.Tb, sizeof(float) * n * ldt32);
+    else
+      take(B32_.Wb, sizeof(float) * n * ldz_);
     for (DevBuf *b : {&B32_.Qb, &B32_.Q2b}) take(*b, sizeof(float) * n * ldq_);
   }
   take(mu_, sizeof(double) * ldz_);
   take(desc_, (sizeof(void *) + sizeof(int64_t) + sizeof(int32_t)) * (size_t)ldz_ + 64);
-  take(outv_, sizeof(double) * n * k_);
+  if (!lean_) take(outv_, sizeof(double) * n * k_);
   if (have_x0_) take(x0_, sizeof(double) * n * w_);
   const int L = lanczos_L_;
   take(lz_V_, sizeof(double) * n * L);
@@ -203,14 +216,16 @@ void Solver::ensure_device() {
   B64_.ldq = ldq_;
   B32_.ldz = ldz_;
   B32_.ldq = ldq_;
+  B64_.ldt = lean_ ? std::min<int64_t>(ldz_, 256) : 0;
+  B32_.ldt = lean_ ? std::min<int64_t>(ldz_, 512) : 0;
   ARR_HIP(hipStreamSynchronize(s_));
   device_ready_ = true;
 }
 
 void Solver::release_device() {
   if (s_) ARR_HIP(hipStreamSynchronize(s_));
-  for (DevBuf *b : {&coef64_, &coef32_, &fcol_, &orp_, &ocol_, &oval64_, &oval32_, &B64_.Zb, &B64_.Ub, &B64_.Wb, &B64_.Qb, &B64_.Q2b, &B32_.Zb,
-                    &B32_.Ub, &B32_.Wb, &B32_.Qb, &B32_.Q2b, &mu_, &desc_, &outv_, &x0_, &lz_V_, &lz_w_, &lz_h_,
+  for (DevBuf *b : {&coef64_, &coef32_, &fcol_, &orp_, &ocol_, &oval64_, &oval32_, &B64_.Zb, &B64_.Ub, &B64_.Wb, &B64_.Qb, &B64_.Q2b,
+                    &B64_.Tb, &B32_.Zb, &B32_.Ub, &B32_.Wb, &B32_.Qb, &B32_.Q2b, &B32_.Tb, &mu_, &desc_, &outv_, &x0_, &lz_V_, &lz_w_, &lz_h_,
                     &lz_part_, &wk_.partial, &wk_.colv, &wk_.gramw, &wk_.small, &wk_.proj, &wk_.info, &wk_.jac.bufA,
                     &wk_.jac.bufB, &wk_.jac.bufV, &wk_.jac.bufOff, &wk_.jac.bufEval})
     b->release();
@@ -222,7 +237,8 @@ void Solver::stash_results(bool keep_vectors) {
   if (!solved) return;
   if (keep_vectors) {
     h_vecs_.resize((size_t)n_ * k_);
-    ARR_HIP(hipMemcpy(h_vecs_.data(), outv_.p, sizeof(double) * n_ * k_, hipMemcpyDeviceToHost));
+    ARR_HIP(hipMemcpy2D(h_vecs_.data(), sizeof(double) * k_, outv_p_, sizeof(double) * outv_ld_, sizeof(double) * k_,
+                        n_, hipMemcpyDeviceToHost));
   } else {
     h_vecs_.clear();
   }
@@ -308,8 +324,8 @@ void Solver::setup_interval() {
   Blocks<double> &B = B64_;
   launch_copy<double>(n, w_, B.Ub.as<double>(), B.ldz, B.Zb.as<double>(), B.ldz, s_);
   const Blk<const double> none{nullptr, 0, 0};
-  Blk<double> U = orthonormalize<double>(n, B.U(0, w_), B.W(0, w_), none, wk_, s_, nullptr);
-  Blk<double> Wt = (U.p == B.Ub.as<double>()) ? B.W(0, w_) : B.U(0, w_);
+  Blk<double> U = orthonormalize<double>(n, B.U(0, w_), B.U(w_, w_), none, wk_, s_, nullptr);
+  Blk<double> Wt = (U.p == B.Ub.as<double>()) ? B.U(w_, w_) : B.U(0, w_);
   std::vector<double> ev;
   rayleigh_ritz<double>(A64_, n, Blk<const double>{U.p, U.ld, w_}, Wt, wk_, ev, s_);
   b_ = ev[w_ - 1];
@@ -362,22 +378,40 @@ void Solver::gather(int64_t n, int w, T *dst, int64_t lddst, const std::vector<c
 // reads before writing, so the iteration may continue after it.
 template <typename T>
 double Solver::finish(Blocks<T> &B, const DevCSR<T> &A, const std::vector<const T *> &src,
-                      const std::vector<int64_t> &lds, const std::vector<int32_t> &cols, const std::vector<double> &mu) {
+                      const std::vector<int64_t> &lds, const std::vector<int32_t> &cols, const std::vector<double> &mu,
+                      T *free) {
   (void)A;
   const int64_t n = n_;
   const int k = k_;
   std::vector<const T *> s(src.begin(), src.begin() + k);
   std::vector<int64_t> l(lds.begin(), lds.begin() + k);
   std::vector<int32_t> c(cols.begin(), cols.begin() + k);
-  if (std::is_same<T, double>::value) {
-    gather<T>(n, k, reinterpret_cast<T *>(outv_.p), k, s, l, c);
+  // lean: the vectors in columns [0, k) of a free FP64 block, A X in [k, 2k)
+  // (ld >= 2 w >= 2 k); otherwise the output block and the W block
+  const bool fp64 = std::is_same<T, double>::value;
+  double *AXp;
+  int64_t ldax;
+  if (lean_) {
+    outv_p_ = fp64 ? reinterpret_cast<double *>(free) : B64_.Ub.as<double>();
+    outv_ld_ = ldz_;
+    AXp = outv_p_ + k;
+    ldax = ldz_;
   } else {
-    gather<T>(n, k, B.W(0, k).p, B.ldz, s, l, c);
-    launch_convert<double, T>(n, k, outv_.as<double>(), k, B.W(0, k).p, B.ldz, s_);
+    outv_p_ = outv_.as<double>();
+    outv_ld_ = k;
+    AXp = B64_.Wb.as<double>();
+    ldax = ldz_;
+  }
+  if (fp64) {
+    gather<T>(n, k, reinterpret_cast<T *>(outv_p_), outv_ld_, s, l, c);
+  } else {
+    T *stage = lean_ ? free : B.W(0, k).p;
+    gather<T>(n, k, stage, B.ldz, s, l, c);
+    launch_convert<double, T>(n, k, outv_p_, outv_ld_, stage, B.ldz, s_);
   }
   // explicit FP64 residuals
-  Blk<double> X{outv_.as<double>(), k, k};
-  Blk<double> AX = B64_.W(0, k);
+  Blk<double> X{outv_p_, outv_ld_, k};
+  Blk<double> AX{AXp, ldax, k};
   const Blk<const double> none{nullptr, 0, 0};
   launch_filter_spmm<double>(A64_, Blk<const double>{X.p, X.ld, k}, none, AX, 1.0, 0.0, 0.0, nullptr, s_);
   ARR_HIP(hipMemcpyAsync(mu_.p, mu.data(), sizeof(double) * k, hipMemcpyHostToDevice, s_));
@@ -443,7 +477,8 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     // a NaN or Inf column norm restores it, renormalizes and restarts the
     // inner loop at half the degree, once per outer iteration.
     const bool mpm = o_.inner_solver != ARR_INNER_GN;
-    if (mpm) launch_copy<T>(n, wp_, B.W(0, wp_).p, B.ldz, X.p, X.ld, s_);
+    const Blk<T> snap = lean_ ? B.Z(wp_, wp_) : B.W(0, wp_);  // Z's Krylov columns are free here
+    if (mpm) launch_copy<T>(n, wp_, snap.p, snap.ld, X.p, X.ld, s_);
     int retries = 0;
   restart_inner:
     const FilterPoly &g = coeffs(d_);
@@ -493,7 +528,7 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
         ++retries;
         stats.nan_retries += 1;
         d_ = std::max(1, d_ / 2);
-        launch_copy<T>(n, wp_, X.p, X.ld, B.W(0, wp_).p, B.ldz, s_);
+        launch_copy<T>(n, wp_, X.p, X.ld, snap.p, snap.ld, s_);
         normalize<T>(n, X, wk_, s_);
         if (nc_) project_out<T>(n, Qc, X, wk_, s_);
         goto restart_inner;
@@ -526,7 +561,10 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     Blk<T> U = orthonormalize<T>(n, B.Z(0, m), B.U(0, m), Qc, wk_, s_, nullptr, &rinv);
     Blk<T> Pfree = (U.p == B.Zb.template as<T>()) ? B.U(0, m) : B.Z(0, m);
     std::vector<double> ritz;
-    rayleigh_ritz<T>(A, n, Blk<const T>{U.p, U.ld, m}, B.W(0, m), wk_, ritz, s_, rinv);
+    if (lean_)
+      rayleigh_ritz_chunked<T>(A, n, Blk<const T>{U.p, U.ld, m}, B.Tc(), wk_, ritz, s_, rinv);
+    else
+      rayleigh_ritz<T>(A, n, Blk<const T>{U.p, U.ld, m}, B.W(0, m), wk_, ritz, s_, rinv);
     stats.t_dense += now() - td;
     stats.arr_calls += 1;
     stats.arr_m2 += (double)m * m;
@@ -544,7 +582,13 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     Blk<T> Xn{Pfree.p, Pfree.ld, cnew};
     launch_update<T>(n, Blk<const T>{U.p, U.ld, m}, V, m, cnew, 1.0, 0.0, Xn, s_, false, /*fp32_cores=*/true);
     Blk<T> AXn{U.p, U.ld, cnew};
-    launch_update<T>(n, Blk<const T>{B.W(0, m).p, B.ldz, m}, V, m, cnew, 1.0, 0.0, AXn, s_, false, /*fp32_cores=*/true);
+    if (lean_) {
+      const Blk<const T> none{nullptr, 0, 0};
+      launch_filter_spmm<T>(A, Blk<const T>{Xn.p, Xn.ld, cnew}, none, AXn, 1.0, 0.0, 0.0, nullptr, s_);
+    } else {
+      launch_update<T>(n, Blk<const T>{B.W(0, m).p, B.ldz, m}, V, m, cnew, 1.0, 0.0, AXn, s_, false,
+                       /*fp32_cores=*/true);
+    }
     ARR_HIP(hipMemcpyAsync(mu_.p, ritz.data(), sizeof(double) * cnew, hipMemcpyHostToDevice, s_));
     std::vector<double> rnew = residual_norms<T>(n, Blk<const T>{AXn.p, AXn.ld, cnew},
                                                  Blk<const T>{Xn.p, Xn.ld, cnew}, mu_.as<double>(), wk_, s_);
@@ -609,7 +653,7 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       if (status < 0 && j_ == o_.maxit) status = ARR_NOT_CONVERGED;
     }
     if (status >= 0) {
-      const double explicit_max = finish<T>(B, A, src, lds, cols, mu);
+      const double explicit_max = finish<T>(B, A, src, lds, cols, mu, U.p);
       // an accepted result must also pass the explicit FP64 check; if it does
       // not, iterate on (or report the result as not converged at maxit)
       if (status == ARR_OK && !(explicit_max <= accept)) status = j_ < o_.maxit ? -1 : ARR_NOT_CONVERGED;
@@ -644,10 +688,15 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       }
     }
     const int nc_new = (int)qs.size(), wp_new = (int)xs.size();
-    // new X -> W scratch, then into Z; new Qc -> Q2, then swap Q / Q2
-    gather<T>(n, wp_new, B.W(0, wp_new).p, B.ldz, xs, xl, xcol);
+    // new X -> a scratch block, then into Z; new Qc -> Q2, then swap Q / Q2.
+    // The scratch is W, or in the lean mode the block that held the basis and
+    // A X_new (both dead now; the sources are X_new and Q): when that block is
+    // Z itself the new X goes there directly.
+    T *scratch = lean_ ? U.p : B.W(0, wp_new).p;
+    gather<T>(n, wp_new, scratch, B.ldz, xs, xl, xcol);
     gather<T>(n, nc_new, B.Q2b.template as<T>(), B.ldq, qs, ql, qcol);
-    launch_copy<T>(n, wp_new, B.Zb.template as<T>(), B.ldz, B.W(0, wp_new).p, B.ldz, s_);
+    if (scratch != B.Zb.template as<T>())
+      launch_copy<T>(n, wp_new, B.Zb.template as<T>(), B.ldz, scratch, B.ldz, s_);
     std::swap(B.Qb, B.Q2b);
     nc_ = nc_new;
     wp_ = wp_new;
@@ -666,7 +715,7 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       std::vector<int64_t> l2;
       std::vector<int32_t> c2;
       for (int q = 0; q < nc_; ++q) { s2.push_back(B.Qb.template as<T>()); l2.push_back(B.ldq); c2.push_back(q); }
-      const double explicit_max = finish<T>(B, A, s2, l2, c2, sig_c_);
+      const double explicit_max = finish<T>(B, A, s2, l2, c2, sig_c_, B.Ub.template as<T>());
       stats.final_p = p_;
       stats.final_d = d_;
       stats.n_locked = nc_;
@@ -810,7 +859,7 @@ void Solver::get(double *evals, double *evecs, int64_t ldv, double *resid) {
       ARR_REQUIRE(!h_vecs_.empty(), "eigenvectors were not kept for this served request (keep_vectors = 0)");
       for (int64_t i = 0; i < n_; ++i) std::copy(&h_vecs_[i * k], &h_vecs_[i * k] + k, evecs + i * ldv);
     } else {
-      ARR_HIP(hipMemcpy2D(evecs, sizeof(double) * ldv, outv_.p, sizeof(double) * k, sizeof(double) * k, n_,
+      ARR_HIP(hipMemcpy2D(evecs, sizeof(double) * ldv, outv_p_, sizeof(double) * outv_ld_, sizeof(double) * k, n_,
                           hipMemcpyDeviceToHost));
     }
     // sign convention: the entry of largest magnitude is positive

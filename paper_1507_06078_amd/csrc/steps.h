@@ -78,6 +78,12 @@ Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk
 template <typename T>
 void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work &wk, std::vector<double> &evals,
                    hipStream_t s, const double *rinv = nullptr);
+// The same with A U formed in column chunks of Tbuf.w columns (Tbuf: n x
+// Tbuf.w scratch) instead of a whole n x m block: H's columns c are
+// U^T (A U[:, c]); H is then symmetrized. For the lean-memory mode.
+template <typename T>
+void rayleigh_ritz_chunked(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> Tbuf, Work &wk,
+                           std::vector<double> &evals, hipStream_t s, const double *rinv = nullptr);
 template <typename T>
 std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, const double *mu_dev, Work &wk,
                                    hipStream_t s);

@@ -327,20 +327,13 @@ Blk<T> orthonormalize(int64_t n, Blk<T> Z, Blk<T> Zalt, Blk<const T> Q, Work &wk
   return cur;
 }
 
-template <typename T>
-void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work &wk, std::vector<double> &evals,
-                   hipStream_t s, const double *rinv) {
-  const int m = U.w;
-  const Blk<const T> none{nullptr, 0, 0};
-  launch_filter_spmm<T>(A, U, none, W, 1.0, 0.0, 0.0, nullptr, s);
-  wk.ensure_gram(n, m, m);
-  wk.ensure_small(m);
+// Eigendecomposition of the m x m Rayleigh quotient H (wk.small) with the
+// closing Cholesky-QR factor folded in (see rayleigh_ritz).
+static void ritz_from_h(int m, Work &wk, std::vector<double> &evals, hipStream_t s, const double *rinv) {
   const size_t mm = (size_t)m * m;
   double *H = wk.small.as<double>();
   double *V = H + mm;
   double *T1 = V + mm + 64;  // below the factor rinv (last m^2 of wk.small)
-  // H = U^T (A U) is symmetric: form its upper tiles and mirror them
-  launch_gram<T>(n, U, Blk<const T>{W.p, W.ld, m}, H, wk.gramw.as<double>(), true, s, /*fp32_cores=*/true);
   // the m x m products below run on the FP64 matrix cores as products with m
   // rows (R^{-1} is upper triangular)
   const Blk<const double> R{rinv, m, m};
@@ -356,6 +349,56 @@ void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work
     launch_update<double>(m, R, V, m, m, 1.0, 0.0, Blk<double>{T1, m, m}, s, false);
     launch_copy<double>(m, m, V, m, T1, m, s);
   }
+}
+
+template <typename T>
+void rayleigh_ritz(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> W, Work &wk, std::vector<double> &evals,
+                   hipStream_t s, const double *rinv) {
+  const int m = U.w;
+  const Blk<const T> none{nullptr, 0, 0};
+  launch_filter_spmm<T>(A, U, none, W, 1.0, 0.0, 0.0, nullptr, s);
+  wk.ensure_gram(n, m, m);
+  wk.ensure_small(m);
+  // H = U^T (A U) is symmetric: form its upper tiles and mirror them
+  launch_gram<T>(n, U, Blk<const T>{W.p, W.ld, m}, wk.small.as<double>(), wk.gramw.as<double>(), true, s,
+                 /*fp32_cores=*/true);
+  ritz_from_h(m, wk, evals, s, rinv);
+}
+
+__global__ __launch_bounds__(256) void k_symmetrize(int m, double *__restrict__ H) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int i = (int)(idx / m), j = (int)(idx % m);
+  if (i < j) {
+    const double v = 0.5 * (H[(int64_t)i * m + j] + H[(int64_t)j * m + i]);
+    H[(int64_t)i * m + j] = v;
+    H[(int64_t)j * m + i] = v;
+  }
+}
+
+template <typename T>
+void rayleigh_ritz_chunked(const DevCSR<T> &A, int64_t n, Blk<const T> U, Blk<T> Tbuf, Work &wk,
+                           std::vector<double> &evals, hipStream_t s, const double *rinv) {
+  const int m = U.w, cw = Tbuf.w;
+  ARR_REQUIRE(cw > 0, "chunked Rayleigh-Ritz: empty chunk buffer");
+  const Blk<const T> none{nullptr, 0, 0};
+  wk.ensure_small(m);
+  const size_t mm = (size_t)m * m;
+  double *H = wk.small.as<double>();
+  // the column block U^T (A U[:, c0:c0+c]) is formed in V's place (free until
+  // the eigensolve) and copied into H's columns
+  double *Gc = H + mm;
+  for (int c0 = 0; c0 < m; c0 += cw) {
+    const int c = std::min(cw, m - c0);
+    Blk<T> Tc{Tbuf.p, Tbuf.ld, c};
+    launch_filter_spmm<T>(A, U.cols(c0, c), none, Tc, 1.0, 0.0, 0.0, nullptr, s);
+    wk.ensure_gram(n, m, c);
+    launch_gram<T>(n, U, Blk<const T>{Tc.p, Tc.ld, c}, Gc, wk.gramw.as<double>(), false, s, /*fp32_cores=*/true);
+    launch_copy<double>(m, c, H + c0, m, Gc, c, s);
+  }
+  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, m, H);
+  ARR_HIP(hipGetLastError());
+  ritz_from_h(m, wk, evals, s, rinv);
 }
 
 template <typename T>
@@ -388,6 +431,8 @@ std::vector<double> residual_norms(int64_t n, Blk<const T> AX, Blk<const T> X, c
                                     const double **);                                                           \
   template void rayleigh_ritz<T>(const DevCSR<T> &, int64_t, Blk<const T>, Blk<T>, Work &, std::vector<double> &, \
                                  hipStream_t, const double *);                                                   \
+  template void rayleigh_ritz_chunked<T>(const DevCSR<T> &, int64_t, Blk<const T>, Blk<T>, Work &,              \
+                                         std::vector<double> &, hipStream_t, const double *);                   \
   template std::vector<double> residual_norms<T>(int64_t, Blk<const T>, Blk<const T>, const double *, Work &,    \
                                                  hipStream_t);
 ARR_INST(double)

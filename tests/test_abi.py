@@ -190,3 +190,25 @@ def test_stats_struct_matches_header():
             parts = decl.split(None, 1)[1]
             names += [x.strip().lstrip("*") for x in parts.split(",")]
         assert names == [f for f, _ in pyt._fields_], cname
+
+
+def test_lean_memory_footprint_and_checks():
+    """Lean-memory mode: the footprint drops by the A U block (n ldz values)
+    and the output block (n k) and grows by the chunk buffer (n min(ldz,
+    256)); it needs the MPM inner solver."""
+    A = W.laplacian_2d(40)
+    o = arr.arr_options_default()
+    o.w = 30
+    h0 = arr.arr_create(A, A.n, 20, arr.SMALLEST, 1e-10, o)
+    o.lean_memory = 1
+    h1 = arr.arr_create(A, A.n, 20, arr.SMALLEST, 1e-10, o)
+    n, ldz = A.n, 120
+    d = arr.arr_footprint(h0) - arr.arr_footprint(h1)
+    expect = 8 * n * (ldz + 20) - 8 * n * min(ldz, 256)
+    assert abs(d - expect) <= 2 * 256
+    h0.close()
+    h1.close()
+    o.inner_solver = arr.INNER_GN
+    with pytest.raises(arr.ArrError) as e:
+        arr.arr_create(A, A.n, 20, arr.SMALLEST, 1e-10, o)
+    assert e.value.code == arr.ARR_EINVAL

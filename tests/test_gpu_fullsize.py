@@ -15,6 +15,8 @@ the solver uses there.
 
 Device inputs come from torch's seeded generator; the CPU references use
 only the sampled rows read back from the device."""
+import os
+
 import numpy as np
 import pytest
 
@@ -25,6 +27,20 @@ from paper_1507_06078_amd import arr, workloads as W
 
 U32 = 2.0 ** -24
 U64 = 2.0 ** -53
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def oracle_fixture(name):
+    """Eigenvalues written by tests/golden/make_eigen_fixtures.py (the oracle's
+    Algorithm 8 at tol 1e-12, with a spectrum-slicing check that no eigenvalue
+    below the k-th was skipped)."""
+    path = os.path.join(GOLDEN, f"eig_{name}.txt")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle fixture {path} not generated")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return np.array([float(r[1]) for r in rows])
 
 
 @pytest.fixture(scope="module")
@@ -67,6 +83,44 @@ def test_lap3d_full_solve_properties(lap3d, precision):
     elif "ev" in _fp64_evals:
         ref = _fp64_evals["ev"]
         assert np.all(np.abs(ev - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref)))
+
+
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+def test_lap3d_full_solve_matches_oracle(lap3d, precision):
+    """The 200 smallest eigenvalues of the 1e6-row benchmark matrix against
+    the oracle's (computed from another starting block at tol 1e-12, and
+    checked complete by spectrum slicing): |dlambda| <= 1e-10 max(1, |lambda|)
+    (reading R23)."""
+    ref = oracle_fixture("lap3d100")
+    st, ev, X, res = _solve(lap3d, precision)
+    assert st == arr.ARR_OK
+    assert ref.shape == ev.shape
+    assert np.all(np.abs(ev - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref))), np.abs(ev - ref).max()
+
+
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+@pytest.mark.parametrize("name,make,k,which,w", [
+    ("powerlaw1e5", lambda: W.powerlaw_random(100_000, seed=1), 100, "LA", 120),
+    ("sbm1e5", lambda: W.sbm_normalized_laplacian(64 * 1563, 64, seed=1), 100, "SA", 120),
+])
+def test_scaled_down_workloads_match_oracle(name, make, k, which, w, precision):
+    """Down-scaled instances (n about 1e5) of the power-law and SBM workloads,
+    from the same generators: the k extreme eigenvalues against the oracle's
+    fixture, residuals <= 1e-10 recomputed on the CPU."""
+    ref = oracle_fixture(name)
+    A = make()
+    o = arr.arr_options_default()
+    o.w = w
+    o.precision = precision
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, 1e-10, o)
+    st = arr.arr_solve(h)
+    ev, X, res = arr.arr_get_eigpairs(h, k, A.n)
+    h.close()
+    assert st == arr.ARR_OK
+    assert np.all(np.abs(ev - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref))), np.abs(ev - ref).max()
+    S = A.to_scipy()
+    r = np.linalg.norm(S @ X - X * ev[None, :], axis=0)
+    assert np.all(r / np.maximum(1.0, np.abs(ev)) <= 1e-10 * 1.0001)
 
 
 def _device_block(n, w, dtype, seed):

@@ -339,3 +339,38 @@ def test_nonfinite_guard_gives_up_with_breakdown():
         arr.arr_solve(h)
     h.close()
     assert e.value.code == arr.ARR_EBREAKDOWN and "non-finite" in str(e.value)
+
+
+@pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
+@pytest.mark.parametrize("case", ["lap2d_40", "lap3d_14V", "powerlaw_3000"])
+def test_lean_memory_mode_matches_default(case, precision):
+    """The lean-memory mode (Rayleigh quotient from column chunks, A X of the
+    new Ritz vectors by an extra SpMM, output vectors in a free block) finds
+    the same eigenpairs as the default mode and the dense/closed-form
+    reference, with a smaller device footprint."""
+    if case == "lap2d_40":
+        A, k, which, w, tol = W.workload("lap2d_40")
+        exact = W.laplacian_2d_eigenvalues(40)[:k]
+    elif case == "lap3d_14V":
+        A, k, which, w, tol = W.laplacian_3d(14, potential_seed=3), 30, "SA", 40, 1e-10
+        exact = np.linalg.eigvalsh(A.to_scipy().toarray())[:k]
+    else:
+        A, k, which, w, tol = W.powerlaw_random(3000, seed=5, cap=400), 40, "LA", 50, 1e-10
+        exact = np.linalg.eigvalsh(A.to_scipy().toarray())[::-1][:k]
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    st0, ev0, X0v, res0, _ = solve(A, k, which, tol, w=w, precision=precision, X0=X0)
+    st1, ev1, X1v, res1, s1 = solve(A, k, which, tol, w=w, precision=precision, X0=X0, lean_memory=1)
+    assert st0 == arr.ARR_OK and st1 == arr.ARR_OK, s1
+    scale = np.maximum(1.0, np.abs(exact))
+    assert np.all(np.abs(ev1 - exact) <= 1e-10 * scale)
+    assert np.all(np.abs(ev1 - ev0) <= 1e-10 * scale)
+    check_pairs(A, ev1, X1v, tol)
+    o = arr.arr_options_default()
+    o.w = w
+    o.precision = precision
+    h0 = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, tol, o)
+    o.lean_memory = 1
+    h1 = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, tol, o)
+    assert arr.arr_footprint(h1) < arr.arr_footprint(h0)
+    h0.close()
+    h1.close()
