@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("3D 7-point Laplacian 100^3 + U[0,1) diagonal potential (seed 1), n=1e6, nnz=6.94e6, "
             "k=200 smallest, block 240, tol 1e-10")
+WORKLOAD_SBM = ("normalized Laplacian of a stochastic block model graph, n=4e6, 64 blocks of 62500, average degree "
+                "20, p_in/p_out 10 (seed 1), k=1000 smallest, block 1200, tol 1e-10")
 WORKLOAD_POWERLAW = ("random symmetric, power-law row lengths (Pareto alpha 2.1, mean 16, cap 2048; seed 1), n=2e6, "
                      "off-diagonal N(0,1), diagonal N(0,4), k=500 largest, block 600, tol 1e-10")
 
@@ -254,10 +256,15 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     o.poly_form = {"product": arr.POLY_PRODUCT, "horner": arr.POLY_HORNER, "chebyshev": arr.POLY_CHEBYSHEV}[args.poly]
     o.row_form = {"auto": arr.ROW_AUTO, "plain": arr.ROW_PLAIN, "paired": arr.ROW_PAIRED,
                   "grid": arr.ROW_GRID}[args.row_form]
+    o.lean_memory = 1 if args.lean else 0
+    if args.p_max is not None:
+        o.p_max = args.p_max
+        o.p0 = min(o.p0, args.p_max)
     torch.cuda.synchronize()
     tc0 = time.perf_counter()
     h = arr.arr_create(A, A.n, k, arr.SMALLEST if which == "SA" else arr.LARGEST, tol, o)
-    print(f"[bench] {label}: handle ready (n={A.n}, nnz={A.nnz}); warmup {args.warmup}, steps {args.steps}",
+    print(f"[bench] {label}: handle ready (n={A.n}, nnz={A.nnz}, device footprint "
+          f"{arr.arr_footprint(h) / 1e9:.1f} GB); warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     cold_ms = None
     for i in range(args.warmup):
@@ -369,8 +376,12 @@ def main():
     ap.add_argument("--row-form", choices=["auto", "plain", "paired", "grid"], default="auto",
                     help="SpMM row form: automatic (grid form for 2D grids, else paired where the matrix "
                          "allows it), plain, paired (never grid), or grid wherever it applies")
-    ap.add_argument("--workload", choices=["lap3d100", "powerlaw2e6"], default="lap3d100",
-                    help="lap3d100: the headline workload; powerlaw2e6: the 2e6-row power-law graph")
+    ap.add_argument("--workload", choices=["lap3d100", "powerlaw2e6", "sbm4e6"], default="lap3d100",
+                    help="lap3d100: the headline workload; powerlaw2e6: the 2e6-row power-law graph; sbm4e6: "
+                         "the 4e6-row SBM normalized Laplacian (k=1000, block 1200; needs --lean --p-max 1 "
+                         "to fit 288 GB in FP64)")
+    ap.add_argument("--lean", action="store_true", help="lean-memory mode (no A U block)")
+    ap.add_argument("--p-max", type=int, default=None, help="largest number of augmentation blocks (default 3)")
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -413,6 +424,12 @@ def main():
     if args.workload == "powerlaw2e6":
         A = W.powerlaw_random(2_000_000, seed=1)
         k, w, tol, which, workload = 500, 600, 1e-10, "LA", WORKLOAD_POWERLAW
+    elif args.workload == "sbm4e6":
+        print("[bench] building the SBM matrix", file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        A = W.sbm_normalized_laplacian(4_000_000, 64, seed=1)
+        print(f"[bench] SBM matrix built in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+        k, w, tol, which, workload = 1000, 1200, 1e-10, "SA", WORKLOAD_SBM
     else:
         A = W.laplacian_3d(100, potential_seed=1)
         k, w, tol, which, workload = 200, 240, 1e-10, "SA", WORKLOAD
@@ -432,7 +449,8 @@ def main():
         "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": workload, "precision": head_prec, "inner_solver": args.inner, "filter": args.poly,
-                   "row_form": args.row_form},
+                   "row_form": args.row_form, "lean_memory": bool(args.lean),
+                   "p_max": args.p_max if args.p_max is not None else 3},
         "converged": head["converged"],
         "max_res": head["max_res"],
         "cold_start_ms": head["cold_start_ms"],
@@ -441,7 +459,24 @@ def main():
         "gemm": head["gemm"],
         "solve": head["solve"],
     }
-    if args.precision == "both":
+    if args.workload == "sbm4e6":
+        # properties that hold at any size (the oracle does not run here):
+        # spectrum of the normalized Laplacian in [0, 2], eigenvalue 0 once per
+        # connected component (an isolated vertex is a component with L_ii = 1,
+        # eigenvalue 1), residuals in both scalings
+        from scipy.sparse.csgraph import connected_components
+        S = A.to_scipy()
+        ncomp, labels = connected_components(S, directed=False)
+        sizes = np.bincount(labels)
+        ev = head["eigenvalues"]
+        out["invariants"] = {
+            "eigenvalue_min": float(ev.min()), "eigenvalue_max": float(ev.max()),
+            "in_0_2": bool(ev.min() > -1e-10 and ev.max() < 2.0),
+            "connected_components_nontrivial": int((sizes > 1).sum()),
+            "eigenvalues_below_1e-10": int((np.abs(ev) < 1e-10).sum()),
+            "max_res_eq_resi": head["max_res"], "max_res_norm_a": head["solve"]["maxres_norm_a"],
+        }
+    if args.precision == "both" and args.workload != "sbm4e6":
         mix = solve_run(A, k, w, tol, "mixed", args, "mixed", which)
         rel = np.abs(mix["eigenvalues"] - head["eigenvalues"]) / np.abs(head["eigenvalues"])
         out["mixed"] = {
