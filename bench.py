@@ -41,6 +41,23 @@ def _blas_threads():
         return None
 
 
+def oracle_eigenvalues(name):
+    """Eigenvalues of a committed oracle fixture (tests/golden/eig_<name>.txt,
+    written by tests/golden/make_eigen_fixtures.py), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"eig_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return np.array([float(r[1]) for r in rows])
+
+
+def eig_error(ev, ref):
+    """max_i |ev_i - ref_i| / max(1, |ref_i|)."""
+    import numpy as np
+    return float(np.max(np.abs(np.asarray(ev) - ref) / np.maximum(1.0, np.abs(ref))))
+
+
 def oracle_c2_fixture():
     """Header facts of the committed oracle fixture of the benchmark workload
     (a full oracle solve at tol 1e-12, timed where it was generated)."""
@@ -196,7 +213,7 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_spmm_lap3d100_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_spmm_traffic.md")
 SPMM_SOURCE = os.path.join(ROOT, "paper_1507_06078_amd", "csrc", "spmm.hip")
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
@@ -283,6 +300,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ev, _, res = arr.arr_get_eigpairs(h, k, A.n, vectors=False)
+    ev32 = arr.arr_get_fp32_stage_values(h, k) if precision == "mixed" else None
     h.close()
     sec = (t1 - t0) / args.steps
     ok = all(s["status"] == 0 for s in stats) and float(res.max()) <= tol
@@ -313,6 +331,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     return {
         "cold_start_ms": cold_ms,
         "fp32_stage_maxres": last["fp32_maxres"] if precision == "mixed" else None,
+        "fp32_stage_eigenvalues": ev32,
         "roofline_fp32_stage": roof32,
         "value": (k / sec) if ok else 0.0, "ms_per_step": sec * 1e3, "converged": ok,
         "max_res": float(res.max()), "eigenvalues": ev,
@@ -453,6 +472,7 @@ def main():
                    "p_max": args.p_max if args.p_max is not None else 3},
         "converged": head["converged"],
         "max_res": head["max_res"],
+        "fp32_stage_maxres": head["fp32_stage_maxres"],
         "cold_start_ms": head["cold_start_ms"],
         "roofline": head["roofline"],
         "roofline_fp32_stage": head["roofline_fp32_stage"],
@@ -483,10 +503,24 @@ def main():
             "value": mix["value"], "ms_per_step": mix["ms_per_step"], "dtype": "f32+f64",
             "speedup_vs_fp64": head["ms_per_step"] / mix["ms_per_step"], "converged": mix["converged"],
             "max_res": mix["max_res"], "max_rel_eig_diff_vs_fp64_path": float(rel.max()),
-            "fp32_stage_maxres": mix["fp32_stage_maxres"], "cold_start_ms": mix["cold_start_ms"],
+            "fp32_stage_maxres": mix["fp32_stage_maxres"],
+            "fp32_stage_max_rel_eig_diff_vs_fp64_path": eig_error(mix["fp32_stage_eigenvalues"], head["eigenvalues"]),
+            "cold_start_ms": mix["cold_start_ms"],
             "roofline": mix["roofline"], "roofline_fp32_stage": mix["roofline_fp32_stage"], "gemm": mix["gemm"],
             "solve": mix["solve"],
         }
+    ref = oracle_eigenvalues("lap3d100") if args.workload == "lap3d100" else None
+    if ref is not None:
+        # eigenvalue error against the oracle's own solve of this workload
+        # (tol 1e-12), scaled as max |dlambda| / max(1, |lambda|)
+        vo = {"fixture": "tests/golden/eig_lap3d100.txt", "bound": 1e-10,
+              head_prec: eig_error(head["eigenvalues"], ref)}
+        if "mixed" in out:
+            vo["mixed"] = eig_error(mix["eigenvalues"], ref)
+            vo["mixed_fp32_stage"] = eig_error(mix["fp32_stage_eigenvalues"], ref)
+        elif head_prec == "mixed":
+            vo["mixed_fp32_stage"] = eig_error(head["fp32_stage_eigenvalues"], ref)
+        out["eig_error_vs_oracle"] = vo
     out["accuracy_small_case"] = small_case_accuracy()
     if args.served_sample > 0 and args.workload == "lap3d100":
         # the served form: a bounded Poisson stream, mixed precision, and the
