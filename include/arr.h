@@ -290,6 +290,13 @@ int arr_get_eigpairs(arr_handle_t h, double *evals, double *evecs, int64_t ldv, 
  * r = A x - lambda x. ARR_ESTATE before a solve. */
 int arr_get_residuals(arr_handle_t h, double *resid, double *resid_norm_a, double *rnorm);
 
+/* ARR_MIXED: the k wanted Ritz values of the last FP32-stage outer iteration
+ * (the values handed to the FP64 stage, in the order of arr_get_eigpairs),
+ * into a host buffer of k values: what the FP32 filter stage of the mixed
+ * path alone reaches. ARR_ESTATE before a solve or when the solve had no FP32
+ * stage (ARR_FP64). */
+int arr_get_fp32_stage_values(arr_handle_t h, double *evals);
+
 int arr_get_stats(arr_handle_t h, arr_stats_t *s);
 const char *arr_last_error(arr_handle_t h);
 const char *arr_last_global_error(void);

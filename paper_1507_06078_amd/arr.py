@@ -101,7 +101,8 @@ class arr_stats_t(ctypes.Structure):
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
-           "arr_get_eigpairs", "arr_get_residuals", "arr_get_stats", "arr_last_error", "arr_last_global_error", "arr_destroy",
+           "arr_get_eigpairs", "arr_get_residuals", "arr_get_fp32_stage_values", "arr_get_stats", "arr_last_error",
+           "arr_last_global_error", "arr_destroy",
            "arr_filter_step", "arr_poly", "arr_filter", "arr_filter_roots", "arr_gn_step",
            "arr_filter_coefficients", "arr_gram", "arr_gram_noalloc", "arr_block_update",
            "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
@@ -130,6 +131,7 @@ def lib() -> ctypes.CDLL:
     L.arr_solve.argtypes = [vp]
     L.arr_get_eigpairs.argtypes = [vp, vp, vp, i64, vp]
     L.arr_get_residuals.argtypes = [vp, vp, vp, vp]
+    L.arr_get_fp32_stage_values.argtypes = [vp, vp]
     L.arr_get_stats.argtypes = [vp, P(arr_stats_t)]
     L.arr_last_error.argtypes = [vp]
     L.arr_last_error.restype = ctypes.c_char_p
@@ -268,6 +270,13 @@ def arr_get_residuals(h: Handle, k: int):
     out = [np.zeros(k) for _ in range(3)]
     _check(lib().arr_get_residuals(h.ptr, *(o.ctypes.data for o in out)), h.ptr)
     return tuple(out)
+
+
+def arr_get_fp32_stage_values(h: Handle, k: int) -> np.ndarray:
+    """The k Ritz values the FP32 stage of a mixed solve handed over."""
+    out = np.zeros(k)
+    _check(lib().arr_get_fp32_stage_values(h.ptr, out.ctypes.data), h.ptr)
+    return out
 
 
 def arr_get_stats(h: Handle) -> dict:

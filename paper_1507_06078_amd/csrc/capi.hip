@@ -279,6 +279,18 @@ int arr_get_residuals(arr_handle_t h, double *resid, double *resid_norm_a, doubl
   });
 }
 
+int arr_get_fp32_stage_values(arr_handle_t h, double *evals) {
+  if (!h || !evals) return ARR_EINVAL;
+  if (!h->s->solved || h->s->fp32_stage_values().empty()) {
+    h->err = h->s->solved ? "arr_get_fp32_stage_values: the solve had no FP32 stage"
+                          : "arr_get_fp32_stage_values called before arr_solve";
+    return ARR_ESTATE;
+  }
+  const std::vector<double> &v = h->s->fp32_stage_values();
+  std::copy(v.begin(), v.end(), evals);
+  return ARR_OK;
+}
+
 int arr_get_stats(arr_handle_t h, arr_stats_t *s) {
   if (!h || !s) return ARR_EINVAL;
   *s = h->s->stats;

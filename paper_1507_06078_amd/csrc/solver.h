@@ -53,6 +53,8 @@ class Solver {
   int solve();
   void get(double *evals, double *evecs, int64_t ldv, double *resid);
   void get_residuals(double *resid, double *resid_norm_a, double *rnorm);
+  // the k wanted Ritz values of the last FP32-stage iteration (empty if none)
+  const std::vector<double> &fp32_stage_values() const { return fp32_vals_; }
   // Device bytes ensure_device() allocates (every buffer of a solve).
   size_t footprint() const { return const_cast<Solver *>(this)->device_plan(false); }
   void ensure_device();
@@ -104,7 +106,7 @@ class Solver {
   std::vector<double> sig_c_, res_c_;
   double best_maxres_ = 0, maxresp_ = -1, best_mu_k_ = 0, best_mu_w_ = 0;
   int since_best_ = 0;
-  std::vector<double> out_vals_, out_res_, out_rn_;
+  std::vector<double> out_vals_, out_res_, out_rn_, fp32_vals_;
   int poly_count_ = 0;  // filter applications so far (for the debug_nan_poly hook)
 
   const FilterPoly &coeffs(int d);

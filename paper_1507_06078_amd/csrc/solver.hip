@@ -621,6 +621,9 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     if (fp32_stage) {
       stats.fp32_outer += 1;
       stats.fp32_maxres = maxres;  // the raw FP32-stage figure, before the FP64 closing iterations
+      fp32_vals_.assign(mu.begin(), mu.begin() + k);
+      if (which_ == ARR_SMALLEST_ALGEBRAIC)
+        for (double &v : fp32_vals_) v = -v;
     }
     if (o_.verbose) {
       std::fprintf(stderr,
@@ -739,6 +742,7 @@ int Solver::solve() {
   t0_ = std::chrono::steady_clock::now();
   stats = arr_stats_t{};
   solved = false;
+  fp32_vals_.clear();
   ARR_HIP(hipSetDevice(o_.device));
   ensure_device();
   host_results_ = false;

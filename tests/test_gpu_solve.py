@@ -313,6 +313,43 @@ def test_residual_scalings():
     assert st["maxres_explicit"] == r1.max() and st["maxres_norm_a"] == pytest.approx(r2.max(), rel=1e-14)
 
 
+def test_fp32_stage_values():
+    """arr_get_fp32_stage_values: the Ritz values the FP32 stage of a mixed
+    solve handed over. On the 2D Laplacian they sit above the closed-form
+    eigenvalues (Cauchy interlacing of a Rayleigh-Ritz projection, up to FP32
+    rounding of the basis and the projected matrix) and within sqrt(k) times
+    the FP32 stage's largest residual of them (Kahan's bound by the residual
+    block's 2-norm); the FP64 path has no FP32 stage (ARR_ESTATE)."""
+    A, k, which, w, _ = W.workload("lap2d_40")
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    o = arr.arr_options_default()
+    o.w = w
+    o.precision = arr.MIXED
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-10, o)
+    arr.arr_set_initial_block(h, X0)
+    with pytest.raises(arr.ArrError):
+        arr.arr_get_fp32_stage_values(h, k)  # before the solve
+    assert arr.arr_solve(h) == arr.ARR_OK
+    v32 = arr.arr_get_fp32_stage_values(h, k)
+    ev, _, _ = arr.arr_get_eigpairs(h, k, A.n, vectors=False)
+    st = arr.arr_get_stats(h)
+    h.close()
+    assert st["fp32_outer"] >= 1 and 0 < st["fp32_maxres"] <= 1.0
+    scale = np.maximum(1.0, np.abs(exact))
+    assert np.all(np.diff(v32) >= 0)
+    assert np.all(v32 >= exact - 1e-4 * scale)
+    assert np.all(np.abs(v32 - exact) <= np.sqrt(k) * st["fp32_maxres"] * scale)
+    assert np.abs(v32 - exact).max() > np.abs(ev - exact).max()  # the FP64 stage improved on it
+    o.precision = arr.FP64
+    h = arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-10, o)
+    arr.arr_set_initial_block(h, X0)
+    assert arr.arr_solve(h) == arr.ARR_OK
+    with pytest.raises(arr.ArrError):
+        arr.arr_get_fp32_stage_values(h, k)
+    h.close()
+
+
 @pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
 def test_nonfinite_guard_recovers_once(precision):
     """A NaN written into the iterate after the third filter application (the
