@@ -8,13 +8,21 @@ block of seed 2 (the GPU solves start from their own device draw, so the two
 sides share no iterate), and stores the k eigenvalues with their residuals in
 the eq. resi scaling.
 
-Independent check (spectrum slicing): by Sylvester's law of inertia the number
-of negative pivots of an LDL^T factorization of A - sigma I equals the number
-of eigenvalues of A below sigma. With sigma halfway between the k-th returned
-eigenvalue and the next Ritz value of the oracle's last iteration, that count
-must be exactly k for the smallest pairs (n - k for the largest), so no
-eigenvalue was skipped. The factorization is SuperLU's in symmetric mode with
-diagonal pivots only (a symmetric ordering, so its U has D on the diagonal).
+Independent checks:
+- the 3D stencil (spectrum slicing): by Sylvester's law of inertia the number
+  of negative pivots of an LDL^T factorization of A - sigma I equals the
+  number of eigenvalues of A below sigma. With sigma halfway between the k-th
+  returned eigenvalue and the next Ritz value of the oracle's last iteration,
+  that count must be exactly k, so no eigenvalue was skipped. The
+  factorization is SuperLU's in symmetric mode with diagonal pivots only (a
+  symmetric ordering, so its U has D on the diagonal), in a nested-dissection
+  order of the grid;
+- the random graphs, whose factorizations fill in almost completely: the
+  implicitly restarted Lanczos method (ARPACK through scipy's eigsh, a Krylov
+  method sharing nothing with the oracle's block iteration) from a seeded
+  start, for the k largest eigenvalues of A (power-law) or of 2I - A (the
+  normalized Laplacian, whose spectrum lies in [0, 2]); both value sets must
+  agree to 1e-10 max(1, |lambda|).
 
 Run from the repository root, one case at a time (the benchmark case holds
 about 40 GB and runs for about an hour on 8 cores):
@@ -137,9 +145,24 @@ def run(name):
     sigma = 0.5 * (lam_k + nxt)
     t1 = time.perf_counter()
     del r.history[:-1]
-    below = inertia_below(S, sigma, nested_dissection_3d(100) if name == "lap3d100" else None)
+    if name == "lap3d100":
+        below = inertia_below(S, sigma, nested_dissection_3d(100))
+        expect_below = k
+        check = f"spectrum slicing: {below} eigenvalues below sigma = {sigma:.17g} (expected {expect_below})"
+        passed = below == expect_below
+    else:
+        v0 = np.random.default_rng(X0_SEED).standard_normal(A.n)
+        if which == "SA":  # normalized Laplacian: smallest of A = 2 - largest of 2I - A
+            M = 2.0 * sp.identity(A.n, format="csr") - S
+            th = spla.eigsh(M, k=k, which="LA", tol=1e-14, ncv=3 * k, v0=v0, return_eigenvectors=False)
+            ref = np.sort(2.0 - th)
+        else:
+            th = spla.eigsh(S, k=k, which="LA", tol=1e-14, ncv=3 * k, v0=v0, return_eigenvectors=False)
+            ref = np.sort(th)[::-1]
+        dev = float(np.max(np.abs(ref - r.evals) / np.maximum(1.0, np.abs(ref))))
+        check = f"ARPACK (eigsh, ncv {3 * k}, tol 1e-14) agrees to max |dlambda| / max(1, |lambda|) = {dev:.2e}"
+        passed = dev <= 1e-10
     t_inertia = time.perf_counter() - t1
-    expect_below = k if which == "SA" else A.n - k
     lines = [
         f"# Oracle eigenvalues: {desc}",
         f"# k = {k} {'smallest' if which == 'SA' else 'largest'}, block {w}, oracle tol {TOL:g}, "
@@ -149,8 +172,7 @@ def run(name):
         f"block SpMM degrees {r.stats['spmm_degrees']}, max res (eq. resi) {r.res.max():.3e}",
         f"# oracle wall time {wall:.1f} s on {os.cpu_count()} cores ({cpu_model()}), "
         f"BLAS threads {blas_threads()}, sparse products single-threaded",
-        f"# spectrum slicing: {below} eigenvalues below sigma = {sigma:.17g} (expected {expect_below}); "
-        f"inertia count took {t_inertia:.1f} s",
+        f"# {check}; the check took {t_inertia:.1f} s",
         "# i lambda_i res_i",
     ]
     for i in range(k):
@@ -161,7 +183,7 @@ def run(name):
     print("\n".join(lines[:6]))
     print("wrote", path)
     assert r.status == 0, r.status
-    assert below == expect_below, (below, expect_below)
+    assert passed, check
 
 
 if __name__ == "__main__":

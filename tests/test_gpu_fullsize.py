@@ -34,8 +34,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 def oracle_fixture(name):
     """Eigenvalues written by tests/golden/make_eigen_fixtures.py (the oracle's
-    Algorithm 8 at tol 1e-12, with a spectrum-slicing check that no eigenvalue
-    below the k-th was skipped)."""
+    Algorithm 8 at tol 1e-12, checked there by spectrum slicing for the
+    stencil and by ARPACK's Lanczos method for the random graphs)."""
     path = os.path.join(GOLDEN, f"eig_{name}.txt")
     if not os.path.exists(path):
         pytest.skip(f"oracle fixture {path} not generated")
