@@ -176,7 +176,7 @@ def run(name):
         "# i lambda_i res_i",
     ]
     for i in range(k):
-        lines.append(f"{i} {r.evals[i]!r} {r.res[i]:.3e}")
+        lines.append(f"{i} {float(r.evals[i])!r} {float(r.res[i]):.3e}")
     path = os.path.join(HERE, f"eig_{name}.txt")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
