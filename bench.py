@@ -119,7 +119,7 @@ def cpu_baseline(A, k, w, stats, a, b):
 
 
 def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slots=8, budget=0, verbose=False,
-                  precision="mixed"):
+                  precision="mixed", batch_spmm=False):
     """Served workload: Poisson arrivals (exponential gaps, mean 1/rate); each
     request is a 2D or 3D (prob. 1/2) Laplacian plus a U[0,1) potential with n
     log-uniform in n_range (n = m^2 or m^3), k ~ U{10..200}, block
@@ -159,7 +159,7 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
     t_build = time.perf_counter() - t_build
     if verbose:
         print(f"[serve] built {n_requests} requests in {t_build:.1f} s", file=sys.stderr, flush=True)
-    srv = arr.Server(hbm_budget_bytes=budget, max_slots=max_slots)
+    srv = arr.Server(hbm_budget_bytes=budget, max_slots=max_slots, batch_spmm=batch_spmm)
     try:
         t0 = time.perf_counter()
         tickets = []
@@ -180,6 +180,7 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
                       flush=True)
         makespan = time.perf_counter() - t0
         times = np.array([srv.times(t) for t in tickets])
+        rounds, launches = srv.batch_stats()
     finally:
         srv.close()  # waits for running requests before any handle is released
     lat = times[:, 2] - times[:, 0]
@@ -210,6 +211,8 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
         "eigenpairs_per_s_tol1e-10": float(k_arr[conv & tight].sum() / makespan),
         "n_median": float(np.median(ns)), "build_s": t_build, "precision": precision,
         "busy_s": float(np.sum(times[:, 2] - times[:, 1])),
+        "multi_request_spmm": {"enabled": bool(batch_spmm), "rounds": rounds, "launches": launches,
+                               "launches_per_round": (launches / rounds) if rounds else None},
     }
 
 
@@ -404,6 +407,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-batch", action="store_true",
+                    help="served stream with the multi-request SpMM launches (batch_spmm)")
     ap.add_argument("--serve-compare", action="store_true",
                     help="also run the same stream on the plain FP64 path with the same slots, and one "
                          "request at a time")
@@ -421,7 +426,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serve:
-        r = served_stream(n_requests=args.serve_requests, max_slots=args.serve_slots, verbose=args.verbose)
+        r = served_stream(n_requests=args.serve_requests, max_slots=args.serve_slots, verbose=args.verbose,
+                          batch_spmm=args.serve_batch)
         if args.serve_compare:
             r64s = served_stream(n_requests=args.serve_requests, max_slots=args.serve_slots, verbose=args.verbose,
                                  precision="fp64")
@@ -531,6 +537,13 @@ def main():
                              precision="fp64")
         sv["fp64_same_slots"] = sv64
         sv["speedup_vs_fp64_same_slots"] = sv64["makespan_s"] / sv["makespan_s"]
+        # and the mixed stream with the SpMMs of the running requests in
+        # multi-request launches (batch_spmm)
+        svb = served_stream(n_requests=args.served_sample, max_slots=args.serve_slots, verbose=args.verbose,
+                            batch_spmm=True)
+        sv["mixed_multi_request_spmm"] = {key: svb[key] for key in ("makespan_s", "latency_p50_s", "latency_p99_s",
+                                                                     "converged", "eigenpairs_per_s",
+                                                                     "multi_request_spmm")}
         out["serving"] = sv
     if not args.no_cpu_baseline and args.workload == "lap3d100":
         # interval of the working operator (-A) as the solver estimated it

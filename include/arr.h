@@ -321,6 +321,12 @@ typedef struct {
   uint64_t hbm_budget_bytes; /* device arena; 0 -> 80% of the free device memory */
   int32_t max_slots;         /* requests solved concurrently; 0 -> 4             */
   int32_t device;            /* HIP device ordinal                               */
+  int32_t batch_spmm;        /* 1: the running requests' filter SpMMs run
+                                together in multi-request launches (the kernel
+                                of arr_filter_step_batch), gathered by a broker
+                                thread; 0 (default): each request launches its
+                                own on its stream                           */
+  int32_t reserved;          /* must be 0                                        */
 } arr_server_opts_t;
 
 void arr_server_opts_default(arr_server_opts_t *o);
@@ -335,6 +341,12 @@ int arr_poll(arr_server_t s, uint64_t ticket, int *done);
 int arr_wait(arr_server_t s, uint64_t ticket);
 /* Seconds since server creation at submission, admission and completion. */
 int arr_request_times(arr_server_t s, uint64_t ticket, double *t_submit, double *t_admit, double *t_done);
+/* With batch_spmm: the broker's rounds so far (each round takes every SpMM
+ * call the running requests had handed in) and the plain- and paired-form
+ * launches those rounds ran inside multi-request launches (grid-form
+ * launches run as launches of their own and are not counted); zeros without
+ * batch_spmm. */
+int arr_server_batch_stats(arr_server_t s, int64_t *batches, int64_t *launches);
 /* Waits for the running requests; queued ones are cancelled (status
  * ARR_ESTATE). */
 void arr_server_destroy(arr_server_t s);
@@ -353,6 +365,22 @@ void arr_server_destroy(arr_server_t s);
 int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t ldy, const void *Z,
                     int64_t ldz, void *Yout, int64_t ldo, double alpha, double beta, double gamma,
                     double *colsumsq, void *stream);
+
+/* `count` independent filter degrees (arr_filter_step's operation on each
+ * item i: A[i], w[i], Yin[i], ldy[i], Z[i] (may be NULL), ldz[i], Yout[i],
+ * ldo[i], alpha[i], beta[i], gamma[i], colsumsq[i] (may be NULL; the array
+ * itself may be NULL)), as the multi-request kernel of the serving loop runs
+ * them: the plain- and paired-form launches of all items share one
+ * persistent launch per kernel variant, whose workgroups take the items'
+ * workgroups from a device task table (grid-form items run as their own
+ * launches). Each item's result is bitwise what arr_filter_step returns for
+ * it. Items may mix dtypes and sizes; their outputs must not overlap any
+ * item's inputs or outputs. ARR_EINVAL for count < 1 or an invalid item.
+ * Synchronous. */
+int arr_filter_step_batch(int32_t count, const arr_dev_csr_t *const *A, const int64_t *w, const void *const *Yin,
+                          const int64_t *ldy, const void *const *Z, const int64_t *ldz, void *const *Yout,
+                          const int64_t *ldo, const double *alpha, const double *beta, const double *gamma,
+                          double *const *colsumsq, void *stream);
 
 /* Algorithm 7 on the shifted operator, as called by Algorithm 8:
  * X <- poly(A - shift I, X, lo, hi, Gamma_d), with Gamma_d (host, d+1 values,

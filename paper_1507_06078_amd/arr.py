@@ -73,7 +73,8 @@ class arr_options_t(ctypes.Structure):
 
 
 class arr_server_opts_t(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32)]
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("batch_spmm", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class arr_stats_t(ctypes.Structure):
@@ -103,11 +104,11 @@ class arr_stats_t(ctypes.Structure):
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",
            "arr_get_eigpairs", "arr_get_residuals", "arr_get_fp32_stage_values", "arr_get_stats", "arr_last_error",
            "arr_last_global_error", "arr_destroy",
-           "arr_filter_step", "arr_poly", "arr_filter", "arr_filter_roots", "arr_gn_step",
+           "arr_filter_step", "arr_filter_step_batch", "arr_poly", "arr_filter", "arr_filter_roots", "arr_gn_step",
            "arr_filter_coefficients", "arr_gram", "arr_gram_noalloc", "arr_block_update",
            "arr_rcond_gram", "arr_orthonormalize", "arr_syev", "arr_augmented_rr", "arr_server_opts_default",
            "arr_server_create", "arr_footprint", "arr_submit", "arr_poll", "arr_wait", "arr_request_times",
-           "arr_server_destroy", "arr_row_form", "arr_row_grid"]
+           "arr_server_destroy", "arr_server_batch_stats", "arr_row_form", "arr_row_grid"]
 
 _lib = None
 
@@ -140,6 +141,7 @@ def lib() -> ctypes.CDLL:
     L.arr_destroy.argtypes = [vp]
     L.arr_destroy.restype = None
     L.arr_filter_step.argtypes = [P(arr_dev_csr_t), i64, vp, i64, vp, i64, vp, i64, f64, f64, f64, vp, vp]
+    L.arr_filter_step_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.arr_poly.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, vp, i32, vp]
     L.arr_gn_step.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, vp, i32, vp]
     L.arr_filter.argtypes = [P(arr_dev_csr_t), i64, vp, i64, f64, f64, f64, i32, i32, vp]
@@ -164,6 +166,7 @@ def lib() -> ctypes.CDLL:
     L.arr_request_times.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
     L.arr_server_destroy.argtypes = [vp]
     L.arr_server_destroy.restype = None
+    L.arr_server_batch_stats.argtypes = [vp, vp, vp]
     void_fns = ("arr_options_default", "arr_destroy", "arr_last_error", "arr_last_global_error",
                 "arr_server_opts_default", "arr_server_destroy")
     for name in EXPORTS:
@@ -290,12 +293,13 @@ def arr_get_stats(h: Handle) -> dict:
 class Server:
     """Owns an arr_server_t (continuous batching of solves on one GPU)."""
 
-    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 4, device: int = 0):
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 4, device: int = 0, batch_spmm: bool = False):
         o = arr_server_opts_t()
         lib().arr_server_opts_default(ctypes.byref(o))
         o.hbm_budget_bytes = int(hbm_budget_bytes)
         o.max_slots = int(max_slots)
         o.device = int(device)
+        o.batch_spmm = 1 if batch_spmm else 0
         p = ctypes.c_void_p()
         _check(lib().arr_server_create(ctypes.byref(o), ctypes.byref(p)))
         self.ptr = p.value
@@ -321,6 +325,12 @@ class Server:
         _check(lib().arr_request_times(self.ptr, ctypes.c_uint64(ticket), ctypes.addressof(a), ctypes.addressof(b),
                                        ctypes.addressof(c)))
         return a.value, b.value, c.value
+
+    def batch_stats(self):
+        """(multi-request launch rounds, single-request launches they replaced)."""
+        b, n = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().arr_server_batch_stats(self.ptr, ctypes.addressof(b), ctypes.addressof(n)))
+        return b.value, n.value
 
     def close(self):
         if getattr(self, "ptr", None):
@@ -386,6 +396,24 @@ def arr_filter_step(A: DeviceCSR, Yin, Z, Yout, alpha: float, beta: float, gamma
     w = int(Yout.shape[1])
     _check(lib().arr_filter_step(ctypes.byref(A.desc), w, _ptr(Yin), _ld(Yin), _ptr(Z), _ld(Z), _ptr(Yout),
                                  _ld(Yout), float(alpha), float(beta), float(gamma), _ptr(colsumsq), _stream()))
+
+
+def arr_filter_step_batch(items):
+    """arr_filter_step on every item of `items`, a list of tuples
+    (A, Yin, Z, Yout, alpha, beta, gamma, colsumsq), in one multi-request
+    launch per kernel variant."""
+    cnt = len(items)
+    arrs = lambda ctype, vals: (ctype * cnt)(*vals)
+    descs = [it[0].desc for it in items]
+    A = (ctypes.POINTER(arr_dev_csr_t) * cnt)(*[ctypes.pointer(d) for d in descs])
+    vp = ctypes.c_void_p
+    _check(lib().arr_filter_step_batch(
+        cnt, A, arrs(ctypes.c_int64, [int(it[3].shape[1]) for it in items]),
+        arrs(vp, [_ptr(it[1]) for it in items]), arrs(ctypes.c_int64, [_ld(it[1]) for it in items]),
+        arrs(vp, [_ptr(it[2]) for it in items]), arrs(ctypes.c_int64, [_ld(it[2]) for it in items]),
+        arrs(vp, [_ptr(it[3]) for it in items]), arrs(ctypes.c_int64, [_ld(it[3]) for it in items]),
+        arrs(ctypes.c_double, [float(it[4]) for it in items]), arrs(ctypes.c_double, [float(it[5]) for it in items]),
+        arrs(ctypes.c_double, [float(it[6]) for it in items]), arrs(vp, [_ptr(it[7]) for it in items]), _stream()))
 
 
 def arr_poly(A: DeviceCSR, X, shift: float, lo: float, hi: float, gamma: np.ndarray):

@@ -320,6 +320,7 @@ void arr_server_opts_default(arr_server_opts_t *o) {
   o->hbm_budget_bytes = 0;
   o->max_slots = 4;
   o->device = 0;
+  o->batch_spmm = 0;
 }
 
 int arr_server_create(const arr_server_opts_t *o, arr_server_t *out) {
@@ -332,6 +333,8 @@ int arr_server_create(const arr_server_opts_t *o, arr_server_t *out) {
     else
       arr_server_opts_default(&d);
     ARR_REQUIRE(d.max_slots >= 0, "max_slots must be >= 0");
+    ARR_REQUIRE(d.batch_spmm == 0 || d.batch_spmm == 1, "batch_spmm must be 0 or 1");
+    ARR_REQUIRE(d.reserved == 0, "reserved must be 0");
     auto s = std::make_unique<arr_server>();
     s->s = std::make_unique<arr::Server>(d);
     *out = s.release();
@@ -381,6 +384,12 @@ int arr_request_times(arr_server_t s, uint64_t ticket, double *t_submit, double 
   });
 }
 
+int arr_server_batch_stats(arr_server_t s, int64_t *batches, int64_t *launches) {
+  if (!s || !batches || !launches) return ARR_EINVAL;
+  s->s->batch_stats(batches, launches);
+  return ARR_OK;
+}
+
 void arr_server_destroy(arr_server_t s) { delete s; }
 
 // ---- step-level entry points ----------------------------------------------
@@ -412,6 +421,64 @@ int arr_filter_step(const arr_dev_csr_t *A, int64_t w, const void *Yin, int64_t 
                                               arr::Blk<float>{(float *)Yout, ldo, (int)w}, alpha, beta, gamma, pp, s);
     }
     if (colsumsq) arr::launch_reduce_groups(pp, groups, (int)w, colsumsq, false, s);
+    ARR_HIP(hipStreamSynchronize(s));  // before the temporary buffers go
+    return ARR_OK;
+  });
+}
+
+int arr_filter_step_batch(int32_t count, const arr_dev_csr_t *const *A, const int64_t *w, const void *const *Yin,
+                          const int64_t *ldy, const void *const *Z, const int64_t *ldz, void *const *Yout,
+                          const int64_t *ldo, const double *alpha, const double *beta, const double *gamma,
+                          double *const *colsumsq, void *stream) {
+  return guarded(nullptr, [&]() {
+    ARR_REQUIRE(count >= 1 && A && w && Yin && ldy && ldz && Yout && ldo && alpha && beta && gamma,
+                "filter_step_batch: NULL array or count < 1");
+    hipStream_t s = as_stream(stream);
+    std::vector<std::unique_ptr<SplitDev<double>>> m64(count);
+    std::vector<std::unique_ptr<SplitDev<float>>> m32(count);
+    std::vector<arr::DevBuf> part(count);
+    std::vector<int> groups(count, 0);
+    for (int i = 0; i < count; ++i) {
+      const void *Zi = Z ? Z[i] : nullptr;
+      ARR_REQUIRE(A[i] && w[i] >= 0 && ldy[i] >= w[i] && ldo[i] >= w[i] && (!Zi || ldz[i] >= w[i]),
+                  "filter_step_batch: bad sizes in item " + std::to_string(i));
+      ARR_REQUIRE(Yin[i] && Yout[i] && Yin[i] != Yout[i],
+                  "filter_step_batch: Yin/Yout NULL or aliased in item " + std::to_string(i));
+      ARR_REQUIRE(A[i]->dtype == 0 || A[i]->dtype == 1, "dtype must be 0 (FP64) or 1 (FP32)");
+      if (A[i]->dtype == 0)
+        m64[i] = dev_split<double>(A[i]);
+      else
+        m32[i] = dev_split<float>(A[i]);
+      if (colsumsq && colsumsq[i]) part[i].alloc(sizeof(double) * arr::spmm_groups(A[i]->n) * std::max<int64_t>(1, w[i]));
+    }
+    arr::SpmmBatch batch;
+    struct Install {
+      arr::SpmmBatch *prev;
+      explicit Install(arr::SpmmBatch *b) : prev(arr::spmm_batch()) { arr::spmm_batch() = b; }
+      ~Install() { arr::spmm_batch() = prev; }
+    };
+    {
+      Install in(&batch);
+      for (int i = 0; i < count; ++i) {
+        const void *Zi = Z ? Z[i] : nullptr;
+        double *pp = part[i].as<double>();
+        const int wi = (int)w[i];
+        if (A[i]->dtype == 0)
+          groups[i] = arr::launch_filter_spmm<double>(
+              m64[i]->M, arr::Blk<const double>{(const double *)Yin[i], ldy[i], wi},
+              arr::Blk<const double>{(const double *)Zi, ldz[i], Zi ? wi : 0},
+              arr::Blk<double>{(double *)Yout[i], ldo[i], wi}, alpha[i], beta[i], gamma[i], pp, s);
+        else
+          groups[i] = arr::launch_filter_spmm<float>(
+              m32[i]->M, arr::Blk<const float>{(const float *)Yin[i], ldy[i], wi},
+              arr::Blk<const float>{(const float *)Zi, ldz[i], Zi ? wi : 0},
+              arr::Blk<float>{(float *)Yout[i], ldo[i], wi}, alpha[i], beta[i], gamma[i], pp, s);
+      }
+    }
+    batch.run(s);
+    for (int i = 0; i < count; ++i)
+      if (colsumsq && colsumsq[i])
+        arr::launch_reduce_groups(part[i].as<double>(), groups[i], (int)w[i], colsumsq[i], false, s);
     ARR_HIP(hipStreamSynchronize(s));  // before the temporary buffers go
     return ARR_OK;
   });

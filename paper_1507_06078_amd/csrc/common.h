@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -223,6 +224,75 @@ enum GemmClass { kGramF64 = 0, kGramF32 = 1, kGramF32Cores = 2, kUpdF64 = 3, kUp
 // Groups that launch_filter_spmm / launch_colsumsq use for n rows (sizes the
 // partial buffer: groups * w doubles).
 int spmm_groups(int64_t n);
+
+// ---- multi-request filter SpMM ----------------------------------------------
+// One launch of the plain- or paired-form SpMM kernel, as its arguments
+// (pointers already offset to the launch's column chunk), for the
+// multi-request kernel: groups is the grid the launch would have had.
+struct SpmmTask {
+  int64_t n, P, ldy, ldz, ldo;
+  const void *coef;
+  const int32_t *fcol;
+  const int64_t *orp;
+  const int32_t *ocol;
+  const void *oval;
+  const void *Yin;
+  const void *Z;
+  void *Yout;
+  double alpha, beta, gamma;
+  double *partial;
+  const double *colss;
+  int32_t w, wtot, c0, groups;
+};
+// Runs ntasks workgroup tasks {launch index into desc, workgroup of that
+// launch} of one kernel variant on s.
+using SpmmTaskLauncher = void (*)(const SpmmTask *desc, const int2 *tasks, int ntasks, hipStream_t s);
+
+// While a batch is installed on the calling thread (spmm_batch()),
+// launch_filter_spmm hands its plain- and paired-form launches to the batch
+// instead of launching them (grid-form launches still go to their stream,
+// and no SpMM timing is taken). run() then executes every collected launch:
+// one persistent launch per kernel variant, whose workgroups take the
+// collected launches' workgroups from a task table, interleaved over the
+// launches. Each workgroup of a collected launch runs the same code on the
+// same rows as in its own launch, so results are bitwise those of separate
+// launches. The tables go through one device buffer of cap bytes (so
+// successive run() calls must use one stream) and a ring of kRing pinned
+// staging buffers: run() waits on the host only for the copy kRing runs
+// back.
+struct SpmmBatch {
+  explicit SpmmBatch(size_t cap_bytes = (size_t)4 << 20);
+  ~SpmmBatch();
+  SpmmBatch(const SpmmBatch &) = delete;
+  SpmmBatch &operator=(const SpmmBatch &) = delete;
+  void add(const SpmmTask &t, SpmmTaskLauncher launcher);
+  // Launches the collected work on s and forgets it; returns the number of
+  // launches it replaced.
+  int run(hipStream_t s);
+  bool empty() const { return tasks_.empty(); }
+
+ private:
+  static constexpr int kRing = 4;
+  std::vector<SpmmTask> tasks_;
+  std::vector<SpmmTaskLauncher> launchers_;
+  DevBuf dev_;
+  char *host_ = nullptr;  // kRing staging buffers of cap_ bytes
+  size_t cap_ = 0;
+  hipEvent_t staged_[kRing] = {};
+  int slot_ = 0;
+};
+SpmmBatch *&spmm_batch();
+
+// A receiver of the calling thread's SpMMs (the serving loop installs one on
+// each request's thread): launch_filter_spmm hands it the whole call as
+// `launch`, which performs the call's launches on the stream it is given,
+// and returns what run returns. run must leave the caller's stream s ordered
+// after those launches.
+struct SpmmSink {
+  virtual ~SpmmSink() = default;
+  virtual int run(const std::function<int(hipStream_t)> &launch, hipStream_t s) = 0;
+};
+SpmmSink *&spmm_sink();
 // y = A x for one vector (Lanczos).
 template <typename T>
 void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s);

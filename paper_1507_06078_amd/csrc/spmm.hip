@@ -45,6 +45,7 @@
 //    store), and the pairing drops one of the six.
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <exception>
 #include <map>
 
@@ -171,220 +172,11 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm(
     const int32_t *__restrict__ ocol, const T *__restrict__ oval, int w, const T *__restrict__ Yin, int64_t ldy,
     const T *Z, int64_t ldz, T *Yout, int64_t ldo, T alpha, T beta, T gamma, double *__restrict__ partial,
     int wtot, int c0, const double *__restrict__ colss) {
-  typedef typename VecT<T, VEC>::type vec;
-  typedef BufIO<T, VEC> IO;
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int x = blockIdx.x % kXcd;
-  const int64_t wave_in_xcd = (int64_t)(blockIdx.x / kXcd) * kWaves + wv;
-  const int64_t waves_per_xcd = (int64_t)(gridDim.x / kXcd) * kWaves;
-  const int lg = chunk_log(waves_per_xcd);
-  const int64_t nruns = (n + kRun - 1) / kRun;
-  const int rowbytes = w * (int)sizeof(T);
-  int off[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) off[t] = (VEC * lane + 64 * VEC * t) * (int)sizeof(T);
-  auto ldrow = [&](const T *base, int64_t ld, int64_t j, vec *dst) {
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(base + j * ld, rowbytes);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) dst[t] = IO::ld(r, off[t]);
-  };
-  auto gather = [&](int64_t j, vec *dst) { ldrow(Yin, ldy, j, dst); };
-
-  double ss[NT][VEC];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) ss[t][v] = 0.0;
-  // launches with column sums may also scale the output's columns by
-  // 1/sqrt(colss[c]) (the normalization of the block the chain started from)
-  vec cs[NT];
-  if constexpr (SUMS) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        const int c = VEC * lane + 64 * VEC * t + v;
-        set_elem<VEC>(cs[t], v, (T)(colss && c < w ? 1.0 / sqrt(colss[c]) : 1.0));
-      }
-  }
-
-  // beta*Yin + gamma*Z and the store of row i; column sums of squares
-  auto finish_row = [&](int64_t i, const vec *acc, const vec *yi, const vec *zi) {
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(Yout + i * ldo, rowbytes);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      vec o = alpha * acc[t];
-      if (beta != T(0)) o += beta * yi[t];
-      if constexpr (HASZ) o += gamma * zi[t];
-      if constexpr (SUMS) o *= cs[t];
-      IO::st(o, r, off[t]);
-      if constexpr (SUMS) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const double ov = lane_elem<VEC>(o, v);
-          ss[t][v] = fma(ov, ov, ss[t][v]);
-        }
-      }
-    }
-  };
-  // far entries past the fourth, four gathers at a time
-  auto overflow = [&](int64_t i, vec *acc) {
-    if constexpr (OVF) {
-      const int64_t b = orp[i], e = orp[i + 1];
-      int64_t p = b;
-      for (; p + 4 <= e; p += 4) {
-        const T a0 = oval[p], a1 = oval[p + 1], a2 = oval[p + 2], a3 = oval[p + 3];
-        vec v0[NT], v1[NT], v2[NT], v3[NT];
-        gather(ocol[p], v0);
-        gather(ocol[p + 1], v1);
-        gather(ocol[p + 2], v2);
-        gather(ocol[p + 3], v3);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] += a0 * v0[t] + a1 * v1[t] + a2 * v2[t] + a3 * v3[t];
-      }
-      for (; p < e; ++p) {
-        const T a0 = oval[p];
-        vec v0[NT];
-        gather(ocol[p], v0);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] += a0 * v0[t];
-      }
-    }
-  };
-
-  for (int64_t k = wave_in_xcd;; k += waves_per_xcd) {
-    const int64_t r = xcd_run(k, x, lg);
-    if (r >= nruns) break;
-    const int64_t i0 = r * kRun;
-    if constexpr (OVF) {
-      // rows with more than four far entries: one row at a time with the
-      // register window, far entries four gathers at a time
-      const int64_t iend = min(n, i0 + kRun);
-      vec wm[NT], w0[NT], wp[NT], zero[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) zero[t] = vec(0);
-      if (i0 > 0) gather(i0 - 1, wm); else for (int t = 0; t < NT; ++t) wm[t] = zero[t];
-      gather(i0, w0);
-      if (i0 + 1 < n) gather(i0 + 1, wp); else for (int t = 0; t < NT; ++t) wp[t] = zero[t];
-      for (int64_t i = i0; i < iend; ++i) {
-        vec nx[NT], zi[NT], g[4][NT];
-        if (i + 1 < iend && i + 2 < n) gather(i + 2, nx); else for (int t = 0; t < NT; ++t) nx[t] = zero[t];
-        const RowCoef<T> kk = *(const RowCoef<T> *)(coef + 8 * i);
-        const RowCols ci = *(const RowCols *)(fcol + 4 * i);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) gather(ci.v[e], g[e]);
-        vec acc[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          acc[t] = kk.v[0] * wm[t] + kk.v[1] * w0[t] + kk.v[2] * wp[t] + kk.v[3] * g[0][t] + kk.v[4] * g[1][t] +
-                   kk.v[5] * g[2][t] + kk.v[6] * g[3][t];
-        overflow(i, acc);
-        if constexpr (HASZ) ldrow(Z, ldz, i, zi);
-        finish_row(i, acc, w0, zi);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          wm[t] = w0[t];
-          w0[t] = wp[t];
-          wp[t] = nx[t];
-        }
-      }
-    } else if (i0 >= 1 && i0 + kRun + 1 <= n) {
-      // full run: rows i0-1 .. i0+kRun exist; straight-line code
-      vec wm[NT], w0[NT], wp[NT], g[4][NT], z[NT];
-      gather(i0 - 1, wm);
-      gather(i0, w0);
-      gather(i0 + 1, wp);
-      RowCols c0 = *(const RowCols *)(fcol + 4 * i0);
-      RowCoef<T> k0 = *(const RowCoef<T> *)(coef + 8 * i0);
-      RowCols c1 = *(const RowCols *)(fcol + 4 * (i0 + 1));
-#pragma unroll
-      for (int e = 0; e < 4; ++e) gather(c0.v[e], g[e]);
-      if constexpr (HASZ) ldrow(Z, ldz, i0, z);
-#pragma unroll
-      for (int q = 0; q < kRun; ++q) {
-        const int64_t i = i0 + q;
-        vec nx[NT], gn[4][NT], zn[NT];
-        RowCols c2 = c1;
-        RowCoef<T> k1 = k0;
-        if (q < kRun - 1) gather(i + 2, nx);
-        if (q < kRun - 1) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) gather(c1.v[e], gn[e]);
-          if constexpr (HASZ) ldrow(Z, ldz, i + 1, zn);
-          k1 = *(const RowCoef<T> *)(coef + 8 * (i + 1));
-        }
-        if (q < kRun - 2) c2 = *(const RowCols *)(fcol + 4 * (i + 2));
-        vec acc[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          acc[t] = k0.v[0] * wm[t] + k0.v[1] * w0[t] + k0.v[2] * wp[t] + k0.v[3] * g[0][t] + k0.v[4] * g[1][t] +
-                   k0.v[5] * g[2][t] + k0.v[6] * g[3][t];
-        finish_row(i, acc, w0, z);
-        // keep the scheduler from hoisting later rows' loads into this one
-        // (register pressure); the loads already issued stay in flight
-        __builtin_amdgcn_sched_barrier(0);
-        if (q < kRun - 1) {
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            wm[t] = w0[t];
-            w0[t] = wp[t];
-            wp[t] = nx[t];
-            if constexpr (HASZ) z[t] = zn[t];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) g[e][t] = gn[e][t];
-          }
-          k0 = k1;
-          c1 = c2;
-        }
-      }
-    } else {
-      // first run and the runs at the end: guarded, one row at a time
-      const int64_t iend = min(n, i0 + kRun);
-      for (int64_t i = i0; i < iend; ++i) {
-        const RowCoef<T> kk = *(const RowCoef<T> *)(coef + 8 * i);
-        const RowCols ci = *(const RowCols *)(fcol + 4 * i);
-        vec acc[NT], yi[NT], v[NT], zi[NT];
-        gather(i, yi);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = kk.v[1] * yi[t];
-        if (i > 0) {
-          gather(i - 1, v);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] += kk.v[0] * v[t];
-        }
-        if (i + 1 < n) {
-          gather(i + 1, v);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] += kk.v[2] * v[t];
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          gather(ci.v[e], v);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] += kk.v[3 + e] * v[t];
-        }
-        overflow(i, acc);
-        if constexpr (HASZ) ldrow(Z, ldz, i, zi);
-        finish_row(i, acc, yi, zi);
-      }
-    }
-  }
-
-  if constexpr (SUMS) {
-    __shared__ double red[kWaves][64 * VEC * NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) red[wv][VEC * lane + 64 * VEC * t + v] = ss[t][v];
-    __syncthreads();
-    for (int c = threadIdx.x; c < w; c += kThreads) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kWaves; ++q) s += red[q][c];
-      partial[(int64_t)blockIdx.x * wtot + c0 + c] = s;
-    }
-  }
+#define ARR_VBLOCK blockIdx.x
+#define ARR_VGRID gridDim.x
+#include "spmm_plain_body.inc"
+#undef ARR_VBLOCK
+#undef ARR_VGRID
 }
 
 // Paired form: a unit is an upper run [a0, a0 + kPairRun) of a block of 2P
@@ -400,215 +192,11 @@ __global__ __launch_bounds__(kThreads) void k_filter_spmm_paired(
     int64_t n, int64_t P, const T *__restrict__ coef, const int32_t *__restrict__ fcol, int w,
     const T *__restrict__ Yin, int64_t ldy, const T *Z, int64_t ldz, T *Yout, int64_t ldo, T alpha, T beta,
     T gamma, double *__restrict__ partial, int wtot, int c0, const double *__restrict__ colss) {
-  typedef typename VecT<T, VEC>::type vec;
-  typedef BufIO<T, VEC> IO;
-  constexpr int R = (int)kPairRun;
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int x = blockIdx.x % kXcd;
-  const int64_t wave_in_xcd = (int64_t)(blockIdx.x / kXcd) * kWaves + wv;
-  const int64_t waves_per_xcd = (int64_t)(gridDim.x / kXcd) * kWaves;
-  const int lg = chunk_log(waves_per_xcd);
-  const int64_t half_runs = (P + R - 1) / R;
-  const int64_t blocks = n / (2 * P);
-  const int64_t paired_units = blocks * half_runs;
-  const int64_t tail0 = blocks * 2 * P;
-  const int64_t units = paired_units + (n - tail0 + R - 1) / R;
-  const int rowbytes = w * (int)sizeof(T);
-  int off[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) off[t] = (VEC * lane + 64 * VEC * t) * (int)sizeof(T);
-  auto ldrow = [&](const T *base, int64_t ld, int64_t j, vec *dst) {
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(base + j * ld, rowbytes);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) dst[t] = IO::ld(r, off[t]);
-  };
-  auto gather = [&](int64_t j, vec *dst) { ldrow(Yin, ldy, j, dst); };
-
-  double ss[NT][VEC];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) ss[t][v] = 0.0;
-  // launches with column sums may also scale the output's columns by
-  // 1/sqrt(colss[c]) (the normalization of the block the chain started from)
-  vec cs[NT];
-  if constexpr (SUMS) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        const int c = VEC * lane + 64 * VEC * t + v;
-        set_elem<VEC>(cs[t], v, (T)(colss && c < w ? 1.0 / sqrt(colss[c]) : 1.0));
-      }
-  }
-
-  auto finish_row = [&](int64_t i, bool own, const vec *acc, const vec *yi, const vec *zi) {
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(Yout + i * ldo, own ? rowbytes : 0);
-    const double m = own ? 1.0 : 0.0;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      vec o = alpha * acc[t];
-      if (beta != T(0)) o += beta * yi[t];
-      if constexpr (HASZ) o += gamma * zi[t];
-      if constexpr (SUMS) o *= cs[t];
-      IO::st(o, r, off[t]);
-      if constexpr (SUMS) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const double ov = lane_elem<VEC>(o, v);
-          ss[t][v] = fma(m * ov, ov, ss[t][v]);
-        }
-      }
-    }
-  };
-
-  for (int64_t k = wave_in_xcd;; k += waves_per_xcd) {
-    const int64_t u = xcd_run(k, x, lg);
-    if (u >= units) break;
-    if (u < paired_units) {
-      const int64_t blk = u / half_runs, r = u % half_runs;
-      const int64_t st = min(r * R, P - R);
-      const int skip = (int)(r * R - st);
-      const int64_t a0 = blk * 2 * P + st, b0 = a0 + P;
-      // Row a0 - 1 is missing only for a0 = 0 and row b0 + R only for
-      // b0 + R = n; their coefficients are zero, so a row of the matrix
-      // stands in for them
-      vec wmA[NT], w0A[NT], wpA[NT], wmB[NT], w0B[NT], wpB[NT], gA[KF][NT], gB[KF][NT], zA[NT], zB[NT];
-      gather(a0 > 0 ? a0 - 1 : 0, wmA);
-      gather(a0, w0A);
-      gather(a0 + 1, wpA);
-      gather(b0 - 1, wmB);
-      gather(b0, w0B);
-      gather(b0 + 1, wpB);
-      RowCols cA = *(const RowCols *)(fcol + 4 * a0), cB = *(const RowCols *)(fcol + 4 * b0);
-      RowCoef<T> kA = *(const RowCoef<T> *)(coef + 8 * a0), kB = *(const RowCoef<T> *)(coef + 8 * b0);
-      RowCols cA1 = *(const RowCols *)(fcol + 4 * (a0 + 1)), cB1 = *(const RowCols *)(fcol + 4 * (b0 + 1));
-#pragma unroll
-      for (int e = 0; e < KF; ++e) {
-        gather(cA.v[e], gA[e]);
-        gather(cB.v[e], gB[e]);
-      }
-      if constexpr (HASZ) {
-        ldrow(Z, ldz, a0, zA);
-        ldrow(Z, ldz, b0, zB);
-      }
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int64_t i = a0 + q, j = b0 + q;
-        vec nxA[NT], nxB[NT], gnA[KF][NT], gnB[KF][NT], znA[NT], znB[NT];
-        RowCols cA2 = cA1, cB2 = cB1;
-        RowCoef<T> kA1 = kA, kB1 = kB;
-        if (q < R - 1) {
-          gather(i + 2, nxA);
-          gather(j + 2 < n ? j + 2 : n - 1, nxB);
-#pragma unroll
-          for (int e = 0; e < KF; ++e) {
-            gather(cA1.v[e], gnA[e]);
-            gather(cB1.v[e], gnB[e]);
-          }
-          if constexpr (HASZ) {
-            ldrow(Z, ldz, i + 1, znA);
-            ldrow(Z, ldz, j + 1, znB);
-          }
-          kA1 = *(const RowCoef<T> *)(coef + 8 * (i + 1));
-          kB1 = *(const RowCoef<T> *)(coef + 8 * (j + 1));
-        }
-        if (q < R - 2) {
-          cA2 = *(const RowCols *)(fcol + 4 * (i + 2));
-          cB2 = *(const RowCols *)(fcol + 4 * (j + 2));
-        }
-        vec accA[NT], accB[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          accA[t] = kA.v[0] * wmA[t] + kA.v[1] * w0A[t] + kA.v[2] * wpA[t] + kA.v[7] * w0B[t];
-          accB[t] = kB.v[0] * wmB[t] + kB.v[1] * w0B[t] + kB.v[2] * wpB[t] + kB.v[7] * w0A[t];
-#pragma unroll
-          for (int e = 0; e < KF; ++e) {
-            accA[t] += kA.v[3 + e] * gA[e][t];
-            accB[t] += kB.v[3 + e] * gB[e][t];
-          }
-        }
-        finish_row(i, q >= skip, accA, w0A, zA);
-        finish_row(j, q >= skip, accB, w0B, zB);
-        __builtin_amdgcn_sched_barrier(0);
-        if (q < R - 1) {
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            wmA[t] = w0A[t];
-            w0A[t] = wpA[t];
-            wpA[t] = nxA[t];
-            wmB[t] = w0B[t];
-            w0B[t] = wpB[t];
-            wpB[t] = nxB[t];
-            if constexpr (HASZ) {
-              zA[t] = znA[t];
-              zB[t] = znB[t];
-            }
-#pragma unroll
-            for (int e = 0; e < KF; ++e) {
-              gA[e][t] = gnA[e][t];
-              gB[e][t] = gnB[e][t];
-            }
-          }
-          kA = kA1;
-          kB = kB1;
-          cA1 = cA2;
-          cB1 = cB2;
-        }
-      }
-    } else {
-      // rows past the last whole block: guarded, one row at a time
-      const int64_t i0 = tail0 + (u - paired_units) * R, iend = min(n, i0 + R);
-      for (int64_t i = i0; i < iend; ++i) {
-        const RowCoef<T> kk = *(const RowCoef<T> *)(coef + 8 * i);
-        const RowCols ci = *(const RowCols *)(fcol + 4 * i);
-        const int64_t pi = (i % (2 * P)) < P ? i + P : i - P;
-        vec acc[NT], yi[NT], v[NT], zi[NT];
-        gather(i, yi);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = kk.v[1] * yi[t];
-        if (i > 0) {
-          gather(i - 1, v);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] += kk.v[0] * v[t];
-        }
-        if (i + 1 < n) {
-          gather(i + 1, v);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] += kk.v[2] * v[t];
-        }
-        if (pi < n) {
-          gather(pi, v);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] += kk.v[7] * v[t];
-        }
-#pragma unroll
-        for (int e = 0; e < KF; ++e) {
-          gather(ci.v[e], v);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] += kk.v[3 + e] * v[t];
-        }
-        if constexpr (HASZ) ldrow(Z, ldz, i, zi);
-        finish_row(i, true, acc, yi, zi);
-      }
-    }
-  }
-
-  if constexpr (SUMS) {
-    __shared__ double red[kWaves][64 * VEC * NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) red[wv][VEC * lane + 64 * VEC * t + v] = ss[t][v];
-    __syncthreads();
-    for (int c = threadIdx.x; c < w; c += kThreads) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kWaves; ++q) s += red[q][c];
-      partial[(int64_t)blockIdx.x * wtot + c0 + c] = s;
-    }
-  }
+#define ARR_VBLOCK blockIdx.x
+#define ARR_VGRID gridDim.x
+#include "spmm_paired_body.inc"
+#undef ARR_VBLOCK
+#undef ARR_VGRID
 }
 
 // Grid form: the operator of a 7-point stencil on a gx x gy x gz grid in
@@ -890,10 +478,63 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, int64_t P, const T *__r
   y[i] = s;
 }
 
+// Multi-request kernel: workgroup g runs tasks g, g + gridDim.x, ... of the
+// table; each task is one workgroup of the collected launch desc[task.x]
+// (FORM 0: plain form, X = overflow rows; FORM 1: paired form, X = far
+// slots), run by the same body as that launch's own kernel.
+template <typename T, int VEC, int NT, int FORM, int X, bool HASZ, bool SUMS>
+__global__ __launch_bounds__(kThreads) void k_filter_spmm_tasks(const SpmmTask *__restrict__ desc,
+                                                                const int2 *__restrict__ tasks, int ntasks) {
+  for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
+    const int2 tk = tasks[task];
+    const SpmmTask &d = desc[tk.x];
+    const unsigned vblock = (unsigned)tk.y, vgrid = (unsigned)d.groups;
+    int64_t n = d.n, ldy = d.ldy, ldz = d.ldz, ldo = d.ldo;
+    const T *coef = (const T *)d.coef;
+    const int32_t *fcol = d.fcol;
+    const T *Yin = (const T *)d.Yin, *Z = (const T *)d.Z;
+    T *Yout = (T *)d.Yout;
+    T alpha = (T)d.alpha, beta = (T)d.beta, gamma = (T)d.gamma;
+    double *partial = d.partial;
+    const double *colss = d.colss;
+    int w = d.w, wtot = d.wtot, c0 = d.c0;
+#define ARR_VBLOCK vblock
+#define ARR_VGRID vgrid
+    if constexpr (FORM == 0) {
+      constexpr bool OVF = X != 0;
+      const int64_t *orp = d.orp;
+      const int32_t *ocol = d.ocol;
+      const T *oval = (const T *)d.oval;
+#include "spmm_plain_body.inc"
+    } else {
+      constexpr int KF = X;
+      int64_t P = d.P;
+#include "spmm_paired_body.inc"
+    }
+#undef ARR_VBLOCK
+#undef ARR_VGRID
+    __syncthreads();  // the column-sum reduction's LDS is reused by the next task
+  }
+}
+
+template <typename T, int VEC, int NT, int FORM, int X, bool HASZ, bool SUMS>
+void launch_tasks(const SpmmTask *desc, const int2 *tasks, int ntasks, hipStream_t s) {
+  const int grid = std::min(ntasks, kMaxGroups);
+  hipLaunchKernelGGL((k_filter_spmm_tasks<T, VEC, NT, FORM, X, HASZ, SUMS>), dim3(grid), dim3(kThreads), 0, s, desc,
+                     tasks, ntasks);
+}
+
 template <typename T, int VEC, int NT, bool OVF, bool HASZ, bool SUMS>
 void launch_variant(const DevCSR<T> &A, Blk<const T> Yin, const T *zp, int64_t ldz, Blk<T> Yout, int w, int c0,
                     T alpha, T beta, T gamma, double *partial, int wtot, int groups, const double *colss,
                     hipStream_t s) {
+  if (SpmmBatch *b = spmm_batch()) {
+    b->add(SpmmTask{A.n, 0, Yin.ld, ldz, Yout.ld, A.coef, A.fcol, A.orp, A.ocol, A.oval, Yin.p + c0, zp,
+                    Yout.p + c0, (double)alpha, (double)beta, (double)gamma, partial, colss ? colss + c0 : nullptr, w,
+                    wtot, c0, groups},
+           &launch_tasks<T, VEC, NT, 0, OVF ? 1 : 0, HASZ, SUMS>);
+    return;
+  }
   hipLaunchKernelGGL((k_filter_spmm<T, VEC, NT, OVF, HASZ, SUMS>), dim3(groups), dim3(kThreads), 0, s, A.n, A.coef,
                      A.fcol, A.orp, A.ocol, A.oval, w, Yin.p + c0, Yin.ld, zp, ldz, Yout.p + c0, Yout.ld, alpha, beta,
                      gamma, partial, wtot, c0, colss ? colss + c0 : nullptr);
@@ -926,6 +567,13 @@ template <typename T, int VEC, int NT, int KF, bool HASZ, bool SUMS>
 void launch_paired_variant(const DevCSR<T> &A, Blk<const T> Yin, const T *zp, int64_t ldz, Blk<T> Yout, int w, int c0,
                            T alpha, T beta, T gamma, double *partial, int wtot, int groups, const double *colss,
                            hipStream_t s) {
+  if (SpmmBatch *b = spmm_batch()) {
+    b->add(SpmmTask{A.n, A.pair, Yin.ld, ldz, Yout.ld, A.coef, A.fcol, nullptr, nullptr, nullptr, Yin.p + c0, zp,
+                    Yout.p + c0, (double)alpha, (double)beta, (double)gamma, partial, colss ? colss + c0 : nullptr, w,
+                    wtot, c0, groups},
+           &launch_tasks<T, VEC, NT, 1, KF, HASZ, SUMS>);
+    return;
+  }
   hipLaunchKernelGGL((k_filter_spmm_paired<T, VEC, NT, KF, HASZ, SUMS>), dim3(groups), dim3(kThreads), 0, s, A.n,
                      A.pair, A.coef, A.fcol, w, Yin.p + c0, Yin.ld, zp, ldz, Yout.p + c0, Yout.ld, alpha, beta, gamma,
                      partial, wtot, c0, colss ? colss + c0 : nullptr);
@@ -1093,6 +741,78 @@ void SpmmTimer::reset() {
 SpmmTimer::~SpmmTimer() {
   for (Pending &p : pending) pool.push_back(p.a), pool.push_back(p.b);
   for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+SpmmBatch *&spmm_batch() {
+  static thread_local SpmmBatch *b = nullptr;
+  return b;
+}
+
+SpmmSink *&spmm_sink() {
+  static thread_local SpmmSink *k = nullptr;
+  return k;
+}
+
+SpmmBatch::SpmmBatch(size_t cap_bytes) : cap_(cap_bytes) {
+  dev_.alloc(cap_);
+  ARR_HIP(hipHostMalloc((void **)&host_, cap_ * kRing, hipHostMallocDefault));
+  for (hipEvent_t &e : staged_) ARR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
+SpmmBatch::~SpmmBatch() {
+  for (hipEvent_t e : staged_)
+    if (e) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
+  if (host_) (void)hipHostFree(host_);
+}
+
+void SpmmBatch::add(const SpmmTask &t, SpmmTaskLauncher launcher) {
+  tasks_.push_back(t);
+  launchers_.push_back(launcher);
+}
+
+int SpmmBatch::run(hipStream_t s) {
+  const int nl = (int)tasks_.size();
+  if (nl == 0) return 0;
+  // launches of one kernel variant together; inside a variant, workgroup b of
+  // every launch before workgroup b + 1 of any, so the persistent grid's
+  // static deal mixes the requests
+  std::vector<int> order(nl);
+  for (int i = 0; i < nl; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return std::less<const void *>()((const void *)launchers_[a], (const void *)launchers_[b]);
+  });
+  std::vector<int2> pairs;
+  std::vector<std::pair<SpmmTaskLauncher, std::pair<size_t, int>>> runs;  // launcher, (first pair, count)
+  for (int i = 0; i < nl;) {
+    int j = i;
+    int gmax = 0;
+    while (j < nl && launchers_[order[j]] == launchers_[order[i]]) gmax = std::max(gmax, tasks_[order[j++]].groups);
+    const size_t first = pairs.size();
+    for (int b = 0; b < gmax; ++b)
+      for (int q = i; q < j; ++q)
+        if (b < tasks_[order[q]].groups) pairs.push_back(int2{order[q], b});
+    runs.push_back({launchers_[order[i]], {first, (int)(pairs.size() - first)}});
+    i = j;
+  }
+  const size_t db = sizeof(SpmmTask) * nl, dpad = (db + 255) / 256 * 256, pb = sizeof(int2) * pairs.size();
+  ARR_REQUIRE(dpad + pb <= cap_, "multi-request SpMM: task table exceeds its buffer");
+  char *h = host_ + cap_ * slot_;
+  ARR_HIP(hipEventSynchronize(staged_[slot_]));  // the copy kRing runs back has left this buffer
+  std::memcpy(h, tasks_.data(), db);
+  std::memcpy(h + dpad, pairs.data(), pb);
+  ARR_HIP(hipMemcpyAsync(dev_.p, h, dpad + pb, hipMemcpyHostToDevice, s));
+  ARR_HIP(hipEventRecord(staged_[slot_], s));
+  slot_ = (slot_ + 1) % kRing;
+  const SpmmTask *ddesc = (const SpmmTask *)dev_.p;
+  const int2 *dpairs = (const int2 *)((const char *)dev_.p + dpad);
+  for (auto &r : runs) r.first(ddesc, dpairs + r.second.first, r.second.second, s);
+  ARR_HIP(hipGetLastError());
+  tasks_.clear();
+  launchers_.clear();
+  return nl;
 }
 
 int spmm_groups(int64_t n) {
@@ -1286,9 +1006,13 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   ARR_REQUIRE(!A.orp || (A.ocol && A.oval), "filter_spmm: overflow entries missing");
   ARR_REQUIRE(A.pair == 0 || (!A.orp && A.pair >= kPairRun && 2 * A.pair <= A.n && (A.kf == 1 || A.kf == 3)),
               "filter_spmm: invalid paired form");
+  if (SpmmSink *k = spmm_sink())
+    return k->run([&](hipStream_t bs) { return launch_filter_spmm<T>(A, Yin, Z, Yout, alpha, beta, gamma, partial,
+                                                                      bs, colss); },
+                  s);
   const int groups = spmm_groups(A.n);
   if (A.n == 0 || w == 0) return groups;
-  SpmmTimer *timer = spmm_timer();
+  SpmmTimer *timer = spmm_batch() ? nullptr : spmm_timer();  // collected launches are not timed
   if (A.gx) {
     ARR_REQUIRE(A.gx * A.gy * A.gz == A.n && A.pair == 0 && !A.orp, "filter_spmm: invalid grid form");
     // FP32 rows with 8-byte alignment: two columns per lane (512-byte segments)

@@ -618,3 +618,63 @@ def test_augmented_rr_matches_oracle(p, deflate):
     assert np.all(r_gpu <= r_or * (1 + 1e-6) + 1e-10)
     if deflate:
         assert np.abs(Qc.T @ Y).max() < 1e-10
+
+
+# Items of one multi-request batch: (matrix, row form, dtype, w, Z operand,
+# column sums). Paired and plain forms in both precisions, with and without
+# overflow rows, Z and column sums, widths with one and several column
+# chunks, and a grid-form item (its own launch) among them.
+BATCH = [
+    ("lap3d_20", arr.ROW_PAIRED, torch.float64, 240, False, False),
+    ("lap3d_20", arr.ROW_PAIRED, torch.float32, 240, False, True),
+    ("lap3d_23V", arr.ROW_PAIRED, torch.float64, 520, True, True),
+    ("powerlaw_4000", arr.ROW_AUTO, torch.float64, 65, True, False),
+    ("powerlaw_4000", arr.ROW_AUTO, torch.float32, 300, False, True),
+    ("lap3d_11V", arr.ROW_PLAIN, torch.float64, 1, False, True),
+    ("band_p40", arr.ROW_AUTO, torch.float32, 131, True, True),
+    ("grid_130x37_2d", arr.ROW_AUTO, torch.float64, 240, False, True),
+]
+
+
+@pytest.mark.parametrize("subset", [list(range(len(BATCH))), [0], [3, 4], [1, 2, 5, 6]])
+def test_filter_step_batch_equals_single_launches(subset):
+    """arr_filter_step_batch (the multi-request kernel: the items' workgroups
+    from one task table per kernel variant) gives each item bitwise the
+    output and column sums of its own arr_filter_step, and writes nothing
+    else (canaries around every output)."""
+    mats = {"lap3d_20": PAIRED["lap3d_20"], **MATS}
+    items, singles = [], []
+    for q, i in enumerate(subset):
+        mat, form, tdt, w, has_z, sums = BATCH[i]
+        A = mats[mat]()
+        Ad = arr.DeviceCSR(A, dtype=tdt, row_form=form)
+        rng = np.random.default_rng(100 + i)
+        Yd = dev(rng.standard_normal((A.n, w)), tdt)
+        Zd = dev(rng.standard_normal((A.n, w)), tdt) if has_z else None
+        al, be, ga = 0.75 + 0.01 * i, -0.5, (1.25 if has_z else 0.0)
+        # output block with a canary column on the right and canary rows around
+        big = torch.full((A.n + 2, w + 1), 7.0, dtype=tdt, device="cuda")
+        Od = big[1:A.n + 1, :w]
+        ss = torch.full((w,), -1.0, dtype=torch.float64, device="cuda") if sums else None
+        items.append((Ad, Yd, Zd, Od, al, be, ga, ss))
+        O1 = torch.zeros((A.n + 2, w + 1), dtype=tdt, device="cuda")[1:A.n + 1, :w]  # the same layout
+        s1 = torch.zeros(w, dtype=torch.float64, device="cuda") if sums else None
+        arr.arr_filter_step(Ad, Yd, Zd, O1, al, be, ga, colsumsq=s1)
+        singles.append((O1, s1, big))
+    arr.arr_filter_step_batch(items)
+    torch.cuda.synchronize()
+    for (Ad, Yd, Zd, Od, al, be, ga, ss), (O1, s1, big) in zip(items, singles):
+        assert torch.equal(Od, O1)
+        if ss is not None:
+            assert torch.equal(ss, s1)
+        assert bool((big[0] == 7.0).all()) and bool((big[-1] == 7.0).all()) and bool((big[:, -1] == 7.0).all())
+
+
+def test_filter_step_batch_rejects_bad_items():
+    A = W.laplacian_2d(30)
+    Ad = arr.DeviceCSR(A)
+    Y = torch.zeros((A.n, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(arr.ArrError):
+        arr.arr_filter_step_batch([])
+    with pytest.raises(arr.ArrError):
+        arr.arr_filter_step_batch([(Ad, Y, None, Y, 1.0, 0.0, 0.0, None)])  # Yout aliases Yin

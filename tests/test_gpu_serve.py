@@ -1,7 +1,7 @@
 """Serving loop on the GPU: continuous batching of many solves.
 
 Checks that (1) every request's result in the mix is bitwise identical to the
-same request solved alone, (2) the admitted requests never exceed the HBM
+same request solved alone, with and without the multi-request SpMM launches, (2) the admitted requests never exceed the HBM
 budget at any instant and are admitted in FIFO order, (3) requests run
 concurrently when budget and slots allow, (4) a request larger than the budget
 is refused with ARR_ENOMEM, (5) the served results are the right eigenpairs
@@ -41,7 +41,12 @@ def handle(A, k, w, tol, prec):
     return arr.arr_create(A, A.n, k, arr.SMALLEST, tol, o)
 
 
-def test_served_results_equal_alone_and_budget_respected():
+@pytest.mark.parametrize("batch_spmm", [True, False])
+def test_served_results_equal_alone_and_budget_respected(batch_spmm):
+    """With batch_spmm the requests' SpMMs run in multi-request launches
+    (the paired and plain forms of the 3D requests; the 2D requests' grid
+    form as launches of their own on the broker's stream); the results must
+    still equal the solves alone bit for bit."""
     reqs = make_requests()
     alone = []
     for (A, k, w, tol, prec) in reqs:
@@ -52,10 +57,15 @@ def test_served_results_equal_alone_and_budget_respected():
     hs = [handle(*r) for r in reqs]
     fps = [arr.arr_footprint(h) for h in hs]
     budget = int(2.2 * max(fps))  # forces queuing: at most two big ones at once
-    srv = arr.Server(hbm_budget_bytes=budget, max_slots=3)
+    srv = arr.Server(hbm_budget_bytes=budget, max_slots=3, batch_spmm=batch_spmm)
     tickets = [srv.submit(h) for h in hs]
     status = [srv.wait(t) for t in tickets]
     times = [srv.times(t) for t in tickets]
+    rounds, launches = srv.batch_stats()
+    if batch_spmm:  # the 3D requests' launches went through the multi-request kernel
+        assert rounds > 0 and launches > 0
+    else:
+        assert rounds == launches == 0
     for i, (A, k, w, tol, prec) in enumerate(reqs):
         ev, X, res = arr.arr_get_eigpairs(hs[i], k, A.n)
         assert status[i] == alone[i][0] == arr.ARR_OK
