@@ -217,7 +217,17 @@ def served_stream(n_requests=256, rate=20.0, seed=3, n_range=(1e4, 1e6), max_slo
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_spmm_traffic.md")
-SPMM_SOURCE = os.path.join(ROOT, "paper_1507_06078_amd", "csrc", "spmm.hip")
+# the SpMM kernels' source: the launcher file and the kernel bodies it includes
+SPMM_SOURCES = [os.path.join(ROOT, "paper_1507_06078_amd", "csrc", f)
+                for f in ("spmm.hip", "spmm_plain_body.inc", "spmm_paired_body.inc")]
+
+
+def spmm_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SPMM_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
@@ -227,7 +237,6 @@ def measured_traffic(kernel):
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the counter
     reads for a plain copy of known size), or None when the summary is missing
     or was taken on another version of the SpMM source."""
-    import hashlib
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
@@ -235,7 +244,7 @@ def measured_traffic(kernel):
     rec = next((json.loads(l.split(":", 1)[1]) for l in lines if l.startswith("traffic-json:")), None)
     if not rec:
         return None
-    sha = hashlib.sha256(open(SPMM_SOURCE, "rb").read()).hexdigest()
+    sha = spmm_source_sha256()
     if rec.get("spmm_source_sha256") != sha or kernel not in rec.get("kernels", {}):
         return None
     k = rec["kernels"][kernel]

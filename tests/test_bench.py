@@ -1,7 +1,6 @@
 """Host-side pieces of bench.py (no GPU): the SpMM kernel names it matches
 against rocprofv3 traces, the committed HBM-traffic record it reports, and
 the one-GPU refusal."""
-import hashlib
 import json
 import os
 import subprocess
@@ -31,7 +30,7 @@ def test_spmm_kernel_names(args, name):
 def test_traffic_record_matches_source_and_kernels():
     lines = open(bench.TRAFFIC_FILE).read().splitlines()
     rec = json.loads(next(l.split(":", 1)[1] for l in lines if l.startswith("traffic-json:")))
-    sha = hashlib.sha256(open(bench.SPMM_SOURCE, "rb").read()).hexdigest()
+    sha = bench.spmm_source_sha256()
     for kern, k in rec["kernels"].items():
         t = bench.measured_traffic(kern)
         if rec["spmm_source_sha256"] == sha:
