@@ -451,7 +451,12 @@ int arr_filter_step_batch(int32_t count, const arr_dev_csr_t *const *A, const in
         m32[i] = dev_split<float>(A[i]);
       if (colsumsq && colsumsq[i]) part[i].alloc(sizeof(double) * arr::spmm_groups(A[i]->n) * std::max<int64_t>(1, w[i]));
     }
-    arr::SpmmBatch batch;
+    // task table: at most one launch per 64 columns of an item, each with at
+    // most spmm_groups(n) workgroups
+    size_t cap = 4096;
+    for (int i = 0; i < count; ++i)
+      cap += ((size_t)w[i] / 64 + 1) * (sizeof(arr::SpmmTask) + 256 + sizeof(int2) * arr::spmm_groups(A[i]->n));
+    arr::SpmmBatch batch(cap);
     struct Install {
       arr::SpmmBatch *prev;
       explicit Install(arr::SpmmBatch *b) : prev(arr::spmm_batch()) { arr::spmm_batch() = b; }
