@@ -272,7 +272,7 @@ struct SpmmBatch {
   bool empty() const { return tasks_.empty(); }
 
  private:
-  static constexpr int kRing = 4;
+  static constexpr int kRing = 8;
   std::vector<SpmmTask> tasks_;
   std::vector<SpmmTaskLauncher> launchers_;
   DevBuf dev_;
@@ -285,14 +285,44 @@ SpmmBatch *&spmm_batch();
 
 // A receiver of the calling thread's SpMMs (the serving loop installs one on
 // each request's thread): launch_filter_spmm hands it the whole call as
-// `launch`, which performs the call's launches on the stream it is given,
-// and returns what run returns. run must leave the caller's stream s ordered
-// after those launches.
+// `launch` (its arguments copied; it performs the call's launches on the
+// stream it is given) and returns what the call would return. The sink must
+// leave the caller's stream s ordered after those launches: at once, or,
+// inside a chain (begin_chain .. end_chain, calls on s with nothing else
+// enqueued on s in between), by end_chain.
 struct SpmmSink {
   virtual ~SpmmSink() = default;
-  virtual int run(const std::function<int(hipStream_t)> &launch, hipStream_t s) = 0;
+  virtual void run(std::function<void(hipStream_t)> launch, hipStream_t s) = 0;
+  virtual void begin_chain() {}
+  virtual void end_chain(hipStream_t) {}
+  virtual void drop_chain() {}
 };
 SpmmSink *&spmm_sink();
+
+// Marks a run of filter SpMMs on s with nothing else enqueued on s in between
+// (one filter application) for the calling thread's sink, which may hand them
+// on together; close() ends the run. A chain left without close() (an
+// exception) is dropped.
+class SpmmChain {
+ public:
+  explicit SpmmChain(hipStream_t s) : s_(s), k_(spmm_sink()) {
+    if (k_) k_->begin_chain();
+  }
+  SpmmChain(const SpmmChain &) = delete;
+  SpmmChain &operator=(const SpmmChain &) = delete;
+  void close() {
+    SpmmSink *k = k_;
+    k_ = nullptr;
+    if (k) k->end_chain(s_);
+  }
+  ~SpmmChain() {
+    if (k_) k_->drop_chain();
+  }
+
+ private:
+  hipStream_t s_;
+  SpmmSink *k_;
+};
 // y = A x for one vector (Lanczos).
 template <typename T>
 void launch_spmv(const DevCSR<T> &A, const T *x, T *y, hipStream_t s);

@@ -26,40 +26,40 @@ struct Arena {
   size_t largest_free() const;
 };
 
-// The running requests' filter SpMMs, gathered and launched together: each
-// request's thread hands its launch_filter_spmm calls in (through a
-// per-request SpmmSink) and blocks only until they are enqueued; the broker
-// thread takes whatever the running requests have handed in, makes its
-// stream wait for each request's stream, runs all of it as one multi-request
-// launch per kernel variant (SpmmBatch) and makes each request's stream wait
-// for that launch. Nothing on the device waits for a later submission, so no
-// request can block another's progress.
+// The running requests' filter SpMMs, launched together. Each request's
+// thread hands in one filter application at a time (a chain of SpMM calls,
+// each depending on the one before) and blocks only until the chain is
+// enqueued. The broker thread runs rounds on its stream: each round takes
+// the next call of every chain in hand, as one multi-request launch per
+// kernel variant (SpmmBatch; grid-form calls as launches of their own), so
+// requests that filter at the same time advance in lockstep, and chains
+// handed in meanwhile join at the next round. The broker's stream waits for
+// a request's stream before its chain's first round; the request's stream
+// waits for the chain's last round. Nothing on the device waits for a later
+// submission, so no request can block another's progress.
 class SpmmBroker {
  public:
   explicit SpmmBroker(int device);
   ~SpmmBroker();
-  // For one request's thread: runs `launch` in the next multi-request launch
-  // and orders s after it (in_ev and done_ev are the request's own events).
-  int submit(const std::function<int(hipStream_t)> &launch, hipStream_t s, hipEvent_t in_ev, hipEvent_t done_ev);
+  // For one request's thread: enqueues `calls` (in order) and orders s after
+  // them (in_ev and done_ev are the request's own events).
+  void submit(std::vector<std::function<void(hipStream_t)>> &calls, hipStream_t s, hipEvent_t in_ev,
+              hipEvent_t done_ev);
   int64_t batches() const { return batches_.load(); }
   int64_t launches() const { return launches_.load(); }
 
  private:
   struct Item {
-    const std::function<int(hipStream_t)> *launch;
+    std::vector<std::function<void(hipStream_t)>> *calls;
+    size_t next = 0;
     hipEvent_t in_ev, done_ev;
-    int result = 0;
     bool enqueued = false;
     std::exception_ptr err;
   };
   void loop();
-  // rounds go to the streams in turn, so that consecutive rounds (of
-  // requests that were not ready together) can still overlap on the device
-  static constexpr int kStreams = 4;
   int device_;
-  hipStream_t bs_[kStreams] = {};
-  std::unique_ptr<SpmmBatch> batch_[kStreams];
-  int next_ = 0;
+  hipStream_t bs_ = nullptr;
+  std::unique_ptr<SpmmBatch> batch_;
   std::mutex mu_;
   std::condition_variable cv_;
   std::vector<Item *> pending_;

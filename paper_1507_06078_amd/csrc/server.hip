@@ -15,13 +15,14 @@
 //    requests execute concurrently; requests that arrive while others run join
 //    as soon as a slot and memory free up.
 //  * Multi-request SpMM (option batch_spmm, off by default): the running
-//    requests' filter SpMMs are gathered by a broker thread and run as one
-//    multi-request launch per kernel variant, whose workgroups take the
-//    requests' workgroups from a device task table (SpmmBroker). Each SpMM
-//    call then waits on the host until the broker has enqueued it; on a mix
-//    of small requests that handoff costs more than the merged launches save
-//    (measured 28.9 s against 20.4 s for a 64-request stream), so by default
-//    each request launches its own SpMMs and concurrent streams overlap them.
+//    requests' filter applications are handed to a broker thread, which runs
+//    them in lockstep rounds, each round one multi-request launch per kernel
+//    variant whose workgroups take the requests' workgroups from a device
+//    task table (SpmmBroker). All SpMMs then share one stream; on a 64-request
+//    mix the requests seldom filter at the same moment (most rounds hold one
+//    request), and the serial stream costs more than the merged launches save
+//    (25.2 s against 20.3 s), so by default each request launches its own
+//    SpMMs and the device overlaps the requests' streams.
 //  * Determinism: no kernel uses atomics in a reduction, and a request's
 //    SpMM workgroups run the same code on the same rows whether launched
 //    alone or in a multi-request launch, so a request's result does not
@@ -76,10 +77,9 @@ size_t Arena::largest_free() const {
 
 SpmmBroker::SpmmBroker(int device) : device_(device) {
   ARR_HIP(hipSetDevice(device_));
-  for (int i = 0; i < kStreams; ++i) {
-    ARR_HIP(hipStreamCreateWithFlags(&bs_[i], hipStreamNonBlocking));
-    batch_[i] = std::make_unique<SpmmBatch>((size_t)1 << 20);  // a round of 8 requests needs at most ~300 KB
-  }
+  ARR_HIP(hipStreamCreateWithFlags(&bs_, hipStreamNonBlocking));
+  // a round of 8 requests needs at most ~300 KB of task table
+  batch_ = std::make_unique<SpmmBatch>((size_t)1 << 20);
   th_ = std::thread([this] { loop(); });
 }
 
@@ -90,18 +90,17 @@ SpmmBroker::~SpmmBroker() {
     cv_.notify_all();
   }
   if (th_.joinable()) th_.join();
-  for (int i = 0; i < kStreams; ++i) {
-    (void)hipStreamSynchronize(bs_[i]);
-    batch_[i].reset();
-    (void)hipStreamDestroy(bs_[i]);
-  }
+  (void)hipStreamSynchronize(bs_);
+  batch_.reset();
+  (void)hipStreamDestroy(bs_);
 }
 
-int SpmmBroker::submit(const std::function<int(hipStream_t)> &launch, hipStream_t s, hipEvent_t in_ev,
-                       hipEvent_t done_ev) {
-  ARR_HIP(hipEventRecord(in_ev, s));  // the request's inputs are ready here
+void SpmmBroker::submit(std::vector<std::function<void(hipStream_t)>> &calls, hipStream_t s, hipEvent_t in_ev,
+                        hipEvent_t done_ev) {
+  if (calls.empty()) return;
+  ARR_HIP(hipEventRecord(in_ev, s));  // the chain's inputs are ready here
   Item it;
-  it.launch = &launch;
+  it.calls = &calls;
   it.in_ev = in_ev;
   it.done_ev = done_ev;
   {
@@ -113,51 +112,62 @@ int SpmmBroker::submit(const std::function<int(hipStream_t)> &launch, hipStream_
   }
   if (it.err) std::rethrow_exception(it.err);
   ARR_HIP(hipStreamWaitEvent(s, done_ev, 0));
-  return it.result;
 }
 
 void SpmmBroker::loop() {
   (void)hipSetDevice(device_);
+  std::vector<Item *> active;  // chains with calls left, in arrival order
   std::unique_lock<std::mutex> lk(mu_);
   while (true) {
-    cv_.wait(lk, [&] { return stop_ || !pending_.empty(); });
-    if (pending_.empty()) break;  // stopping, nothing left
-    std::vector<Item *> items;
-    items.swap(pending_);
+    if (active.empty()) cv_.wait(lk, [&] { return stop_ || !pending_.empty(); });
+    std::vector<Item *> fresh;
+    fresh.swap(pending_);
+    if (active.empty() && fresh.empty()) break;  // stopping, nothing left
     lk.unlock();
-    std::exception_ptr err;
-    hipStream_t bs = bs_[next_];
-    SpmmBatch &batch = *batch_[next_];
-    next_ = (next_ + 1) % kStreams;
+    std::vector<Item *> done;
     try {
-      for (Item *it : items) ARR_HIP(hipStreamWaitEvent(bs, it->in_ev, 0));
+      for (Item *it : fresh) ARR_HIP(hipStreamWaitEvent(bs_, it->in_ev, 0));
+      active.insert(active.end(), fresh.begin(), fresh.end());
+      // one round: the next call of every chain
       struct Install {
         SpmmBatch *prev;
         explicit Install(SpmmBatch *b) : prev(spmm_batch()) { spmm_batch() = b; }
         ~Install() { spmm_batch() = prev; }
       };
       {
-        Install in(&batch);
-        for (Item *it : items) {
+        Install in(batch_.get());
+        for (Item *it : active) {
           try {
-            it->result = (*it->launch)(bs);
+            (*it->calls)[it->next](bs_);
           } catch (...) {
-            it->err = std::current_exception();
+            if (!it->err) it->err = std::current_exception();
           }
+          ++it->next;
         }
       }
-      launches_ += batch.run(bs);
+      launches_ += batch_->run(bs_);
       ++batches_;
-      for (Item *it : items) ARR_HIP(hipEventRecord(it->done_ev, bs));
+      for (size_t q = 0; q < active.size();) {
+        Item *it = active[q];
+        if (it->next == it->calls->size()) {
+          ARR_HIP(hipEventRecord(it->done_ev, bs_));
+          done.push_back(it);
+          active.erase(active.begin() + (long)q);
+        } else {
+          ++q;
+        }
+      }
     } catch (...) {
-      err = std::current_exception();
+      // a failure outside one call's launches ends every chain in hand
+      for (Item *it : active) {
+        if (!it->err) it->err = std::current_exception();
+        done.push_back(it);
+      }
+      active.clear();
     }
     lk.lock();
-    for (Item *it : items) {
-      if (err && !it->err) it->err = err;
-      it->enqueued = true;
-    }
-    cv_.notify_all();
+    for (Item *it : done) it->enqueued = true;
+    if (!done.empty()) cv_.notify_all();
   }
 }
 
@@ -287,8 +297,25 @@ void Server::work(uint64_t id) {
   struct BrokerSink : SpmmSink {
     SpmmBroker *b = nullptr;
     hipEvent_t in_ev = nullptr, done_ev = nullptr;
-    int run(const std::function<int(hipStream_t)> &launch, hipStream_t st) override {
-      return b->submit(launch, st, in_ev, done_ev);
+    std::vector<std::function<void(hipStream_t)>> calls;
+    bool chain = false;
+    void run(std::function<void(hipStream_t)> launch, hipStream_t st) override {
+      calls.push_back(std::move(launch));
+      if (!chain) flush(st);
+    }
+    void begin_chain() override { chain = true; }
+    void end_chain(hipStream_t st) override {
+      chain = false;
+      flush(st);
+    }
+    void drop_chain() override {
+      chain = false;
+      calls.clear();
+    }
+    void flush(hipStream_t st) {
+      std::vector<std::function<void(hipStream_t)>> c;
+      c.swap(calls);
+      b->submit(c, st, in_ev, done_ev);
     }
     ~BrokerSink() {
       // done_ev is recorded after every use of in_ev on the broker's stream

@@ -995,6 +995,25 @@ void split_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
   if (out.ocol.empty()) out.orp.clear();
 }
 
+// Grid form: FP32 rows with 8-byte alignment take two columns per lane
+// (512-byte segments).
+template <typename T>
+bool grid_vec2(Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout) {
+  const int w = Yout.w;
+  return sizeof(T) == 4 && w % 2 == 0 && Yin.ld % 2 == 0 && Yout.ld % 2 == 0 && (!Z.p || Z.ld % 2 == 0) &&
+         aligned8(Yin.p) && aligned8(Yout.p) && (!Z.p || aligned8(Z.p));
+}
+
+// What launch_filter_spmm returns for these arguments (the rows of column
+// partial sums its launches write), without launching anything.
+template <typename T>
+int filter_spmm_groups(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout) {
+  const int groups = spmm_groups(A.n);
+  if (!A.gx || A.n == 0 || Yout.w == 0) return groups;
+  const GridPlan p = grid_plan(A.gx, A.gy, A.gz, Yout.w, grid_vec2<T>(Yin, Z, Yout) ? 2 : 1, groups);
+  return p.ntile * p.nseg;
+}
+
 template <typename T>
 int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk<T> Yout, double alpha,
                        double beta, double gamma, double *partial, hipStream_t s, const double *colss) {
@@ -1006,18 +1025,18 @@ int launch_filter_spmm(const DevCSR<T> &A, Blk<const T> Yin, Blk<const T> Z, Blk
   ARR_REQUIRE(!A.orp || (A.ocol && A.oval), "filter_spmm: overflow entries missing");
   ARR_REQUIRE(A.pair == 0 || (!A.orp && A.pair >= kPairRun && 2 * A.pair <= A.n && (A.kf == 1 || A.kf == 3)),
               "filter_spmm: invalid paired form");
-  if (SpmmSink *k = spmm_sink())
-    return k->run([&](hipStream_t bs) { return launch_filter_spmm<T>(A, Yin, Z, Yout, alpha, beta, gamma, partial,
-                                                                      bs, colss); },
-                  s);
+  if (SpmmSink *k = spmm_sink()) {
+    // A outlives the call (the solver's matrix); the rest is copied
+    k->run([=, &A](hipStream_t bs) { launch_filter_spmm<T>(A, Yin, Z, Yout, alpha, beta, gamma, partial, bs, colss); },
+           s);
+    return filter_spmm_groups<T>(A, Yin, Z, Yout);
+  }
   const int groups = spmm_groups(A.n);
   if (A.n == 0 || w == 0) return groups;
   SpmmTimer *timer = spmm_batch() ? nullptr : spmm_timer();  // collected launches are not timed
   if (A.gx) {
     ARR_REQUIRE(A.gx * A.gy * A.gz == A.n && A.pair == 0 && !A.orp, "filter_spmm: invalid grid form");
-    // FP32 rows with 8-byte alignment: two columns per lane (512-byte segments)
-    const bool v2 = sizeof(T) == 4 && w % 2 == 0 && Yin.ld % 2 == 0 && Yout.ld % 2 == 0 &&
-                    (!Z.p || Z.ld % 2 == 0) && aligned8(Yin.p) && aligned8(Yout.p) && (!Z.p || aligned8(Z.p));
+    const bool v2 = grid_vec2<T>(Yin, Z, Yout);
     const int vec = v2 ? 2 : 1;
     const GridPlan p = grid_plan(A.gx, A.gy, A.gz, w, vec, groups);
     // rows are addressed by 32-bit byte offsets within a plane of each block

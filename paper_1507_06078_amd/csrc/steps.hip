@@ -75,8 +75,10 @@ void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doubl
   // Y_1 = c0 Y_0 + c1 (A - shift I) Y_0 + g1 X with Y_0 = g0 X
   const double al1 = c1 * g[0], be1 = g[0] * (c0 - c1 * shift) + g[1];
   const double al = c1, be = c0 - c1 * shift;
+  SpmmChain chain(s);
   if (d == 1) {
     wk.groups = launch_filter_spmm<T>(A, Xc, none, Ya, al1, be1, 0.0, partial, s, in_colss);
+    chain.close();
     launch_copy<T>(A.n, w, X.p, X.ld, Ya.p, Ya.ld, s);
     return;
   }
@@ -88,6 +90,7 @@ void poly_apply_horner(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doubl
   }
   // last degree writes X in place (Z = X is read row-locally before the store)
   wk.groups = launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, Xc, X, al, be, g[d], partial, s, in_colss);
+  chain.close();
 }
 
 // The same polynomial as a product of linear factors over its real roots
@@ -107,9 +110,11 @@ void poly_apply_product(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doub
   const double c0 = (lo + hi) / (lo - hi), c1 = 2.0 / (hi - lo);
   const Blk<const T> none{nullptr, 0, 0};
   auto beta = [&](int i) { return c0 - c1 * shift - roots[i]; };
+  SpmmChain chain(s);
   if (d == 1) {
     wk.groups = launch_filter_spmm<T>(A, Blk<const T>{X.p, X.ld, w}, none, Ya, lead * c1, lead * beta(0), 0.0,
                                       partial, s, in_colss);
+    chain.close();
     launch_copy<T>(A.n, w, X.p, X.ld, Ya.p, Ya.ld, s);
     return;
   }
@@ -121,6 +126,7 @@ void poly_apply_product(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, doub
   }
   wk.groups =
       launch_filter_spmm<T>(A, Blk<const T>{cur.p, cur.ld, w}, none, X, c1, beta(d - 1), 0.0, partial, s, in_colss);
+  chain.close();
 }
 
 // The classic Chebyshev filter (eq. cheby-poly) in place of psi_d:
@@ -141,11 +147,13 @@ void poly_apply_chebyshev(const DevCSR<T> &A, Blk<T> X, Blk<T> Ya, Blk<T> Yb, do
   const Blk<T> buf[3] = {Blk<T>{X.p, X.ld, w}, Blk<T>{Ya.p, Ya.ld, w}, Blk<T>{Yb.p, Yb.ld, w}};
   auto in = [&](int j) { return Blk<const T>{buf[j % 3].p, buf[j % 3].ld, w}; };
   const Blk<const T> none{nullptr, 0, 0};
+  SpmmChain chain(s);
   int groups = launch_filter_spmm<T>(A, in(0), none, buf[1], c1, b1, 0.0, d == 1 ? partial : nullptr, s,
                                      d == 1 ? in_colss : nullptr);
   for (int j = 1; j < d; ++j)
     groups = launch_filter_spmm<T>(A, in(j), in(j - 1), buf[(j + 1) % 3], 2.0 * c1, 2.0 * b1, -1.0,
                                    j == d - 1 ? partial : nullptr, s, j == d - 1 ? in_colss : nullptr);
+  chain.close();
   if (d % 3 != 0) launch_copy<T>(A.n, w, X.p, X.ld, buf[d % 3].p, buf[d % 3].ld, s);
   if (want_norms) wk.groups = groups;
 }
