@@ -52,9 +52,7 @@ class arr_csr_t(ctypes.Structure):
 class arr_dev_csr_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
                 ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32),
-                ("row_form", ctypes.c_int32),
-                ("debug_nan_poly", ctypes.c_int32),
-                ("lean_memory", ctypes.c_int32)]
+                ("row_form", ctypes.c_int32)]
 
 
 class arr_options_t(ctypes.Structure):

@@ -175,11 +175,13 @@ def test_results_before_solve_are_refused():
 
 
 def test_stats_struct_matches_header():
-    """The binding's arr_stats_t and arr_options_t list every field of the
-    header's structs, in order."""
+    """The binding's structs list every field of the header's structs, in
+    order, with the header's sizes."""
     text = open(os.path.join(ROOT, "include", "arr.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    for cname, pyt in (("arr_stats_t", arr.arr_stats_t), ("arr_options_t", arr.arr_options_t)):
+    for cname, pyt in (("arr_stats_t", arr.arr_stats_t), ("arr_options_t", arr.arr_options_t),
+                       ("arr_csr_t", arr.arr_csr_t), ("arr_dev_csr_t", arr.arr_dev_csr_t),
+                       ("arr_server_opts_t", arr.arr_server_opts_t)):
         head = re.search(r"\}\s*" + cname + ";", text)
         body = text[:head.start()].rsplit("typedef struct {", 1)[1]
         names = []
@@ -187,9 +189,34 @@ def test_stats_struct_matches_header():
             decl = decl.strip()
             if not decl:
                 continue
-            parts = decl.split(None, 1)[1]
-            names += [x.strip().lstrip("*") for x in parts.split(",")]
+            first, *rest = decl.split(",")  # "const int64_t *rowptr" or "int32_t p0, p_max"
+            names += [x.split()[-1].lstrip("*") for x in [first] + rest]
         assert names == [f for f, _ in pyt._fields_], cname
+    # sizes and field offsets as a C compiler lays the header's structs out
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler for the layout check")
+    structs = (arr.arr_stats_t, arr.arr_options_t, arr.arr_csr_t, arr.arr_dev_csr_t, arr.arr_server_opts_t)
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "arr.h"', "int main(void) {"]
+    for pyt in structs:
+        c = pyt.__name__
+        lines.append(f'  printf("%zu\\n", sizeof({c}));')
+        for f, _ in pyt._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({c}, {f}));')
+    lines.append("  return 0;\n}")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        got = [int(x) for x in subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()]
+    want = []
+    for pyt in structs:
+        want.append(ctypes.sizeof(pyt))
+        want += [getattr(pyt, f).offset for f, _ in pyt._fields_]
+    assert got == want
 
 
 def test_lean_memory_footprint_and_checks():
