@@ -360,7 +360,8 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
         "solve": {key: last[key] for key in ("outer_iters", "arr_calls", "poly_calls", "final_p", "final_d",
                                              "n_locked", "fp32_outer", "spmm_degrees", "spmm_cols", "t_total",
                                              "t_setup", "t_filter", "t_arr", "t_dense", "a", "b", "arr_m2",
-                                             "maxres_explicit", "maxres_norm_a", "norm_est")},
+                                             "maxres_explicit", "maxres_norm_a", "norm_est",
+                                             "handover_contin")},
     }
 
 

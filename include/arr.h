@@ -173,6 +173,11 @@ typedef struct {
    * n x (p_max + 1) w blocks and the output block) for one extra SpMM of the
    * new Ritz vectors per outer iteration. Needs the MPM inner solver. */
   int32_t lean_memory;
+  /* ARR_MIXED: at the handover to the FP64 stage, when the FP32 stage's last
+   * maxres is at most this, b moves up to that iteration's mu_{k+q}, as a
+   * continuation step (eq. contin) moves it; tol_t is unchanged. Default
+   * 1e-2 (the default mixed_switch: every handover by the switch); 0 never. */
+  double mixed_contin;
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -238,6 +243,9 @@ typedef struct {
    * subspace ((p + 1) w' columns): the dense work of a solve scales with n
    * times this */
   double arr_m2;
+  /* ARR_MIXED: 1 if the handover to the FP64 stage took the continuation
+   * step of option mixed_contin */
+  int32_t handover_contin;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

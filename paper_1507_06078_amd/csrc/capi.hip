@@ -161,6 +161,7 @@ void arr_options_default(arr_options_t *o) {
   o->device = 0;
   o->seed = 2;
   o->mixed_switch = 1e-2;
+  o->mixed_contin = 1e-2;
   o->verbose = 0;
   o->timing = 0;
   o->keep_vectors = 1;

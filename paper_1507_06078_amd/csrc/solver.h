@@ -107,6 +107,7 @@ class Solver {
   double best_maxres_ = 0, maxresp_ = -1, best_mu_k_ = 0, best_mu_w_ = 0;
   int since_best_ = 0;
   std::vector<double> out_vals_, out_res_, out_rn_, fp32_vals_;
+  double fp32_mu_w_ = 0;  // mu_{k+q} of the last FP32-stage iteration
   int poly_count_ = 0;  // filter applications so far (for the debug_nan_poly hook)
 
   const FilterPoly &coeffs(int d);

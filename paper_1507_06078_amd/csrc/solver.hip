@@ -91,6 +91,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
   ARR_REQUIRE((int64_t)(o.p_max + 1) * w_ < n, "need (p_max + 1) * w < n (Algorithm 8)");
   ARR_REQUIRE(o.d0 >= 1 && o.d_max >= o.d0 && o.d_max <= 64, "need 1 <= d0 <= d_max <= 64");
   ARR_REQUIRE(o.maxit >= 1 && o.maxit1 >= 1 && o.maxit2 >= 1, "iteration limits must be >= 1");
+  ARR_REQUIRE(o.mixed_contin >= 0.0, "mixed_contin must be >= 0");
   ARR_REQUIRE(o.precision == ARR_FP64 || o.precision == ARR_MIXED, "unknown precision");
   ARR_REQUIRE(o.inner_solver == ARR_INNER_MPM || o.inner_solver == ARR_INNER_GN, "unknown inner solver");
   ARR_REQUIRE(o.poly_form == ARR_POLY_PRODUCT || o.poly_form == ARR_POLY_HORNER || o.poly_form == ARR_POLY_CHEBYSHEV,
@@ -622,6 +623,7 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       stats.fp32_outer += 1;
       stats.fp32_maxres = maxres;  // the raw FP32-stage figure, before the FP64 closing iterations
       fp32_vals_.assign(mu.begin(), mu.begin() + k);
+      fp32_mu_w_ = mu[w - 1];
       if (which_ == ARR_SMALLEST_ALGEBRAIC)
         for (double &v : fp32_vals_) v = -v;
     }
@@ -796,6 +798,16 @@ int Solver::solve() {
       // the FP64 stage re-derives its stagnation reference
       best_maxres_ = std::numeric_limits<double>::infinity();
       since_best_ = 0;
+      // continuation step at the handover: b moves up to the FP32 stage's
+      // mu_{k+q}, as eq. contin moves it (tol_t unchanged). The FP32 stage
+      // takes no continuation step itself (see outer()).
+      if (stats.fp32_maxres <= o_.mixed_contin) {
+        if (o_.verbose)
+          std::fprintf(stderr, "[arr] handover to FP64 at maxres %.3e: b %.6e -> %.6e\n", stats.fp32_maxres, b_,
+                       fp32_mu_w_);
+        b_ = fp32_mu_w_;
+        stats.handover_contin = 1;
+      }
       status = outer<double>(B64_, A64_, false);
     }
   } else {

@@ -350,6 +350,30 @@ def test_fp32_stage_values():
     h.close()
 
 
+def test_mixed_handover_continuation():
+    """ARR_MIXED hands over to the FP64 stage with one continuation step (b
+    up to the FP32 stage's mu_{k+q}) when the FP32 stage's maxres is at most
+    mixed_contin (default 1e-2, the handover threshold); with mixed_contin = 0
+    b stays. Both reach the dense solver's eigenvalues and residuals <= tol."""
+    A = W.laplacian_3d(16, potential_seed=4)
+    k, w = 40, 48
+    lam = np.linalg.eigvalsh(A.to_scipy().toarray())[:k]
+    flags = {}
+    for contin in (1e-2, 0.0):
+        status, ev, X, res, st = solve(A, k, "SA", 1e-10, w=w, precision=arr.MIXED, mixed_contin=contin)
+        assert status == arr.ARR_OK, st
+        assert np.abs(ev - lam).max() <= 1e-10 * max(1.0, np.abs(lam).max())
+        check_pairs(A, ev, X, 1e-10)
+        flags[contin] = (st["handover_contin"], st["fp32_maxres"])
+    assert flags[1e-2][0] == (1 if flags[1e-2][1] <= 1e-2 else 0)
+    assert flags[0.0][0] == 0
+    o = arr.arr_options_default()
+    assert o.mixed_contin == 1e-2
+    o.mixed_contin = -1.0
+    with pytest.raises(arr.ArrError):
+        arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-10, o)
+
+
 @pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
 def test_nonfinite_guard_recovers_once(precision):
     """A NaN written into the iterate after the third filter application (the
