@@ -178,6 +178,13 @@ struct DevBuf {
     pooled = false;
   }
   template <typename T> T *as() const { return static_cast<T *>(p); }
+  // A view of `b` bytes of memory owned elsewhere (never freed here).
+  void view(void *q, size_t b) {
+    release();
+    p = q;
+    bytes = b;
+    pooled = true;
+  }
 };
 
 // ---- launchers (spmm.hip) ----------------------------------------------------

@@ -157,19 +157,28 @@ size_t Solver::device_plan(bool allocate) {
   }
   // lean: no A U block (chunks of ldt columns instead) and no output block
   const int64_t ldt64 = std::min<int64_t>(ldz_, 256), ldt32 = std::min<int64_t>(ldz_, 512);
-  for (DevBuf *b : {&B64_.Zb, &B64_.Ub}) take(*b, sizeof(double) * n * ldz_);
+  // The FP32 stage's blocks live inside FP64 blocks that the FP32 stage does
+  // not use: its Z and U in the two halves of the FP64 U block (256 bytes of
+  // slack keep the second half 256-byte aligned), its W (or chunk buffer) in
+  // the FP64 W (chunk) block. It locks nothing, so it has no Q blocks. The
+  // handover converts its Z into the FP64 Z block, which it never touched.
+  const size_t half32 = (sizeof(float) * n * ldz_ + 255) / 256 * 256;
+  take(B64_.Zb, sizeof(double) * n * ldz_);
+  take(B64_.Ub, sizeof(double) * n * ldz_ + (mixed ? 256 : 0));
   if (lean_)
     take(B64_.Tb, sizeof(double) * n * ldt64);
   else
     take(B64_.Wb, sizeof(double) * n * ldz_);
   for (DevBuf *b : {&B64_.Qb, &B64_.Q2b}) take(*b, sizeof(double) * n * ldq_);
-  if (mixed) {
-    for (DevBuf *b : {&B32_.Zb, &B32_.Ub}) take(*b, sizeof(float) * n * ldz_);
+  if (mixed && allocate) {
+    B32_.Zb.view(B64_.Ub.p, sizeof(float) * n * ldz_);
+    B32_.Ub.view(B64_.Ub.as<char>() + half32, sizeof(float) * n * ldz_);
     if (lean_)
-      take(B32_.Tb, sizeof(float) * n * ldt32);
+      B32_.Tb.view(B64_.Tb.p, sizeof(float) * n * ldt32);
     else
-      take(B32_.Wb, sizeof(float) * n * ldz_);
-    for (DevBuf *b : {&B32_.Qb, &B32_.Q2b}) take(*b, sizeof(float) * n * ldq_);
+      B32_.Wb.view(B64_.Wb.p, sizeof(float) * n * ldz_);
+    B32_.Qb.release();
+    B32_.Q2b.release();
   }
   take(mu_, sizeof(double) * ldz_);
   take(desc_, (sizeof(void *) + sizeof(int64_t) + sizeof(int32_t)) * (size_t)ldz_ + 64);
@@ -679,7 +688,9 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       b_ = mu[w - 1];
     }
     // ---- deflation (eq. defl): Qc re-collected from the merged set ----
-    const double tol_d = std::max(1e-14, tol_t_ * tol_t_);
+    // the FP32 stage locks nothing (its residuals do not reach tol_t^2, and it
+    // keeps no Q blocks); the FP64 stage locks at eq. defl's threshold
+    const double tol_d = fp32_stage ? -1.0 : std::max(1e-14, tol_t_ * tol_t_);
     std::vector<const T *> qs, xs;
     std::vector<int64_t> ql, xl;
     std::vector<int32_t> qcol, xcol;
@@ -792,9 +803,8 @@ int Solver::solve() {
     status = outer<float>(B32_, A32_, true);
     if (status == -100) {
       // hand the iterate and the locked pairs to the FP64 stage
+      ARR_REQUIRE(nc_ == 0, "FP32 stage ended with locked pairs");
       launch_convert<double, float>(n_, wp_, B64_.Zb.as<double>(), B64_.ldz, B32_.Zb.as<float>(), B32_.ldz, s_);
-      if (nc_)
-        launch_convert<double, float>(n_, nc_, B64_.Qb.as<double>(), B64_.ldq, B32_.Qb.as<float>(), B32_.ldq, s_);
       // the FP64 stage re-derives its stagnation reference
       best_maxres_ = std::numeric_limits<double>::infinity();
       since_best_ = 0;
