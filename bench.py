@@ -372,7 +372,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
                                              "n_locked", "fp32_outer", "spmm_degrees", "spmm_cols", "t_total",
                                              "t_setup", "t_filter", "t_arr", "t_dense", "a", "b", "arr_m2",
                                              "maxres_explicit", "maxres_norm_a", "norm_est",
-                                             "handover_contin")},
+                                             "handover_contin", "fp32_collapsed")},
     }
 
 

@@ -178,6 +178,9 @@ typedef struct {
    * continuation step (eq. contin) moves it; tol_t is unchanged. Default
    * 1e-2 (the default mixed_switch: every handover by the switch); 0 never. */
   double mixed_contin;
+  /* Test hook of the FP32 stage's collapse check, 0 (off) by default: 1
+   * treats the first FP32-stage iteration as collapsed. */
+  int32_t debug_fp32_collapse;
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -246,6 +249,11 @@ typedef struct {
   /* ARR_MIXED: 1 if the handover to the FP64 stage took the continuation
    * step of option mixed_contin */
   int32_t handover_contin;
+  /* ARR_MIXED: 1 if the FP32 stage's Ritz values collapsed (all w within
+   * 1e-6 (b - a) of each other: the block driven onto one isolated dominant
+   * eigenvector below FP32 resolution) and the FP64 stage restarted from the
+   * starting block */
+  int32_t fp32_collapsed;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

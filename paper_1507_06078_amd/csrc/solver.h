@@ -108,6 +108,7 @@ class Solver {
   int since_best_ = 0;
   std::vector<double> out_vals_, out_res_, out_rn_, fp32_vals_;
   double fp32_mu_w_ = 0;  // mu_{k+q} of the last FP32-stage iteration
+  bool fp32_collapsed_ = false;  // its Ritz values collapsed (see outer())
   int poly_count_ = 0;  // filter applications so far (for the debug_nan_poly hook)
 
   const FilterPoly &coeffs(int d);

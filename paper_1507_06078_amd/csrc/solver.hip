@@ -633,6 +633,12 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       stats.fp32_maxres = maxres;  // the raw FP32-stage figure, before the FP64 closing iterations
       fp32_vals_.assign(mu.begin(), mu.begin() + k);
       fp32_mu_w_ = mu[w - 1];
+      // A collapsed block: the w Ritz values within 1e-6 (b - a) of each other.
+      // The filter can drive every column onto one isolated dominant
+      // eigenvector below FP32 resolution (the FP32 stage cannot lock it
+      // out), after which the FP32 pairs (w copies of one vector, with tiny
+      // residuals) say nothing about the rest of the wanted set.
+      fp32_collapsed_ = !(mu[0] - mu[w - 1] > 1e-6 * (b_ - a_)) || (o_.debug_fp32_collapse && j_ == 1);
       if (which_ == ARR_SMALLEST_ALGEBRAIC)
         for (double &v : fp32_vals_) v = -v;
     }
@@ -745,7 +751,8 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
       } else {
         ++fp32_since_best;
       }
-      if (maxres <= o_.mixed_switch || fp32_since_best >= 2 || fp32_iters >= fp32_limit) return -100;
+      if (fp32_collapsed_ || maxres <= o_.mixed_switch || fp32_since_best >= 2 || fp32_iters >= fp32_limit)
+        return -100;
     }
   }
   return ARR_NOT_CONVERGED;
@@ -756,6 +763,7 @@ int Solver::solve() {
   stats = arr_stats_t{};
   solved = false;
   fp32_vals_.clear();
+  fp32_collapsed_ = false;
   ARR_HIP(hipSetDevice(o_.device));
   ensure_device();
   host_results_ = false;
@@ -800,9 +808,26 @@ int Solver::solve() {
   int status;
   if (o_.precision == ARR_MIXED) {
     launch_convert<float, double>(n_, w_, B32_.Zb.as<float>(), B32_.ldz, B64_.Zb.as<double>(), B64_.ldz, s_);
+    const double b0 = b_, tol_t0 = tol_t_;
     status = outer<float>(B32_, A32_, true);
-    if (status == -100) {
-      // hand the iterate and the locked pairs to the FP64 stage
+    if (status == -100 && fp32_collapsed_) {
+      // the FP32 stage's block collapsed: Algorithm 8 starts again in FP64
+      // from the starting block, which the FP64 Z block still holds
+      if (o_.verbose)
+        std::fprintf(stderr, "[arr] FP32 stage collapsed (Ritz values within 1e-6 (b - a)): FP64 restarts from the "
+                             "starting block\n");
+      stats.fp32_collapsed = 1;
+      d_ = o_.d0;
+      p_ = o_.p0;
+      wp_ = w_;
+      b_ = b0;
+      tol_t_ = tol_t0;
+      maxresp_ = -1.0;
+      best_maxres_ = std::numeric_limits<double>::infinity();
+      since_best_ = 0;
+      status = outer<double>(B64_, A64_, false);
+    } else if (status == -100) {
+      // hand the iterate to the FP64 stage
       ARR_REQUIRE(nc_ == 0, "FP32 stage ended with locked pairs");
       launch_convert<double, float>(n_, wp_, B64_.Zb.as<double>(), B64_.ldz, B32_.Zb.as<float>(), B32_.ldz, s_);
       // the FP64 stage re-derives its stagnation reference

@@ -374,6 +374,24 @@ def test_mixed_handover_continuation():
         arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-10, o)
 
 
+def test_mixed_fp32_collapse_restarts_in_fp64():
+    """A collapsed FP32 stage (forced by the debug_fp32_collapse hook) hands
+    over without its iterate: Algorithm 8 starts again in FP64 from the
+    starting block and reaches the closed-form spectrum; an ordinary mixed
+    solve reports no collapse."""
+    A, k, which, w, tol = W.workload("lap2d_40")
+    X0 = W.gaussian_block(A.n, w, seed=2)
+    exact = W.laplacian_2d_eigenvalues(40)[:k]
+    for hook in (1, 0):
+        status, ev, X, res, st = solve(A, k, which, tol, w=w, precision=arr.MIXED, X0=X0, debug_fp32_collapse=hook)
+        assert status == arr.ARR_OK, st
+        assert st["fp32_collapsed"] == hook
+        if hook:
+            assert st["fp32_outer"] == 1 and st["handover_contin"] == 0
+        assert np.all(np.abs(ev - exact) <= 1e-10 * np.maximum(1, np.abs(exact)))
+        check_pairs(A, ev, X, tol)
+
+
 @pytest.mark.parametrize("precision", [arr.FP64, arr.MIXED])
 def test_nonfinite_guard_recovers_once(precision):
     """A NaN written into the iterate after the third filter application (the
