@@ -55,9 +55,9 @@ def test_interpolant_matches_barycentric_lagrange(d):
     (3, 0.468, 1.344, -0.028), (5, 0.203, 2.080, -0.036),
     (8, 0.169, 4.96, 0.060), (15, 0.080, 55.7, -0.272)])
 def test_interpolant_profile(d, maxabs, at11, atm105):
-    """Low profile on [-1, 0.8] (Sec. 5: magnitude 'less than or around 0.2
-    except near 1'); values computed independently with barycentric
-    interpolation, 3 significant digits."""
+    """Low profile on [-1, 0.8] (Sec. 5: away from the right end the
+    interpolant stays at about 0.2 in magnitude or below); values computed
+    independently with barycentric interpolation, 3 significant digits."""
     t = O.interpolation_nodes(d)
     bary = BarycentricInterpolator(t, O.target_function(t, d))
     g = O.interpolant_coefficients(d)
