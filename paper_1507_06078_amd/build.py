@@ -16,8 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libarr.so")
-SOURCES = ["spmm.hip", "gemm.hip", "dense.hip", "misc.hip", "steps.hip", "solver.hip", "server.hip", "capi.hip",
-           "coeffs.cpp"]
+SOURCES = ["spmm.hip", "batch.hip", "gemm.hip", "dense.hip", "misc.hip", "steps.hip", "solver.hip", "server.hip",
+           "capi.hip", "coeffs.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
