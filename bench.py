@@ -297,6 +297,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
     o.row_form = {"auto": arr.ROW_AUTO, "plain": arr.ROW_PLAIN, "paired": arr.ROW_PAIRED,
                   "grid": arr.ROW_GRID}[args.row_form]
     o.lean_memory = 1 if args.lean else 0
+    o.early_contin = args.early_contin
     if args.p_max is not None:
         o.p_max = args.p_max
         o.p0 = min(o.p0, args.p_max)
@@ -372,7 +373,7 @@ def solve_run(A, k, w, tol, precision, args, label, which="SA"):
                                              "n_locked", "fp32_outer", "spmm_degrees", "spmm_cols", "t_total",
                                              "t_setup", "t_filter", "t_arr", "t_dense", "a", "b", "arr_m2",
                                              "maxres_explicit", "maxres_norm_a", "norm_est",
-                                             "handover_contin", "fp32_collapsed")},
+                                             "handover_contin", "fp32_collapsed", "early_contin")},
     }
 
 
@@ -424,6 +425,8 @@ def main():
                          "the 4e6-row SBM normalized Laplacian (k=1000, block 1200; needs --lean --p-max 1 "
                          "to fit 288 GB in FP64)")
     ap.add_argument("--lean", action="store_true", help="lean-memory mode (no A U block)")
+    ap.add_argument("--early-contin", type=float, default=0.0,
+                    help="FP64 path: move b at the first maxres <= this (option early_contin; 0: Sec. 6 exactly)")
     ap.add_argument("--p-max", type=int, default=None, help="largest number of augmentation blocks (default 3)")
     ap.add_argument("--serve", action="store_true", help="run the served request stream instead")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -495,7 +498,7 @@ def main():
         "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": workload, "precision": head_prec, "inner_solver": args.inner, "filter": args.poly,
-                   "row_form": args.row_form, "lean_memory": bool(args.lean),
+                   "row_form": args.row_form, "lean_memory": bool(args.lean), "early_contin": args.early_contin,
                    "p_max": args.p_max if args.p_max is not None else 3},
         "converged": head["converged"],
         "max_res": head["max_res"],

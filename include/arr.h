@@ -181,6 +181,12 @@ typedef struct {
   /* Test hook of the FP32 stage's collapse check, 0 (off) by default: 1
    * treats the first FP32-stage iteration as collapsed. */
   int32_t debug_fp32_collapse;
+  /* ARR_FP64: the first time maxres is at most this, b moves up to that
+   * iteration's mu_{k+q} (the b update of eq. contin, tol_t unchanged),
+   * before Sec. 6's continuation would move it at maxres <= tol_t. 0
+   * (default): Sec. 6 exactly. The mixed path takes its step at the handover
+   * instead (mixed_contin). */
+  double early_contin;
 } arr_options_t;
 
 /* Counters and timings of the last solve. */
@@ -254,6 +260,8 @@ typedef struct {
    * eigenvector below FP32 resolution) and the FP64 stage restarted from the
    * starting block */
   int32_t fp32_collapsed;
+  /* the outer iteration that took option early_contin's step, 0 if none */
+  int32_t early_contin;
 } arr_stats_t;
 
 typedef struct arr_solver *arr_handle_t;

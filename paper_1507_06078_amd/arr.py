@@ -69,7 +69,8 @@ class arr_options_t(ctypes.Structure):
                 ("debug_nan_poly", ctypes.c_int32),
                 ("lean_memory", ctypes.c_int32),
                 ("mixed_contin", ctypes.c_double),
-                ("debug_fp32_collapse", ctypes.c_int32)]
+                ("debug_fp32_collapse", ctypes.c_int32),
+                ("early_contin", ctypes.c_double)]
 
 
 class arr_server_opts_t(ctypes.Structure):
@@ -99,7 +100,8 @@ class arr_stats_t(ctypes.Structure):
                 ("fp32_maxres", ctypes.c_double), ("spmm_flags", ctypes.c_int32), ("spmm32_flags", ctypes.c_int32),
                 ("nan_retries", ctypes.c_int32), ("maxres_explicit", ctypes.c_double),
                 ("maxres_norm_a", ctypes.c_double), ("arr_m2", ctypes.c_double),
-                ("handover_contin", ctypes.c_int32), ("fp32_collapsed", ctypes.c_int32)]
+                ("handover_contin", ctypes.c_int32), ("fp32_collapsed", ctypes.c_int32),
+                ("early_contin", ctypes.c_int32)]
 
 
 EXPORTS = ["arr_options_default", "arr_create", "arr_create_ex", "arr_set_initial_block", "arr_solve",

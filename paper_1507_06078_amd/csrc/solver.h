@@ -109,6 +109,7 @@ class Solver {
   std::vector<double> out_vals_, out_res_, out_rn_, fp32_vals_;
   double fp32_mu_w_ = 0;  // mu_{k+q} of the last FP32-stage iteration
   bool fp32_collapsed_ = false;  // its Ritz values collapsed (see outer())
+  bool early_contin_done_ = false;  // option early_contin's step taken (or not wanted)
   int poly_count_ = 0;  // filter applications so far (for the debug_nan_poly hook)
 
   const FilterPoly &coeffs(int d);

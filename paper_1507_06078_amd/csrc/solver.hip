@@ -92,6 +92,7 @@ Solver::Solver(const arr_csr_t *csr, int64_t n, int k, int which, double tol, co
   ARR_REQUIRE(o.d0 >= 1 && o.d_max >= o.d0 && o.d_max <= 64, "need 1 <= d0 <= d_max <= 64");
   ARR_REQUIRE(o.maxit >= 1 && o.maxit1 >= 1 && o.maxit2 >= 1, "iteration limits must be >= 1");
   ARR_REQUIRE(o.mixed_contin >= 0.0, "mixed_contin must be >= 0");
+  ARR_REQUIRE(o.early_contin >= 0.0, "early_contin must be >= 0");
   ARR_REQUIRE(o.precision == ARR_FP64 || o.precision == ARR_MIXED, "unknown precision");
   ARR_REQUIRE(o.inner_solver == ARR_INNER_MPM || o.inner_solver == ARR_INNER_GN, "unknown inner solver");
   ARR_REQUIRE(o.poly_form == ARR_POLY_PRODUCT || o.poly_form == ARR_POLY_HORNER || o.poly_form == ARR_POLY_CHEBYSHEV,
@@ -692,6 +693,12 @@ int Solver::outer(Blocks<T> &B, const DevCSR<T> &A, bool fp32_stage) {
     if (!fp32_stage && maxres <= tol_t_) {
       tol_t_ = std::max(1e-2 * tol_t_, tol_);
       b_ = mu[w - 1];
+      early_contin_done_ = true;
+    } else if (!fp32_stage && !early_contin_done_ && maxres <= o_.early_contin) {
+      // option early_contin: one earlier step of b only (tol_t unchanged)
+      b_ = mu[w - 1];
+      early_contin_done_ = true;
+      stats.early_contin = j_;
     }
     // ---- deflation (eq. defl): Qc re-collected from the merged set ----
     // the FP32 stage locks nothing (its residuals do not reach tol_t^2, and it
@@ -764,6 +771,8 @@ int Solver::solve() {
   solved = false;
   fp32_vals_.clear();
   fp32_collapsed_ = false;
+  // the mixed path's handover takes its own step; FP64 takes at most one
+  early_contin_done_ = o_.precision == ARR_MIXED;
   ARR_HIP(hipSetDevice(o_.device));
   ensure_device();
   host_results_ = false;

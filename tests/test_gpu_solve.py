@@ -374,6 +374,23 @@ def test_mixed_handover_continuation():
         arr.arr_create(A, A.n, k, arr.SMALLEST, 1e-10, o)
 
 
+def test_fp64_early_continuation_option():
+    """Option early_contin: the FP64 path moves b once, at the first maxres
+    <= early_contin, before Sec. 6's continuation would (with 10 that is the
+    first outer iteration); the solve reaches the dense solver's eigenvalues.
+    By default (0) it follows Sec. 6 exactly."""
+    A = W.laplacian_3d(16, potential_seed=4)
+    k, w = 40, 48
+    lam = np.linalg.eigvalsh(A.to_scipy().toarray())[:k]
+    for ec in (10.0, 0.0):
+        status, ev, X, res, st = solve(A, k, "SA", 1e-10, w=w, early_contin=ec)
+        assert status == arr.ARR_OK, st
+        assert np.abs(ev - lam).max() <= 1e-10 * max(1.0, np.abs(lam).max())
+        check_pairs(A, ev, X, 1e-10)
+        assert st["early_contin"] == (1 if ec else 0)
+    assert arr.arr_options_default().early_contin == 0.0
+
+
 def test_mixed_fp32_collapse_restarts_in_fp64():
     """A collapsed FP32 stage (forced by the debug_fp32_collapse hook) hands
     over without its iterate: Algorithm 8 starts again in FP64 from the
